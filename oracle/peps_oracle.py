@@ -1,0 +1,408 @@
+"""FP64 CPU oracle for the PEPS-VMC hot path (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  The product path (the HIP library and its Python binding) never
+calls it, and it shares no code with that path.
+
+What it computes, per spin configuration S (paper Sec. II-A):
+  * W(S), the single-layer contraction of Eq. (1) at fixed S, approximated by
+    the row-by-row boundary-MPS contraction with bond truncation Dc of Fig. 1(c);
+  * the local energy E(S) of Eq. (4) for the J1-J2 Hamiltonian of Sec. III-A;
+  * the log-derivatives Delta = B/W of Eqs. (6)-(7).
+Everything is IEEE float64.  numpy's QR and SVD (LAPACK) are used as library
+steps; contractions are written as einsum calls, one per tensor pair.
+
+Readings of points the paper leaves open (each one is listed in the design notes):
+  * boundary legs of the open lattice are restricted to index 0; other entries of
+    the uniform D^4 storage are dead parameters (zero derivative);
+  * truncation = canonical SVD truncation: a left-to-right QR sweep to
+    left-canonical form, then a right-to-left SVD sweep keeping
+    t = min(Dc, rows, cols) singular vectors (zero ones included), then the
+    norm is pulled out of the first site and kept as a log;
+  * the bottom-up sweep uses the same column orientation as the top-down one;
+  * the reported amplitude is the top-down one (final overlap with the last row);
+  * spin-flip ratios use the sandwich that holds both sites: the single-row
+    sandwich <U_i|row i|L_i> for horizontal bonds, the two-row sandwich
+    <U_i|rows i,i+1|L_{i+1}> for vertical and diagonal bonds, each divided by the
+    same sandwich at the unflipped S;
+  * Delta_m is the frozen-environment derivative of ln|W_i| (row i holds site m);
+  * s = 0 is spin up (S^z = +1/2), sigma = 1 - 2s; S_i.S_j = sigma_i sigma_j / 4
+    plus 1/2 for the exchange of an anti-parallel pair (no sign rotation).
+
+Parity pins live in the test suite: dense transfer-matrix contraction (exact
+regime), dense sequential Schmidt projection (truncated regime), brute force
+over all 2^16 configurations of a 4x4 lattice, closed forms of product states,
+finite differences and invariants.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Per-sample status flags (same meaning as the library's).
+FLAG_OK, FLAG_BAD_CONFIG, FLAG_ZERO_AMPLITUDE, FLAG_NONFINITE = 0, 1, 2, 3
+
+
+# --------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------
+def leg_dims(lat, i, j):
+    """(Dl, Du, Dr, Dd) of site (i, j): outward legs of the open lattice have dim 1."""
+    D = lat.D
+    return (1 if j == 0 else D, 1 if i == 0 else D,
+            1 if j == lat.Lx - 1 else D, 1 if i == lat.Ly - 1 else D)
+
+
+def site_tensor(A, lat, i, j, s):
+    """T = A_m^{s} of Eq. (1) as a rank-4 tensor [l, u, r, d] (m = i*Lx + j)."""
+    Dl, Du, Dr, Dd = leg_dims(lat, i, j)
+    return A[i * lat.Lx + j, s, :Dl, :Du, :Dr, :Dd]
+
+
+def row_tensors(A, lat, S, i):
+    return [site_tensor(A, lat, i, j, int(S[i * lat.Lx + j])) for j in range(lat.Lx)]
+
+
+def j1_bonds(lat):
+    """Nearest-neighbour pairs <i,j> of the open lattice (Sec. III-A): (site, site, kind)."""
+    out = []
+    for i in range(lat.Ly):
+        for j in range(lat.Lx):
+            m = i * lat.Lx + j
+            if j + 1 < lat.Lx:
+                out.append((m, m + 1, "h"))
+            if i + 1 < lat.Ly:
+                out.append((m, m + lat.Lx, "v"))
+    return out
+
+
+def j2_bonds(lat):
+    """Next-nearest-neighbour pairs <<i,j>>: both diagonals of every plaquette."""
+    out = []
+    for i in range(lat.Ly - 1):
+        for j in range(lat.Lx - 1):
+            m = i * lat.Lx + j
+            out.append((m, m + lat.Lx + 1, "d"))      # (i,j)-(i+1,j+1)
+            out.append((m + 1, m + lat.Lx, "a"))      # (i,j+1)-(i+1,j)
+    return out
+
+
+def _c(spec, x, y):
+    """One pairwise contraction (a tensordot), the only contraction primitive used here."""
+    return np.einsum(spec, x, y, optimize=True)
+
+
+def _row_step(P, Uj, T, Lj):
+    """P_{j+1}[b,r,c] = sum_{a,l,e,u,d} P_j[a,l,e] U_j[a,u,b] T_j[l,u,r,d] L_j[e,d,c]."""
+    Y = _c("ale,aub->leub", P, Uj)
+    Y = _c("leub,lurd->ebrd", Y, T)
+    return _c("ebrd,edc->brc", Y, Lj)
+
+
+def _row_step_right(Uj, T, Lj, Q):
+    """Q_j[a,l,e] = sum U_j[a,u,b] T_j[l,u,r,d] L_j[e,d,c] Q_{j+1}[b,r,c]."""
+    Y = _c("edc,brc->edbr", Lj, Q)
+    Y = _c("lurd,edbr->lueb", T, Y)
+    return _c("aub,lueb->ale", Uj, Y)
+
+
+def _two_row_step(P, Uj, T1, T2, Lj):
+    """P_{j+1}[b,r,s,c] = sum P_j[a,x,y,e] U_j[a,u,b] T1[x,u,r,m] T2[y,m,s,q] L_j[e,q,c]."""
+    Y = _c("axye,aub->xyeub", P, Uj)
+    Y = _c("xyeub,xurm->yebrm", Y, T1)
+    Y = _c("yebrm,ymsq->ebrsq", Y, T2)
+    return _c("ebrsq,eqc->brsc", Y, Lj)
+
+
+def _rescale(x):
+    """x / c and ln c with c = max|x| (c = 1 if x is all zero): keeps partials in range."""
+    c = float(np.max(np.abs(x))) if x.size else 0.0
+    if c == 0.0 or not math.isfinite(c):
+        return x, 0.0
+    return x / c, math.log(c)
+
+
+# --------------------------------------------------------------------------
+# boundary MPS: apply a row, truncate to Dc (Fig. 1(c))
+# --------------------------------------------------------------------------
+def trivial_mps(Lx):
+    """Boundary MPS of bond 1 and physical dim 1 (index 0 on the outward legs)."""
+    return [np.ones((1, 1, 1)) for _ in range(Lx)]
+
+
+def apply_row_down(U, row):
+    """Exact product of row i (as an MPO acting on its u-legs) with the MPS U_i.
+    C_j[(a,l), d, (b,r)] = sum_u U_j[a,u,b] T_j[l,u,r,d]: bond chi*D, physical d."""
+    out = []
+    for Uj, T in zip(U, row):
+        a, _, b = Uj.shape
+        l, _, r, d = T.shape
+        out.append(np.einsum("aub,lurd->aldbr", Uj, T).reshape(a * l, d, b * r))
+    return out
+
+
+def apply_row_up(L, row):
+    """Mirror of apply_row_down for the bottom-up sweep: contract the d-legs, keep u."""
+    out = []
+    for Lj, T in zip(L, row):
+        a, _, b = Lj.shape
+        l, u, r, _ = T.shape
+        out.append(np.einsum("adb,lurd->alubr", Lj, T).reshape(a * l, u, b * r))
+    return out
+
+
+def truncate(mps, Dc):
+    """Canonical truncation of an open MPS to bond <= Dc.
+
+    Left-to-right QR sweep (left-canonical form), then right-to-left SVD sweep
+    keeping the t = min(Dc, rows, cols) largest singular values at every cut,
+    then the norm nu of the first site is pulled out.  Returns (mps, ln nu);
+    ln nu = -inf for the zero state.
+    """
+    mps = [x.copy() for x in mps]
+    n = len(mps)
+    for j in range(n - 1):
+        a, p, b = mps[j].shape
+        Q, R = np.linalg.qr(mps[j].reshape(a * p, b), mode="reduced")
+        mps[j] = Q.reshape(a, p, Q.shape[1])
+        mps[j + 1] = np.einsum("kb,bpc->kpc", R, mps[j + 1])
+    for j in range(n - 1, 0, -1):
+        a, p, b = mps[j].shape
+        Um, sv, Vt = np.linalg.svd(mps[j].reshape(a, p * b), full_matrices=False)
+        t = min(Dc, a, p * b)
+        mps[j] = Vt[:t].reshape(t, p, b)
+        mps[j - 1] = np.einsum("apk,kt->apt", mps[j - 1], Um[:, :t] * sv[:t])
+    nu = float(np.linalg.norm(mps[0]))
+    if nu == 0.0:
+        return mps, -math.inf
+    mps[0] = mps[0] / nu
+    return mps, math.log(nu)
+
+
+def boundary_envs(A, lat, S):
+    """Upper envs U_0..U_{Ly-1} and lower envs L_0..L_{Ly-1} with their log scales.
+
+    U_0 and L_{Ly-1} are trivial; U_{i+1} = Trunc(Apply(U_i, row i)) and
+    L_{i-1} = Trunc(Apply_up(L_i, row i)).  True env = exp(log) * stored MPS.
+    """
+    Ly = lat.Ly
+    U = [None] * Ly
+    L = [None] * Ly
+    logU = [0.0] * Ly
+    logL = [0.0] * Ly
+    U[0] = trivial_mps(lat.Lx)
+    for i in range(Ly - 1):
+        U[i + 1], ln = truncate(apply_row_down(U[i], row_tensors(A, lat, S, i)), lat.Dc)
+        logU[i + 1] = logU[i] + ln
+    L[Ly - 1] = trivial_mps(lat.Lx)
+    for i in range(Ly - 1, 0, -1):
+        L[i - 1], ln = truncate(apply_row_up(L[i], row_tensors(A, lat, S, i)), lat.Dc)
+        logL[i - 1] = logL[i] + ln
+    return U, L, logU, logL
+
+
+def final_overlap(Ulast, row_last):
+    """w = <U_{Ly-1}| last row> with the last row's d-legs at index 0."""
+    v = np.ones((1, 1))
+    for Uj, T in zip(Ulast, row_last):
+        v = np.einsum("al,aub,lur->br", v, Uj, T[:, :, :, 0])
+    return float(v[0, 0])
+
+
+# --------------------------------------------------------------------------
+# sandwiches <U_i| row(s) |L>
+# --------------------------------------------------------------------------
+def row_sandwich(Ui, row, Li):
+    """(sign, ln|.|) of <U_i| row i |L_i> contracted column by column (no truncation)."""
+    P = np.ones((1, 1, 1))
+    logs = 0.0
+    for Uj, T, Lj in zip(Ui, row, Li):
+        P, ln = _rescale(_row_step(P, Uj, T, Lj))
+        logs += ln
+    w = float(P[0, 0, 0])
+    return (0, -math.inf) if w == 0.0 else (int(np.sign(w)), logs + math.log(abs(w)))
+
+
+def two_row_sandwich(Ui, row1, row2, Lk):
+    """(sign, ln|.|) of <U_i| row i, row i+1 |L_{i+1}>."""
+    P = np.ones((1, 1, 1, 1))
+    logs = 0.0
+    for Uj, T1, T2, Lj in zip(Ui, row1, row2, Lk):
+        P, ln = _rescale(_two_row_step(P, Uj, T1, T2, Lj))
+        logs += ln
+    w = float(P[0, 0, 0, 0])
+    return (0, -math.inf) if w == 0.0 else (int(np.sign(w)), logs + math.log(abs(w)))
+
+
+def _ratio(num, den):
+    """W(S')/W(S) from two (sign, log) pairs."""
+    if num[0] == 0:
+        return 0.0
+    return num[0] * den[0] * math.exp(num[1] - den[1])
+
+
+# --------------------------------------------------------------------------
+# per-sample results
+# --------------------------------------------------------------------------
+def _check_config(lat, S):
+    S = np.asarray(S)
+    return S.shape == (lat.N,) and bool(np.all((S == 0) | (S == 1)))
+
+
+def log_amplitude_one(A, lat, S):
+    """(ln|W(S)|, sign W(S), flag) from the top-down boundary-MPS contraction."""
+    if not _check_config(lat, S):
+        return math.nan, 0, FLAG_BAD_CONFIG
+    U = trivial_mps(lat.Lx)
+    logscale = 0.0
+    for i in range(lat.Ly - 1):
+        U, ln = truncate(apply_row_down(U, row_tensors(A, lat, S, i)), lat.Dc)
+        logscale += ln
+    w = final_overlap(U, row_tensors(A, lat, S, lat.Ly - 1))
+    if w == 0.0 or not math.isfinite(logscale):
+        return -math.inf, 0, FLAG_ZERO_AMPLITUDE
+    out = logscale + math.log(abs(w))
+    if not math.isfinite(out):
+        return out, int(np.sign(w)), FLAG_NONFINITE
+    return out, int(np.sign(w)), FLAG_OK
+
+
+def local_energy_one(A, lat, S, envs=None):
+    """E(S) of Eq. (4) for H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j.
+
+    Off-diagonal terms: 1/2 * W(S')/W(S) for every anti-parallel bond, where S'
+    exchanges the two spins; W(S')/W(S) is taken from the sandwich that holds
+    both sites, with the cached upper and lower environments.
+    """
+    S = np.asarray(S)
+    if not _check_config(lat, S):
+        return math.nan
+    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S)
+    sig = 1 - 2 * S.astype(np.int64)
+    Lx = lat.Lx
+
+    row_den = {}
+    pair_den = {}
+
+    def w_row(i, Sx):
+        return row_sandwich(U[i], row_tensors(A, lat, Sx, i), L[i])
+
+    def w_pair(i, Sx):
+        return two_row_sandwich(U[i], row_tensors(A, lat, Sx, i),
+                                row_tensors(A, lat, Sx, i + 1), L[i + 1])
+
+    E = 0.0
+    for bonds, J in ((j1_bonds(lat), lat.J1), (j2_bonds(lat), lat.J2)):
+        for m, n, kind in bonds:
+            E += J * sig[m] * sig[n] / 4.0
+            if S[m] == S[n]:
+                continue
+            Sp = S.copy()
+            Sp[m], Sp[n] = S[n], S[m]
+            i = min(m, n) // Lx
+            if kind == "h":
+                if i not in row_den:
+                    row_den[i] = w_row(i, S)
+                rho = _ratio(w_row(i, Sp), row_den[i])
+            else:
+                if i not in pair_den:
+                    pair_den[i] = w_pair(i, S)
+                rho = _ratio(w_pair(i, Sp), pair_den[i])
+            E += J * 0.5 * rho
+    return E
+
+
+def log_derivative_one(A, lat, S, envs=None):
+    """Delta[m][s][l][u][r][d] = (1/W_i) dW_i/dA_m^{s}, Eqs. (6)-(7), frozen environments.
+
+    B_m is the row-i sandwich with site m removed: left partial P_j (columns < j),
+    the environment legs U_i[j], L_i[j], and right partial Q_{j+1} (columns > j).
+    Only the slice s = S[m] and the live (non-outward) leg entries are non-zero.
+    """
+    S = np.asarray(S)
+    D, Lx, Ly = lat.D, lat.Lx, lat.Ly
+    out = np.zeros((lat.N, 2, D, D, D, D))
+    if not _check_config(lat, S):
+        out[:] = np.nan
+        return out
+    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S)
+    for i in range(Ly):
+        row = row_tensors(A, lat, S, i)
+        left = [(np.ones((1, 1, 1)), 0.0)]
+        for j in range(Lx):
+            P, lg = left[-1]
+            P, ln = _rescale(_row_step(P, U[i][j], row[j], L[i][j]))
+            left.append((P, lg + ln))
+        right = [None] * (Lx + 1)
+        right[Lx] = (np.ones((1, 1, 1)), 0.0)
+        for j in range(Lx - 1, -1, -1):
+            Q, lg = right[j + 1]
+            Q, ln = _rescale(_row_step_right(U[i][j], row[j], L[i][j], Q))
+            right[j] = (Q, lg + ln)
+        Pn, lgn = left[Lx]
+        w = float(Pn[0, 0, 0])
+        if w == 0.0:
+            continue
+        for j in range(Lx):
+            P, lp = left[j]
+            Q, lq = right[j + 1]
+            B = _c("leub,edbr->lurd", _c("ale,aub->leub", P, U[i][j]),
+                   _c("edc,brc->edbr", L[i][j], Q))
+            m = i * Lx + j
+            Dl, Du, Dr, Dd = leg_dims(lat, i, j)
+            out[m, int(S[m]), :Dl, :Du, :Dr, :Dd] = B / w * math.exp(lp + lq - lgn)
+    return out
+
+
+# --------------------------------------------------------------------------
+# batched front ends (plain loops over samples)
+# --------------------------------------------------------------------------
+def log_amplitude(A, lat, S):
+    B = S.shape[0]
+    la = np.empty(B)
+    sg = np.empty(B, dtype=np.int8)
+    fl = np.empty(B, dtype=np.int8)
+    for b in range(B):
+        la[b], sg[b], fl[b] = log_amplitude_one(A, lat, S[b])
+    return la, sg, fl
+
+
+def local_energy(A, lat, S):
+    """(log_abs, sign, e_loc, flags) per sample."""
+    B = S.shape[0]
+    la, sg, fl = log_amplitude(A, lat, S)
+    e = np.full(B, np.nan)
+    for b in range(B):
+        if fl[b] == FLAG_OK:
+            e[b] = local_energy_one(A, lat, S[b])
+            if not math.isfinite(e[b]):
+                fl[b] = FLAG_NONFINITE
+    return la, sg, e, fl
+
+
+def log_derivative(A, lat, S, weights=None):
+    """Per-sample Delta [B][N][2][D^4] or, with weights, sum_b weights[b] * Delta_b
+    accumulated in sample order (the per-sample term of Eq. (5))."""
+    B = S.shape[0]
+    D4 = lat.D ** 4
+    if weights is None:
+        out = np.zeros((B, lat.N, 2, D4))
+        for b in range(B):
+            out[b] = log_derivative_one(A, lat, S[b]).reshape(lat.N, 2, D4)
+        return out
+    g = np.zeros((lat.N, 2, D4))
+    for b in range(B):
+        g += weights[b] * log_derivative_one(A, lat, S[b]).reshape(lat.N, 2, D4)
+    return g
+
+
+def full_path_one(A, lat, S):
+    """Amplitude, local energy and log-derivative of one sample from one set of envs."""
+    la, sg, fl = log_amplitude_one(A, lat, S)
+    if fl != FLAG_OK:
+        return la, sg, math.nan, np.zeros((lat.N, 2, lat.D ** 4)), fl
+    envs = boundary_envs(A, lat, S)
+    e = local_energy_one(A, lat, S, envs)
+    d = log_derivative_one(A, lat, S, envs).reshape(lat.N, 2, -1)
+    return la, sg, e, d, fl
