@@ -1,0 +1,137 @@
+"""Throughput of the PEPS-VMC hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of spin configurations:
+top-down and bottom-up boundary-MPS sweeps (apply + QR/SVD truncation), the
+single- and two-row sandwiches, every J1/J2 spin-flip ratio, the local energy,
+and the energy gradient dE/dA of the Monte Carlo estimator (log-derivatives of
+every site contracted with 2(E - <E>)/B).
+
+Workload: 8x8 open J1-J2 lattice (J2/J1 = 0.5), D = 4, Dc = 16, 4096 samples
+(one per Markov chain, seeded S^z = 0 configurations), site tensors N(0,1)
+normalised per site; contraction GEMMs in f32, QR/SVD/logs in f64.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _oracle_worker(args):
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    from paper_1806_03761_amd.workloads import make_workload
+    name, lo, hi = args
+    with threadpool_limits(limits=1):
+        lat, A, S, _ = make_workload(name, hi)
+        for b in range(lo, hi):
+            O.full_path_one(A, lat, S[b])
+    return hi - lo
+
+
+def cpu_baseline(name: str, per_core: int = 2):
+    """Time the FP64 oracle (amplitude + local energy + log-derivatives, one sample per
+    process) on the host cores, over a bounded sample of the workload."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    n = per_core * cores
+    tasks = [(name, k * per_core, (k + 1) * per_core) for k in range(cores)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_worker, [(name, 0, 1)] * cores)      # import warm-up
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_worker, tasks))
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done} of the 4096 configurations, {per_core} per process, "
+                      f"{cores} processes, numpy single-threaded; wall {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on one GPU only (the path is data-parallel over samples; "
+              "multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1806_03761_amd import peps
+    from paper_1806_03761_amd.workloads import make_workload
+
+    name = "8x8_D4_Dc16"
+    lat, A, S, _ = make_workload(name, args.batch)
+    B = S.shape[0]
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A).to(dev)
+    Sd = torch.from_numpy(S).to(dev)
+    N, D4 = lat.N, lat.D ** 4
+    grad = torch.empty((N, 2, D4), dtype=torch.float64, device=dev)
+
+    def step():
+        return peps.evaluate(Ad, Sd, lat, args.prec, grad_mode=3, out=grad)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt * 1e3 / args.steps
+    value = B * args.steps / dt
+
+    res = {
+        "metric": "samples/sec (amplitude+E_loc+grad)",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "8x8 open J1-J2 (J2/J1=0.5), D=4, Dc=16, f32 contraction GEMMs, "
+                               "f64 QR/SVD; amplitude + local energy + dE/dA",
+                   "lattice": [lat.Lx, lat.Ly], "D": lat.D, "Dc": lat.Dc, "batch": B,
+                   "gemm_precision": args.prec, "factorisation_precision": "f64"},
+    }
+    if not args.no_plain:
+        # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
+        nplain = 8
+        for b in range(2):
+            peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(nplain):
+            peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
+        torch.cuda.synchronize()
+        res["plain"] = {"value": nplain / (time.perf_counter() - t0), "unit": "samples/s",
+                        "sample": f"{nplain} samples one at a time, f64 GEMMs"}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(name)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

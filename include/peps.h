@@ -1,0 +1,137 @@
+/*
+ * peps.h - C ABI of the MI355X (gfx950) PEPS variational Monte Carlo hot path.
+ *
+ * For a batch of spin configurations S of an open Lx x Ly spin-1/2 lattice and
+ * a PEPS with bond dimension D (physical dimension d = 2), the library computes
+ *   - ln|W(S)| and sign W(S), the single-layer contraction of the PEPS at fixed
+ *     S (Eq. (1) of the paper, the W(S) of Sec. II-A), approximated by the
+ *     row-by-row boundary-MPS contraction with bond truncation Dc (Fig. 1(c));
+ *   - the local energy E(S) of Eq. (4) for the J1-J2 Heisenberg model of
+ *     Sec. III-A (Eq. (9)), from cached upper and lower environments;
+ *   - the log-derivatives Delta = B/W of Eqs. (6)-(7), per sample or contracted
+ *     with per-sample weights (the Monte Carlo gradient of Eq. (5)).
+ *
+ * Conventions shared by every entry point
+ *   A      device, float64, [Ly*Lx][2][D][D][D][D] = [site][phys][l][u][r][d],
+ *          C order, site m = i*Lx + j (row i from the top, column j from the
+ *          left).  Legs that point out of the open lattice (l at j = 0, u at
+ *          i = 0, r at j = Lx-1, d at i = Ly-1) are read at index 0 only; the
+ *          other entries of those legs are never read.  Read-only.
+ *   S      device, int8, [batch][Ly*Lx], values {0, 1}; 0 = spin up (S^z=+1/2).
+ *   batch  number of configurations (>= 0; 0 is a no-op that returns PEPS_OK).
+ *   flags  optional device int8 [batch] (may be NULL): 0 ok, 1 configuration
+ *          value outside {0,1}, 2 zero amplitude, 3 non-finite result.
+ *          A flagged sample never aborts the batch: its outputs are NaN
+ *          (flag 1, 3) or sign 0 / ln|W| = -inf / E = NaN / Delta = 0 (flag 2).
+ *   prec   arithmetic of the contraction GEMMs (boundary apply, sandwiches,
+ *          environment tensors).  QR, SVD, normalisation, ln|W|, sign and the
+ *          energy assembly are always float64.  PEPS_PREC_F32 and
+ *          PEPS_PREC_BF16 round GEMM operands to that type and accumulate in
+ *          float32.
+ *   Every buffer is owned by the caller; outputs are written asynchronously on
+ *   the context's stream and are valid after that stream is synchronised.
+ *   Host-detectable errors (NULL pointers, Lx < 2 or Ly < 2, D < 1, Dc < 1,
+ *   batch < 0, unsupported sizes) return before anything is enqueued.
+ *   A context must not be used by two host threads at once.
+ */
+#ifndef PEPS_H
+#define PEPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PEPS_OK = 0,
+    PEPS_ERR_INVALID_ARG = 1,
+    PEPS_ERR_OOM = 2,
+    PEPS_ERR_HIP = 3,
+    PEPS_ERR_UNSUPPORTED = 4,
+    PEPS_ERR_NUMERICAL = 5
+} peps_status;
+
+typedef enum { PEPS_PREC_F64 = 0, PEPS_PREC_F32 = 1, PEPS_PREC_BF16 = 2 } peps_precision;
+
+/* Lattice Lx x Ly (open boundaries), bond dimension D, boundary-MPS truncation Dc,
+ * couplings of H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j (Sec. III-A). */
+typedef struct {
+    int32_t Lx, Ly, D, Dc;
+    double J1, J2;
+} peps_lattice;
+
+typedef struct peps_ctx peps_ctx;
+
+/* Create a context on HIP device `device`.  It owns a lazily grown workspace and
+ * the tuned launch parameters.  Returns PEPS_ERR_HIP if the device is unusable. */
+peps_status peps_create(peps_ctx** ctx, int device);
+
+/* Free the context and its workspace.  NULL is accepted. */
+peps_status peps_destroy(peps_ctx* ctx);
+
+/* Stream on which all later work is enqueued (a hipStream_t; NULL = default stream). */
+peps_status peps_set_stream(peps_ctx* ctx, void* hip_stream);
+
+/* Cap the device workspace in bytes (0 = default: 1/4 of free device memory at
+ * first use).  Larger batches are processed in chunks that fit; a single sample
+ * that does not fit returns PEPS_ERR_OOM. */
+peps_status peps_set_workspace_limit(peps_ctx* ctx, size_t bytes);
+
+/* Device bytes the context would use for one chunk of `batch` samples. */
+peps_status peps_workspace_query(peps_ctx* ctx, const peps_lattice* lat, int64_t batch,
+                                 peps_precision prec, size_t* bytes);
+
+/* Message of the last failing call on this context ("" if none); valid until the
+ * next call on the context. */
+const char* peps_last_error(const peps_ctx* ctx);
+
+/* ln|W(S)| and sign W(S) (top-down boundary-MPS contraction, then the overlap
+ * with the last row).  log_abs: device float64 [batch]; sign: device int8 [batch]. */
+peps_status peps_log_amplitude(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                               const double* A, const int8_t* S, int64_t batch,
+                               double* log_abs, int8_t* sign, int8_t* flags);
+
+/* Local energy of Eq. (4): E(S) = sum_bonds J [sigma sigma'/4 + 1/2 [s != s'] W(S')/W(S)],
+ * with W(S')/W(S) from the single-row sandwich <U_i|row i|L_i> (horizontal bonds) or
+ * the two-row sandwich <U_i|rows i,i+1|L_{i+1}> (vertical and diagonal bonds).
+ * e_loc: device float64 [batch], total energy of the sample.  log_abs, sign as above. */
+peps_status peps_local_energy(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                              const double* A, const int8_t* S, int64_t batch,
+                              double* log_abs, int8_t* sign, double* e_loc, int8_t* flags);
+
+/* Log-derivatives of Eqs. (6)-(7), Delta_m = (1/W_i) dW_i/dA_m with the row-i
+ * environments held fixed (row i holds site m).
+ * weights == NULL: out is device float64 [batch][Ly*Lx][2][D^4], per sample; only the
+ *                  slice s = S[b][m] and live leg entries are non-zero.
+ * weights != NULL (device float64 [batch]): out is [Ly*Lx][2][D^4] =
+ *                  sum_b weights[b] * Delta_b, summed in sample order (overwritten). */
+peps_status peps_log_derivative(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                                const double* A, const int8_t* S, int64_t batch,
+                                const double* weights, double* out, double* log_abs,
+                                int8_t* sign, int8_t* flags);
+
+/* One pass of the whole path from one set of environments.  Any output may be NULL.
+ * grad_mode: 0 = no gradient; 1 = per-sample Delta into `out` ([batch][N][2][D^4]);
+ *            2 = out = sum_b weights[b] Delta_b ([N][2][D^4]);
+ *            3 = out = dE/dA of Eq. (5) = sum_b (2/B)(E_b - mean E) Delta_b over the
+ *                samples with flag 0 (B = their count); needs e_loc. */
+peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                          const double* A, const int8_t* S, int64_t batch, int32_t grad_mode,
+                          const double* weights, double* log_abs, int8_t* sign,
+                          double* e_loc, double* out, int8_t* flags);
+
+/* Diagnostic, no device work: lay out the workspace of one chunk of `batch` samples
+ * and walk the whole launch sequence of an evaluation (want_eloc, grad_mode as in
+ * peps_evaluate) without launching anything, checking on the host that every
+ * operand offset stays inside its buffer.  Returns PEPS_OK and the chunk's
+ * workspace bytes, or PEPS_ERR_INVALID_ARG if a check fails.  Needs no GPU. */
+peps_status peps_plan_check(const peps_lattice* lat, int64_t batch, int32_t grad_mode,
+                            int32_t want_eloc, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEPS_H */

@@ -1,0 +1,372 @@
+// Small per-sample kernels: validation, rescaling of partial contractions,
+// spin-flip amplitude ratios, local-energy assembly and log-derivative output.
+#include "common.h"
+#include "kernels.h"
+
+namespace peps {
+
+static constexpr int NT = 256;
+
+__device__ inline double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wmax(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double bsum(double v, double* red) {
+    v = wsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+__device__ inline double bmax(double v, double* red) {
+    v = wmax(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < NT / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+__global__ void k_fill(double* x, long long n, double v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+__global__ void k_fill_i8(int8_t* x, long long n, int8_t v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill(double* x, long long n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, v);
+    return hipGetLastError();
+}
+
+// flags[b] = 1 if any S[b][m] is outside {0, 1}, else 0.
+__global__ void k_check_configs(const int8_t* S, int N, int batch, int8_t* flags) {
+    const int b = blockIdx.x;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const int8_t v = S[(long long)b * N + m];
+        if (v != 0 && v != 1) bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) flags[b] = bad ? 1 : 0;
+}
+hipError_t launch_check_configs(const int8_t* S, int N, int batch, int8_t* flags, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_configs, dim3(batch), dim3(256), 0, st, S, N, batch, flags);
+    return hipGetLastError();
+}
+
+// x /= max|x|, lout = lin + ln max|x| (unchanged when x is all zero or not finite).
+__global__ __launch_bounds__(NT) void k_rescale(double* x, long long xs, int n, const double* lin,
+                                                double* lout) {
+    __shared__ double red[NT / 64];
+    const int b = blockIdx.x;
+    double* xb = x + (long long)b * xs;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) mx = fmax(mx, fabs(xb[i]));
+    mx = bmax(mx, red);
+    const bool ok = mx > 0.0 && isfinite(mx);
+    if (ok) {
+        const double inv = 1.0 / mx;
+        for (int i = threadIdx.x; i < n; i += NT) xb[i] *= inv;
+    }
+    if (threadIdx.x == 0) lout[b] = (lin ? lin[b] : 0.0) + (ok ? log(mx) : 0.0);
+}
+hipError_t launch_rescale(double* x, long long xs, int n, const double* lin, double* lout,
+                          int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rescale, dim3(batch), dim3(NT), 0, st, x, xs, n, lin, lout);
+    return hipGetLastError();
+}
+
+// ratio[b][bond] = <F,G> exp(la + lb - lnW) * sgW: W(S')/W(S) from partial contractions.
+__global__ __launch_bounds__(NT) void k_ratio(const double* F, long long fs, const double* G,
+                                              long long gs, int n, const double* la,
+                                              const double* lb, const double* lnW,
+                                              const double* sgW, double* ratio, int nbonds,
+                                              int bond) {
+    __shared__ double red[NT / 64];
+    const int b = blockIdx.x;
+    const double* Fb = F + (long long)b * fs;
+    const double* Gb = G + (long long)b * gs;
+    double d = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) d += Fb[i] * Gb[i];
+    d = bsum(d, red);
+    if (threadIdx.x == 0) {
+        double r;
+        if (d == 0.0) {
+            r = 0.0;
+        } else {
+            const double sg = sgW[b];
+            r = (sg == 0.0) ? NAN : copysign(exp(log(fabs(d)) + la[b] + lb[b] - lnW[b]), d) * sg;
+        }
+        ratio[(long long)b * nbonds + bond] = r;
+    }
+}
+hipError_t launch_ratio(const double* F, long long fs, const double* G, long long gs, int n,
+                        const double* la, const double* lb, const double* lnW, const double* sgW,
+                        double* ratio, int nbonds, int bond, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ratio, dim3(batch), dim3(NT), 0, st, F, fs, G, gs, n, la, lb, lnW, sgW,
+                       ratio, nbonds, bond);
+    return hipGetLastError();
+}
+
+// Full sandwich value from the last (1x1x...) partial: ln|W| = lam + ln|P|, sign.
+__global__ void k_sandwich_value(const double* P, long long ps, const double* lam, double* lnW,
+                                 double* sgW, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const double v = P[(long long)b * ps];
+    if (v == 0.0 || !isfinite(v)) {
+        lnW[b] = (v == 0.0) ? -INFINITY : NAN;
+        sgW[b] = (v == 0.0) ? 0.0 : NAN;
+    } else {
+        lnW[b] = lam[b] + log(fabs(v));
+        sgW[b] = v > 0.0 ? 1.0 : -1.0;
+    }
+}
+hipError_t launch_sandwich_value(const double* P, long long ps, const double* lam, double* lnW,
+                                 double* sgW, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sandwich_value, dim3((batch + 255) / 256), dim3(256), 0, st, P, ps, lam,
+                       lnW, sgW, batch);
+    return hipGetLastError();
+}
+
+// E(S) = sum_bonds J [sigma sigma'/4 + 1/2 [s != s'] ratio]; bonds in the fixed order
+// J1 horizontal (i, j<Lx-1), J1 vertical (i<Ly-1, j), J2 (i,j)-(i+1,j+1), J2 (i,j+1)-(i+1,j).
+__global__ void k_eloc(ElocArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.batch) return;
+    const int Lx = a.Lx, Ly = a.Ly, N = Lx * Ly;
+    const int8_t* s = a.S + (long long)b * N;
+    const double* rt = a.ratio + (long long)b * a.nbonds;
+    if (a.flags[b] != 0) {
+        a.e_loc[b] = NAN;
+        return;
+    }
+    double E = 0.0;
+    int id = 0;
+    auto term = [&](int m, int n, double J, int bid) {
+        const int sm = s[m], sn = s[n];
+        E += J * ((sm == sn) ? 0.25 : -0.25);
+        if (sm != sn) E += J * 0.5 * rt[bid];
+    };
+    for (int i = 0; i < Ly; ++i)
+        for (int j = 0; j + 1 < Lx; ++j) term(i * Lx + j, i * Lx + j + 1, a.J1, id++);
+    for (int i = 0; i + 1 < Ly; ++i)
+        for (int j = 0; j < Lx; ++j) term(i * Lx + j, (i + 1) * Lx + j, a.J1, id++);
+    for (int i = 0; i + 1 < Ly; ++i)
+        for (int j = 0; j + 1 < Lx; ++j) term(i * Lx + j, (i + 1) * Lx + j + 1, a.J2, id++);
+    for (int i = 0; i + 1 < Ly; ++i)
+        for (int j = 0; j + 1 < Lx; ++j) term(i * Lx + j + 1, (i + 1) * Lx + j, a.J2, id++);
+    a.e_loc[b] = E;
+}
+hipError_t launch_eloc(const ElocArgs& a, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eloc, dim3((a.batch + 127) / 128), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
+// log_abs = logU + lnW, sign; zero amplitude -> flag 2, non-finite -> flag 3.
+__global__ void k_amp_out(const double* logU, const double* lnW, const double* sgW,
+                          int8_t* flags, double* log_abs, int8_t* sign, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    int8_t f = flags[b];
+    double la = logU[b] + lnW[b];
+    double sg = sgW[b];
+    if (f == 0) {
+        if (sg == 0.0 || la == -INFINITY) {
+            f = 2;
+        } else if (!isfinite(la) || !isfinite(sg)) {
+            f = 3;
+        }
+    }
+    if (f == 1 || f == 3) {
+        la = NAN;
+        sg = 0.0;
+    } else if (f == 2) {
+        la = -INFINITY;
+        sg = 0.0;
+    }
+    flags[b] = f;
+    if (log_abs) log_abs[b] = la;
+    if (sign) sign[b] = (int8_t)(sg > 0.0 ? 1 : (sg < 0.0 ? -1 : 0));
+}
+hipError_t launch_amp_out(const double* logU, const double* lnW, const double* sgW,
+                          int8_t* flags, double* log_abs, int8_t* sign, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_amp_out, dim3((batch + 255) / 256), dim3(256), 0, st, logU, lnW, sgW,
+                       flags, log_abs, sign, batch);
+    return hipGetLastError();
+}
+
+__global__ void k_nan_flagged(const int8_t* flags, double* log_abs, int8_t* sign, double* e_loc,
+                              int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    if (flags[b] == 1 || flags[b] == 3) {
+        if (e_loc) e_loc[b] = NAN;
+        if (log_abs) log_abs[b] = NAN;
+        if (sign) sign[b] = 0;
+    }
+}
+hipError_t launch_nan_flagged(const int8_t* flags, double* log_abs, int8_t* sign, double* e_loc,
+                              int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nan_flagged, dim3((batch + 255) / 256), dim3(256), 0, st, flags, log_abs,
+                       sign, e_loc, batch);
+    return hipGetLastError();
+}
+
+// Delta = B / <B, T> over the live block (l<Dl, u<Du, r<Dr, d<Dd) of site `site`.
+// Dsite points at the site's D^4 block of sample 0; samples are `bs` doubles apart.
+__global__ __launch_bounds__(NT) void k_grad_site(double* Dsite, long long bs, const double* A,
+                                                  const int8_t* S, int site, int N, int D, int Dl,
+                                                  int Du, int Dr, int Dd) {
+    __shared__ double red[NT / 64];
+    const int b = blockIdx.x;
+    const int D2 = D * D, D3 = D2 * D, D4 = D3 * D;
+    double* Bb = Dsite + (long long)b * bs;
+    const int s = S[(long long)b * N + site] & 1;
+    const double* T = A + ((long long)site * 2 + s) * D4;
+    const int nl = Dl * Du * Dr * Dd;
+    double w = 0.0;
+    for (int e = threadIdx.x; e < nl; e += NT) {
+        int x = e;
+        const int d = x % Dd; x /= Dd;
+        const int r = x % Dr; x /= Dr;
+        const int u = x % Du;
+        const int l = x / Du;
+        const int o = l * D3 + u * D2 + r * D + d;
+        w += Bb[o] * T[o];
+    }
+    w = bsum(w, red);
+    const double inv = (w != 0.0) ? 1.0 / w : 0.0;
+    for (int e = threadIdx.x; e < D4; e += NT) Bb[e] *= inv;
+}
+hipError_t launch_grad_site(double* Dsite, long long bs, const double* A, const int8_t* S, int site,
+                            int N, int D, int Dl, int Du, int Dr, int Dd, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_site, dim3(batch), dim3(NT), 0, st, Dsite, bs, A, S, site, N, D, Dl,
+                       Du, Dr, Dd);
+    return hipGetLastError();
+}
+
+// out[b][m][s][e] from Delta[b][m][e] (the slice s = S[b][m]; the other slice is zero).
+__global__ void k_grad_store(const double* Dall, const int8_t* S, int N, int D4,
+                             const int8_t* flags, double* out) {
+    const int b = blockIdx.y;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = 2LL * N * D4;
+    if (e >= per) return;
+    const int m = (int)(e / (2 * D4));
+    const int rem = (int)(e % (2 * D4));
+    const int slice = rem / D4, k = rem % D4;
+    const int s = S[(long long)b * N + m] & 1;
+    const int8_t f = flags[b];
+    double v = 0.0;
+    if (f == 1 || f == 3) {
+        v = NAN;
+    } else if (f == 0 && slice == s) {
+        v = Dall[((long long)b * N + m) * D4 + k];
+    }
+    out[(long long)b * per + e] = v;
+}
+hipError_t launch_grad_store(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
+                             double* out, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const long long per = 2LL * N * D4;
+    hipLaunchKernelGGL(k_grad_store, dim3((unsigned)((per + 255) / 256), batch), dim3(256), 0, st,
+                       Dall, S, N, D4, flags, out);
+    return hipGetLastError();
+}
+
+// out[m][s][e] (+)= sum over b in order of w_b [S_b[m] = s] Delta_b[m][e]; flagged samples skipped.
+__global__ void k_grad_reduce(const double* Dall, const int8_t* S, int N, int D4,
+                              const int8_t* flags, const double* w, int wmode, int accumulate,
+                              double* out, int batch) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2LL * N * D4) return;
+    const int m = (int)(e / (2 * D4));
+    const int rem = (int)(e % (2 * D4));
+    const int slice = rem / D4, k = rem % D4;
+    double acc = 0.0;
+    for (int b = 0; b < batch; ++b) {
+        if (flags[b] != 0) continue;
+        if ((S[(long long)b * N + m] & 1) != slice) continue;
+        const double wb = (wmode == 2) ? 1.0 : w[b];
+        acc += wb * Dall[((long long)b * N + m) * D4 + k];
+    }
+    out[e] = accumulate ? out[e] + acc : acc;
+}
+hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
+                              const double* w, int wmode, int accumulate, double* out, int batch,
+                              hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const long long n = 2LL * N * D4;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, Dall, S, N,
+                       D4, flags, w, wmode, accumulate, out, batch);
+    return hipGetLastError();
+}
+
+// acc[0] += sum of e_loc over flag-0 samples (in order), acc[1] += their count.
+__global__ void k_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
+                              int accumulate) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < batch; ++b)
+        if (flags[b] == 0) {
+            s += e_loc[b];
+            c += 1.0;
+        }
+    acc[0] = accumulate ? acc[0] + s : s;
+    acc[1] = accumulate ? acc[1] + c : c;
+}
+hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
+                              int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_sums, dim3(1), dim3(64), 0, st, e_loc, flags, batch, acc, accumulate);
+    return hipGetLastError();
+}
+
+// Eq. (5): dE/dA = 2 <Delta E> - 2 <Delta><E> with <.> the mean over flag-0 samples.
+__global__ void k_energy_grad_combine(const double* G1, const double* G0, const double* acc,
+                                      long long n, double* out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double cnt = acc[1];
+    if (cnt == 0.0) {
+        out[i] = 0.0;
+        return;
+    }
+    const double Em = acc[0] / cnt;
+    out[i] = 2.0 * G1[i] / cnt - 2.0 * (G0[i] / cnt) * Em;
+}
+hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,
+                                      long long n, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_energy_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       G1, G0, acc, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace peps

@@ -1,0 +1,471 @@
+// Batched float64 factorisations of the boundary-MPS truncation (Fig. 1(c)).
+//
+//  k_qr      Householder QR of one column tensor X (rows (a,phys), cols right bond),
+//            one workgroup per matrix, column-major, LDS-resident when it fits.
+//            The reflectors stay in X (below the diagonal) for the later
+//            implicit application of Q; R is written to its own buffer.
+//  k_svd     centre formation Z = Q G (implicit Q, reflectors applied in reverse)
+//            followed by a one-sided (Hestenes) Jacobi SVD of Z reshaped to
+//            (left bond) x (phys, right bond); the t = min(Dc, rows, cols)
+//            leading right singular vectors become the new boundary tensor and
+//            U_t Sigma_t is carried to the next column on the left.
+//  k_center0 the same centre formation for the first column, then the norm is
+//            pulled out into the running log scale.
+#include "common.h"
+#include "kernels.h"
+
+namespace peps {
+
+static constexpr int NT = 256;
+static constexpr int kRelayout = 32;
+static constexpr double kTiny = 1e-292;   // Z -> X relayout through registers up to NT*kRelayout
+
+__host__ __device__ inline bool svd_alias(int mz, int tin) {
+    return (long long)mz * tin <= (long long)NT * kRelayout;
+}
+
+__device__ inline double wave_sum(double v, int width) {
+    for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the whole workgroup; every thread gets the result.
+__device__ inline double block_sum(double v, double* red) {
+    v = wave_sum(v, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// Max over the whole workgroup; every thread gets the result.
+__device__ inline double block_max(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+__device__ inline int npow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// QR
+// ---------------------------------------------------------------------------
+// X: column-major m x n per batch item (stride xs); in place -> reflectors + R.
+// R: row-major r x n (zeros below the diagonal), r = min(m, n); tau: [r].
+__global__ __launch_bounds__(NT) void k_qr(double* X, long long xs, int m, int n,
+                                           double* R, long long rs, double* tau, long long ts,
+                                           int use_lds) {
+    extern __shared__ double lds[];
+    __shared__ double red[NT / 64];
+    __shared__ double s_beta, s_tau, s_scal;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    double* Xg = X + (long long)b * xs;
+    double* W = use_lds ? lds : Xg;
+    const int r = min(m, n);
+    if (use_lds) {
+        for (int e = tid; e < m * n; e += NT) W[e] = Xg[e];
+        __syncthreads();
+    }
+    for (int k = 0; k < r; ++k) {
+        double* colk = W + (long long)k * m;
+        double part = 0.0;
+        for (int i = k + 1 + tid; i < m; i += NT) part += colk[i] * colk[i];
+        const double s = block_sum(part, red);
+        if (tid == 0) {
+            const double alpha = colk[k];
+            if (s == 0.0) {
+                s_tau = 0.0;
+                s_beta = alpha;
+                s_scal = 0.0;
+            } else {
+                const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+                s_tau = (beta - alpha) / beta;
+                s_scal = 1.0 / (alpha - beta);
+                s_beta = beta;
+            }
+        }
+        __syncthreads();
+        const double tk = s_tau;
+        if (tk != 0.0) {
+            const double sc = s_scal;
+            for (int i = k + 1 + tid; i < m; i += NT) colk[i] *= sc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            colk[k] = s_beta;
+            tau[(long long)b * ts + k] = tk;
+        }
+        if (tk != 0.0) {
+            const int ncols = n - k - 1;
+            if (ncols > 0) {
+                const int tpc = min(64, max(1, NT / npow2(ncols)));
+                const int ngroups = NT / tpc;
+                const int g = tid / tpc, l = tid % tpc;
+                for (int c0 = k + 1; c0 < n; c0 += ngroups) {
+                    const int c = c0 + g;
+                    const bool act = c < n;
+                    double* colc = W + (long long)(act ? c : k) * m;
+                    double dot = 0.0;
+                    if (act) {
+                        for (int i = k + 1 + l; i < m; i += tpc) dot += colk[i] * colc[i];
+                        if (l == 0) dot += colc[k];
+                    }
+                    dot = wave_sum(dot, tpc);
+                    if (act) {
+                        const double f = tk * dot;
+                        if (l == 0) colc[k] -= f;
+                        for (int i = k + 1 + l; i < m; i += tpc) colc[i] -= f * colk[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // R (row-major r x n) and write-back of the reflectors
+    double* Rb = R + (long long)b * rs;
+    for (int e = tid; e < r * n; e += NT) {
+        const int i = e / n, c = e % n;
+        Rb[e] = (i <= c) ? W[(long long)c * m + i] : 0.0;
+    }
+    if (use_lds) {
+        for (int e = tid; e < m * n; e += NT) Xg[e] = W[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// implicit Q: Z (column-major mz x tin) <- H_0 H_1 ... H_{r-1} Z
+// V column-major mz x r (reflector k in column k below the diagonal, unit diagonal).
+// ---------------------------------------------------------------------------
+__device__ void apply_q(const double* V, const double* tau, int mz, int r, double* Z, int tin,
+                        double* vbuf) {
+    const int tid = threadIdx.x;
+    const int tpc = min(64, max(1, NT / npow2(tin)));
+    const int ngroups = NT / tpc;
+    const int g = tid / tpc, l = tid % tpc;
+    for (int k = r - 1; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        __syncthreads();
+        for (int i = k + 1 + tid; i < mz; i += NT) vbuf[i] = V[(long long)k * mz + i];
+        __syncthreads();
+        for (int c0 = 0; c0 < tin; c0 += ngroups) {
+            const int c = c0 + g;
+            const bool act = c < tin;
+            double* zc = Z + (long long)(act ? c : 0) * mz;
+            double dot = 0.0;
+            if (act) {
+                for (int i = k + 1 + l; i < mz; i += tpc) dot += vbuf[i] * zc[i];
+                if (l == 0) dot += zc[k];
+            }
+            dot = wave_sum(dot, tpc);
+            if (act) {
+                const double f = tk * dot;
+                if (l == 0) zc[k] -= f;
+                for (int i = k + 1 + l; i < mz; i += tpc) zc[i] -= f * vbuf[i];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Load Z = [G; 0] column-major (mz x tin) from G row-major (r x tin), then apply Q.
+__device__ void form_center(const double* V, const double* tau, const double* G, int mz, int r,
+                            int tin, double* Z, double* vbuf) {
+    for (int e = threadIdx.x; e < mz * tin; e += NT) {
+        const int c = e / mz, i = e % mz;
+        Z[e] = (i < r) ? G[(long long)i * tin + c] : 0.0;
+    }
+    __syncthreads();
+    if (V) apply_q(V, tau, mz, r, Z, tin, vbuf);
+}
+
+// ---------------------------------------------------------------------------
+// SVD truncation step
+// ---------------------------------------------------------------------------
+// Modes:  V != nullptr: Z = Q G (Q from reflectors V/tau, G row-major r x tin)
+//         V == nullptr: Z = G read as a column-major mz x tin matrix (tin = 1 here)
+// M = Z reshaped to m' x n' with m' = mz/p, n' = p*tin, M[a][d*tin+t] = Z[a*p+d][t].
+// Outputs: newU row-major tk x n' (new boundary tensor (tk, p, tin)), Gout row-major
+// m' x tk (U_t Sigma_t).  tk = min(Dc, m', n').
+struct SvdArgs {
+    const double* V; long long vs;
+    const double* tau; long long ts;
+    const double* G; long long gs;
+    int mz, r, tin, p, Dc;
+    double* newU; long long us;
+    double* Gout; long long gos;
+    double* scratch; long long ss;   // global scratch when LDS is too small
+    int use_lds, max_sweeps;
+    int8_t* flags;                    // set to 3 when Jacobi does not converge
+};
+
+__global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double red[NT / 64];
+    __shared__ int s_rot;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int mz = a.mz, tin = a.tin, p = a.p;
+    const int mp = mz / p, np = p * tin;
+    const bool caseA = mp >= np;              // orthogonalise columns of M, else of M^T
+    const int len = caseA ? mp : np, cnt = caseA ? np : mp;
+    const int tk = min(a.Dc, cnt);
+    // scratch: Z (mz*tin) | X (only when Z cannot be relaid in registers) | J | vbuf | sig | perm
+    const bool alias = svd_alias(mz, tin);
+    double* base = a.use_lds ? lds : a.scratch + (long long)b * a.ss;
+    double* Z = base;
+    double* X = alias ? Z : Z + (long long)mz * tin;
+    double* J = X + (long long)mz * tin;
+    double* vbuf = J + (long long)cnt * cnt;
+    double* sig = vbuf + mz;
+    int* perm = (int*)(sig + cnt);
+
+    form_center(a.V ? a.V + (long long)b * a.vs : nullptr, a.tau + (long long)b * a.ts,
+                a.G + (long long)b * a.gs, mz, a.V ? a.r : mz, tin, Z, vbuf);
+    // Z (col-major mz x tin) -> X (col-major len x cnt): M[a][d*tin+t] = Z[a*p+d][t]
+    if (alias) {
+        double tmp[kRelayout];
+        const int tot = mz * tin;
+#pragma unroll
+        for (int q = 0; q < kRelayout; ++q) {
+            const int e = q * NT + tid;
+            tmp[q] = e < tot ? Z[e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRelayout; ++q) {
+            const int e = q * NT + tid;
+            if (e < tot) {
+                const int t = e / mz, i = e % mz;
+                const int ar = i / p, d = i % p;
+                const int col = d * tin + t;
+                X[caseA ? (long long)col * len + ar : (long long)ar * len + col] = tmp[q];
+            }
+        }
+    } else {
+        for (int e = tid; e < mz * tin; e += NT) {
+            const int t = e / mz, i = e % mz;
+            const int ar = i / p, d = i % p;
+            const int col = d * tin + t;
+            X[caseA ? (long long)col * len + ar : (long long)ar * len + col] = Z[e];
+        }
+    }
+    __syncthreads();
+    // exact power-of-two prescale so that the largest entry is in [0.5, 1): the
+    // underflow floor below is then relative to the matrix
+    int ex = 0;
+    {
+        double mx = 0.0;
+        for (int e = tid; e < len * cnt; e += NT) mx = fmax(mx, fabs(X[e]));
+        mx = block_max(mx, red);
+        if (mx > 0.0 && isfinite(mx)) frexp(mx, &ex);
+        for (int e = tid; e < len * cnt; e += NT) X[e] = ldexp(X[e], -ex);
+    }
+    for (int e = tid; e < cnt * cnt; e += NT) J[e] = ((e / cnt) == (e % cnt)) ? 1.0 : 0.0;
+    __syncthreads();
+
+    const int cpad = cnt + (cnt & 1);
+    const int npairs = cpad / 2;
+    const int tpp = min(64, max(1, NT / npow2(npairs)));
+    const int ngroups = NT / tpp;
+    const int g = tid / tpp, l = tid % tpp;
+    const double tol = 2.220446049250313e-16 * sqrt((double)len);
+    int sweep = 0;
+    for (; sweep < a.max_sweeps; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int rd = 0; rd < cpad - 1; ++rd) {
+            for (int p0 = 0; p0 < npairs; p0 += ngroups) {
+                const int pi = p0 + g;
+                int cp = -1, cq = -1;
+                if (pi < npairs) {
+                    const int k1 = pi, k2 = cpad - 1 - pi;
+                    cp = (k1 == 0) ? 0 : ((k1 - 1 + rd) % (cpad - 1)) + 1;
+                    cq = (k2 == 0) ? 0 : ((k2 - 1 + rd) % (cpad - 1)) + 1;
+                    if (cp >= cnt || cq >= cnt) cp = cq = -1;
+                }
+                const bool act = cp >= 0;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                double* xp = X + (long long)(act ? cp : 0) * len;
+                double* xq = X + (long long)(act ? cq : 0) * len;
+                if (act) {
+                    for (int i = l; i < len; i += tpp) {
+                        const double u = xp[i], v = xq[i];
+                        al += u * u;
+                        be += v * v;
+                        ga += u * v;
+                    }
+                }
+                al = wave_sum(al, tpp);
+                be = wave_sum(be, tpp);
+                ga = wave_sum(ga, tpp);
+                // sqrt(al)*sqrt(be), not sqrt(al*be): the product underflows for
+                // columns of norm ~1e-140 and the test would then never pass
+                // pairs with a squared column norm in the underflow range (< 1e-292 of
+                // the largest entry squared) are left alone: their contribution to the
+                // state is below 1e-146 and their rotations cannot be resolved
+                if (act && al > kTiny && be > kTiny && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    // smaller root of t^2 + 2 zeta t - 1 = 0; for |zeta| > 1e150 zeta^2
+                    // would overflow and t = 1/(2 zeta) to working precision
+                    const double t = fabs(zeta) > 1e150
+                                         ? 0.5 / zeta
+                                         : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                    for (int i = l; i < len; i += tpp) {
+                        const double u = xp[i], v = xq[i];
+                        xp[i] = c * u - s * v;
+                        xq[i] = s * u + c * v;
+                    }
+                    double* jp = J + (long long)cp * cnt;
+                    double* jq = J + (long long)cq * cnt;
+                    for (int i = l; i < cnt; i += tpp) {
+                        const double u = jp[i], v = jq[i];
+                        jp[i] = c * u - s * v;
+                        jq[i] = s * u + c * v;
+                    }
+                    if (l == 0 && s != 0.0) s_rot = 1;   // an underflowed rotation changes nothing
+                }
+            }
+            __syncthreads();
+        }
+        if (s_rot == 0) break;
+        __syncthreads();
+    }
+    if (sweep == a.max_sweeps && tid == 0 && a.flags && a.flags[b] == 0) a.flags[b] = 3;
+
+    // singular values and descending order (ties by index)
+    for (int k = tid; k < cnt; k += NT) {
+        const double* xk = X + (long long)k * len;
+        double s2 = 0.0;
+        for (int i = 0; i < len; ++i) s2 += xk[i] * xk[i];
+        sig[k] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int k = tid; k < cnt; k += NT) {
+        int rank = 0;
+        const double sk = sig[k];
+        for (int j = 0; j < cnt; ++j) rank += (sig[j] > sk) || (sig[j] == sk && j < k);
+        perm[rank] = k;
+    }
+    __syncthreads();
+    double* U = a.newU + (long long)b * a.us;
+    double* Go = a.Gout + (long long)b * a.gos;
+    if (caseA) {
+        // V = J (np x np), G = X columns (mp)
+        for (int e = tid; e < tk * np; e += NT) {
+            const int rr = e / np, c = e % np;
+            U[e] = J[(long long)perm[rr] * cnt + c];
+        }
+        for (int e = tid; e < mp * tk; e += NT) {
+            const int i = e / tk, rr = e % tk;
+            Go[e] = ldexp(X[(long long)perm[rr] * len + i], ex);
+        }
+    } else {
+        // X = M^T: columns are sigma_k v_k; U = J (mp x mp)
+        for (int e = tid; e < tk * np; e += NT) {
+            const int rr = e / np, c = e % np;
+            const int k = perm[rr];
+            const double s = sig[k];
+            U[e] = s > 0.0 ? X[(long long)k * len + c] / s : 0.0;
+        }
+        for (int e = tid; e < mp * tk; e += NT) {
+            const int i = e / tk, rr = e % tk;
+            const int k = perm[rr];
+            Go[e] = ldexp(J[(long long)k * cnt + i] * sig[k], ex);
+        }
+    }
+}
+
+// First column: Z = Q_0 G_1 (mz x tin), nu = ||Z||, newU_0 = Z / nu (row-major mz x tin),
+// logs[b] = logs_in[b] + ln nu.
+__global__ __launch_bounds__(NT) void k_center0(const double* V, long long vs, const double* tau,
+                                                long long ts, const double* G, long long gs, int mz,
+                                                int r, int tin, double* newU, long long us,
+                                                const double* logs_in, double* logs_out,
+                                                double* scratch, long long ss, int use_lds) {
+    extern __shared__ double lds[];
+    __shared__ double red[NT / 64];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    double* Z = use_lds ? lds : scratch + (long long)b * ss;
+    double* vbuf = Z + (long long)mz * tin;
+    form_center(V ? V + (long long)b * vs : nullptr, tau + (long long)b * ts, G + (long long)b * gs,
+                mz, V ? r : mz, tin, Z, vbuf);
+    double part = 0.0;
+    for (int e = tid; e < mz * tin; e += NT) part += Z[e] * Z[e];
+    const double nu = sqrt(block_sum(part, red));
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    double* U = newU + (long long)b * us;
+    for (int e = tid; e < mz * tin; e += NT) {
+        const int i = e / tin, c = e % tin;
+        U[e] = Z[(long long)c * mz + i] * inv;
+    }
+    if (tid == 0) logs_out[b] = (logs_in ? logs_in[b] : 0.0) + (nu > 0.0 ? log(nu) : -INFINITY);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static size_t lds_cap() { return get_lds_cap(); }
+
+hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
+                     long long ts, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const size_t bytes = (size_t)m * n * sizeof(double);
+    const int use = bytes <= lds_cap() - 1024;
+    hipLaunchKernelGGL(k_qr, dim3(batch), dim3(NT), use ? bytes : 0, st, X, xs, m, n, R, rs, tau,
+                       ts, use);
+    return hipGetLastError();
+}
+
+size_t svd_scratch_doubles(int mz, int tin, int p) {
+    const int mp = mz / p, np = p * tin;
+    const int cnt = mp < np ? mp : np;
+    const size_t zx = (size_t)mz * tin * (svd_alias(mz, tin) ? 1 : 2);
+    return zx + (size_t)cnt * cnt + mz + cnt + (cnt + 1) / 2 + 8;
+}
+
+hipError_t launch_svd(const double* V, long long vs, const double* tau, long long ts,
+                      const double* G, long long gs, int mz, int r, int tin, int p, int Dc,
+                      double* newU, long long us, double* Gout, long long gos, double* scratch,
+                      long long ss, int8_t* flags, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    SvdArgs a;
+    a.V = V; a.vs = vs; a.tau = tau; a.ts = ts; a.G = G; a.gs = gs;
+    a.mz = mz; a.r = r; a.tin = tin; a.p = p; a.Dc = Dc;
+    a.newU = newU; a.us = us; a.Gout = Gout; a.gos = gos;
+    a.scratch = scratch; a.ss = ss; a.max_sweeps = 40; a.flags = flags;
+    const size_t bytes = svd_scratch_doubles(mz, tin, p) * sizeof(double);
+    a.use_lds = bytes <= lds_cap() - 1024;
+    hipLaunchKernelGGL(k_svd, dim3(batch), dim3(NT), a.use_lds ? bytes : 0, st, a);
+    return hipGetLastError();
+}
+
+size_t center0_scratch_doubles(int mz, int tin) { return (size_t)mz * tin + mz + 8; }
+
+hipError_t launch_center0(const double* V, long long vs, const double* tau, long long ts,
+                          const double* G, long long gs, int mz, int r, int tin, double* newU,
+                          long long us, const double* logs_in, double* logs_out, double* scratch,
+                          long long ss, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const size_t bytes = center0_scratch_doubles(mz, tin) * sizeof(double);
+    const int use = bytes <= lds_cap() - 1024;
+    hipLaunchKernelGGL(k_center0, dim3(batch), dim3(NT), use ? bytes : 0, st, V, vs, tau, ts, G, gs,
+                       mz, r, tin, newU, us, logs_in, logs_out, scratch, ss, use);
+    return hipGetLastError();
+}
+
+}  // namespace peps

@@ -1,0 +1,64 @@
+// Launchers of the library's HIP kernels (all enqueue on `st`, none synchronises).
+#pragma once
+
+#include "common.h"
+
+namespace peps {
+
+hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st);
+size_t get_lds_cap();
+
+hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
+                     long long ts, int batch, hipStream_t st);
+size_t svd_scratch_doubles(int mz, int tin, int p);
+hipError_t launch_svd(const double* V, long long vs, const double* tau, long long ts,
+                      const double* G, long long gs, int mz, int r, int tin, int p, int Dc,
+                      double* newU, long long us, double* Gout, long long gos, double* scratch,
+                      long long ss, int8_t* flags, int batch, hipStream_t st);
+size_t center0_scratch_doubles(int mz, int tin);
+hipError_t launch_center0(const double* V, long long vs, const double* tau, long long ts,
+                          const double* G, long long gs, int mz, int r, int tin, double* newU,
+                          long long us, const double* logs_in, double* logs_out, double* scratch,
+                          long long ss, int batch, hipStream_t st);
+
+// misc
+hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
+hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st);
+hipError_t launch_check_configs(const int8_t* S, int N, int batch, int8_t* flags, hipStream_t st);
+hipError_t launch_rescale(double* x, long long xs, int n, const double* lin, double* lout,
+                          int batch, hipStream_t st);
+hipError_t launch_ratio(const double* F, long long fs, const double* G, long long gs, int n,
+                        const double* la, const double* lb, const double* lnW, const double* sgW,
+                        double* ratio, int nbonds, int bond, int batch, hipStream_t st);
+hipError_t launch_sandwich_value(const double* P, long long ps, const double* lam, double* lnW,
+                                 double* sgW, int batch, hipStream_t st);
+struct ElocArgs {
+    const int8_t* S; int Lx, Ly;
+    double J1, J2;
+    const double* ratio; int nbonds;
+    const int8_t* flags;
+    double* e_loc;
+    int batch;
+};
+hipError_t launch_eloc(const ElocArgs& a, hipStream_t st);
+hipError_t launch_amp_out(const double* logU, const double* lnW, const double* sgW,
+                          int8_t* flags, double* log_abs, int8_t* sign, int batch, hipStream_t st);
+// Delta = B / <B, T> on the live block of site `site`, in place.
+hipError_t launch_grad_site(double* Dsite, long long bs, const double* A, const int8_t* S, int site,
+                            int N, int D, int Dl, int Du, int Dr, int Dd, int batch, hipStream_t st);
+// per-sample output out[b][m][s][D^4] (both slices written) from Delta[b][m][D^4]
+hipError_t launch_grad_store(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
+                             double* out, int batch, hipStream_t st);
+// out[m][s][e] (+)= sum_b w_b [S_b[m] = s] Delta_b[m][e]; wmode 0/1: w[b], 2: ones.
+// Flagged samples are skipped.
+hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
+                              const double* w, int wmode, int accumulate, double* out, int batch,
+                              hipStream_t st);
+hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
+                              int accumulate, hipStream_t st);
+hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,
+                                      long long n, double* out, hipStream_t st);
+hipError_t launch_nan_flagged(const int8_t* flags, double* log_abs, int8_t* sign, double* e_loc,
+                              int batch, hipStream_t st);
+
+}  // namespace peps

@@ -1,0 +1,843 @@
+// Host side of the PEPS library: argument checks, the per-lattice plan (bond
+// dimensions of every boundary MPS and truncation), workspace layout, and the
+// launch sequence of one evaluation.  Every arithmetic step runs in the HIP
+// kernels; this file only computes shapes, offsets and strides.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/peps.h"
+#include "common.h"
+#include "kernels.h"
+
+struct peps_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t ws_limit = 0;
+    double* ones = nullptr;   // 4096 ones
+    std::string err;
+};
+
+namespace peps {
+
+void set_lds_cap(size_t bytes);
+
+namespace {
+
+constexpr int kOnes = 4096;
+
+struct Op {
+    double* p;
+    long long bs;    // batch stride in doubles
+    long long ext;   // doubles addressable from p for one sample (host-side bounds check)
+    Op at(long long off) const { return Op{p + off, bs, ext - off}; }
+};
+
+inline Idx2 I1(long long s) { return Idx2{1 << 30, 0, s}; }
+inline Idx2 I2(int inner, long long so, long long si) { return Idx2{inner, so, si}; }
+
+struct Trunc {
+    std::vector<int> chi, K, rho, tau;
+    int pin = 1, p = 1;
+};
+
+struct Layout {
+    // per-chunk byte offsets of each buffer and per-sample strides (doubles)
+    size_t bytes = 0;
+    int Bc = 0;
+    size_t alloc(long long per_sample, long long fixed = 0) {
+        size_t off = bytes;
+        size_t n = (size_t)(per_sample * Bc + fixed) * sizeof(double);
+        bytes += (n + 255) / 256 * 256;
+        return off;
+    }
+};
+
+class Runner {
+public:
+    Runner(peps_ctx* c, const peps_lattice& l, peps_precision pr)
+        : ctx(c), lat(l), prec(pr) {
+        Lx = l.Lx; Ly = l.Ly; D = l.D; Dc = l.Dc; N = Lx * Ly;
+        D2 = D * D; D3 = D2 * D; D4 = D3 * D;
+        ar = prec == PEPS_PREC_F64 ? Arith::F64 : (prec == PEPS_PREC_F32 ? Arith::F32 : Arith::BF16);
+        Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
+        Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
+        chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
+        chiL.assign(Ly, std::vector<int>(Lx + 1, 1));
+        tU.resize(Ly);
+        tL.resize(Ly);
+        for (int i = 0; i + 1 < Ly; ++i) {
+            tU[i] = make_trunc(chiU[i], Dv[i], Dv[i + 1]);
+            chiU[i + 1] = tU[i].tau;
+        }
+        for (int i = Ly - 1; i >= 1; --i) {
+            tL[i] = make_trunc(chiL[i], Dv[i + 1], Dv[i]);
+            chiL[i - 1] = tL[i].tau;
+        }
+    }
+
+    Trunc make_trunc(const std::vector<int>& chi, int pin, int p) const {
+        Trunc t;
+        t.chi = chi; t.pin = pin; t.p = p;
+        t.K.resize(Lx + 1); t.rho.resize(Lx + 1); t.tau.resize(Lx + 1);
+        for (int c = 0; c <= Lx; ++c) t.K[c] = chi[c] * Dh[c];
+        t.rho[0] = 1;
+        for (int j = 0; j + 1 < Lx; ++j) t.rho[j + 1] = std::min(t.rho[j] * p, t.K[j + 1]);
+        t.rho[Lx] = 1;
+        t.tau[Lx] = 1;
+        for (int j = Lx - 1; j >= 1; --j) t.tau[j] = std::min(std::min(Dc, t.rho[j]), p * t.tau[j + 1]);
+        t.tau[0] = 1;
+        return t;
+    }
+
+    long long env_row_size(const std::vector<int>& chi, int phys) const {
+        long long s = 0;
+        for (int j = 0; j < Lx; ++j) s += (long long)chi[j] * phys * chi[j + 1];
+        return s;
+    }
+    long long env_off(const std::vector<int>& chi, int phys, int j) const {
+        long long s = 0;
+        for (int c = 0; c < j; ++c) s += (long long)chi[c] * phys * chi[c + 1];
+        return s;
+    }
+
+    // ---- workspace layout for a chunk of Bc samples ----
+    void layout(int Bc_, bool want_e, bool want_g) {
+        L = Layout();
+        L.Bc = Bc_;
+        Bc = Bc_;
+        want_eloc = want_e; want_grad = want_g;
+        o_envU.resize(Ly); o_envL.resize(Ly); o_logU.resize(Ly); o_logL.resize(Ly);
+        s_envU.resize(Ly); s_envL.resize(Ly);
+        for (int i = 0; i < Ly; ++i) {
+            s_envU[i] = env_row_size(chiU[i], Dv[i]);
+            o_envU[i] = L.alloc(s_envU[i]);
+            o_logU[i] = L.alloc(1);
+        }
+        const bool need_L = want_e || want_g;
+        for (int i = 0; i < Ly; ++i) {
+            s_envL[i] = env_row_size(chiL[i], Dv[i + 1]);
+            o_envL[i] = (need_L || i == Ly - 1) ? L.alloc(s_envL[i]) : 0;
+            o_logL[i] = (need_L || i == Ly - 1) ? L.alloc(1) : 0;
+        }
+        // truncation buffers (max over every truncation of the plan)
+        s_X.assign(Lx, 1); s_tau.assign(Lx, 1);
+        s_R = 1; s_Y = 1; s_G = 1; s_svd = 0;
+        auto visit = [&](const Trunc& t) {
+            for (int j = 0; j < Lx; ++j) {
+                const long long rows = (long long)t.rho[j] * t.p, cols = t.K[j + 1];
+                s_X[j] = std::max(s_X[j], rows * cols);
+                s_tau[j] = std::max<long long>(s_tau[j], std::min(rows, cols));
+                if (j + 1 < Lx) s_R = std::max(s_R, (long long)t.rho[j + 1] * t.K[j + 1]);
+                s_Y = std::max(s_Y, (long long)t.rho[j] * Dh[j] * t.pin * t.chi[j + 1]);
+                s_G = std::max(s_G, (long long)t.rho[j] * t.tau[j]);
+                const int tin = t.tau[j + 1];
+                const long long mz = rows;
+                size_t sc = (j == 0) ? center0_scratch_doubles((int)mz, tin)
+                                     : svd_scratch_doubles((int)mz, tin, t.p);
+                if (sc * sizeof(double) > lds_cap_bytes()) s_svd = std::max<long long>(s_svd, sc);
+            }
+        };
+        for (int i = 0; i + 1 < Ly; ++i) visit(tU[i]);
+        if (need_L)
+            for (int i = Ly - 1; i >= 1; --i) visit(tL[i]);
+        o_X.resize(Lx); o_tau.resize(Lx);
+        for (int j = 0; j < Lx; ++j) {
+            o_X[j] = L.alloc(s_X[j]);
+            o_tau[j] = L.alloc(s_tau[j]);
+        }
+        o_R[0] = L.alloc(s_R); o_R[1] = L.alloc(s_R);
+        o_Y = L.alloc(s_Y);
+        o_G[0] = L.alloc(s_G); o_G[1] = L.alloc(s_G);
+        o_svd = s_svd ? L.alloc(s_svd) : 0;
+        // single-row partials
+        s_P.assign(Lx + 1, 1);
+        for (int i = 0; i < Ly; ++i)
+            for (int j = 0; j <= Lx; ++j)
+                s_P[j] = std::max(s_P[j], (long long)chiU[i][j] * Dh[j] * chiL[i][j]);
+        o_P.resize(Lx + 1); o_Q.resize(Lx + 1); o_lP.resize(Lx + 1); o_lQ.resize(Lx + 1);
+        for (int j = 0; j <= Lx; ++j) {
+            o_P[j] = L.alloc(s_P[j]);
+            o_Q[j] = (need_L) ? L.alloc(s_P[j]) : 0;
+            o_lP[j] = L.alloc(1);
+            o_lQ[j] = L.alloc(1);
+        }
+        long long sT = 1, sF = 1;
+        for (int i = 0; i < Ly; ++i)
+            for (int j = 0; j < Lx; ++j) {
+                const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
+                const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
+                sT = std::max({sT, h * cl * Du * cu1, cl * cu1 * h1 * Dd, cl * Dd * cu1 * h1,
+                               h * Du * cl * cu1});
+                sF = std::max(sF, cu1 * h1 * cl1);
+            }
+        // two-row partials
+        s_P2.assign(Lx + 1, 1);
+        if (want_e) {
+            for (int i = 0; i + 1 < Ly; ++i)
+                for (int j = 0; j <= Lx; ++j)
+                    s_P2[j] = std::max(s_P2[j], (long long)chiU[i][j] * Dh[j] * Dh[j] * chiL[i + 1][j]);
+            for (int i = 0; i + 1 < Ly; ++i)
+                for (int j = 0; j < Lx; ++j) {
+                    const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j],
+                                    cl1 = chiL[i + 1][j + 1];
+                    const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
+                    sT = std::max({sT, h * h * cl * Du * cu1, h * cl * cu1 * h1 * Dm,
+                                   cl * cu1 * h1 * h1 * Dq, cl * Dq * cu1 * h1 * h1,
+                                   h * Dm * cl * cu1 * h1, h * Du * h * cl * cu1});
+                    sF = std::max(sF, cu1 * h1 * h1 * cl1);
+                    (void)cu;
+                }
+            o_P2.resize(Lx + 1); o_Q2.resize(Lx + 1); o_lP2.resize(Lx + 1); o_lQ2.resize(Lx + 1);
+            for (int j = 0; j <= Lx; ++j) {
+                o_P2[j] = L.alloc(s_P2[j]);
+                o_Q2[j] = L.alloc(s_P2[j]);
+                o_lP2[j] = L.alloc(1);
+                o_lQ2[j] = L.alloc(1);
+            }
+        }
+        s_T = sT; s_F = sF;
+        for (int k = 0; k < 3; ++k) o_T[k] = L.alloc(s_T);
+        o_F = L.alloc(s_F);
+        o_Gf = L.alloc(s_F);
+        o_lnW = L.alloc(1); o_sgW = L.alloc(1);
+        o_lnW2 = L.alloc(1); o_sgW2 = L.alloc(1);
+        o_lnWf = L.alloc(1); o_sgWf = L.alloc(1);
+        o_zero = L.alloc(1);
+        nbonds = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
+        o_ratio = want_e ? L.alloc(nbonds) : 0;
+        o_delta = want_g ? L.alloc((long long)N * D4) : 0;
+        o_flags = L.alloc(1);   // int8 flags in a double-sized slot per sample
+        o_eloc = L.alloc(1);
+        o_acc = L.alloc(0, 8);
+        o_G1 = want_g ? L.alloc(0, 2LL * N * D4) : 0;
+        o_G0 = want_g ? L.alloc(0, 2LL * N * D4) : 0;
+    }
+
+    static size_t lds_cap_bytes();
+
+    double* buf(size_t off) const { return (double*)(ctx->ws + off); }
+    Op op(size_t off, long long per) const { return Op{buf(off), per, per}; }
+    Op ones() const { return Op{ctx->ones, 0, kOnes}; }
+
+    // largest element offset an Idx2 can produce over [0, n) (an upper bound)
+    static long long idx_max(const Idx2& x, int n) {
+        if (n <= 0) return 0;
+        const long long outer = (long long)(n - 1) / x.inner;
+        const long long inner = std::min<long long>(n, x.inner) - 1;
+        return outer * x.s_outer + inner * x.s_inner;
+    }
+    bool bounds_ok(const char* what, const Op& o, long long maxoff, long long slice) {
+        if (maxoff + slice < o.ext) return true;
+        char b[256];
+        snprintf(b, sizeof b, "internal bounds check failed in %s: offset %lld + %lld >= extent %lld",
+                 what, maxoff, slice, o.ext);
+        bounds_msg = b;
+        return false;
+    }
+
+    // ---- launch helpers ----
+    hipError_t gemm(int M, int Nn, int K, Op A, Idx2 am, Idx2 ak, Gather ga, Op B, Idx2 bk, Idx2 bn,
+                    Gather gb, Op C, Idx2 cm, Idx2 cn) {
+        if (!bounds_ok("gemm A", A, idx_max(am, M) + idx_max(ak, K), ga.sel ? ga.slice : 0) ||
+            !bounds_ok("gemm B", B, idx_max(bk, K) + idx_max(bn, Nn), gb.sel ? gb.slice : 0) ||
+            !bounds_ok("gemm C", C, idx_max(cm, M) + idx_max(cn, Nn), 0))
+            return hipErrorInvalidValue;
+        if (dry) return hipSuccess;
+        GemmArgs g;
+        g.M = M; g.N = Nn; g.K = K; g.batch = Bcur;
+        g.am = am; g.ak = ak; g.bk = bk; g.bn = bn; g.cm = cm; g.cn = cn;
+        g.a_bs = A.bs; g.b_bs = B.bs; g.c_bs = C.bs;
+        g.ga = ga; g.gb = gb; g.gc = Gather{nullptr, 0, 0, 0};
+        g.A = A.p; g.B = B.p; g.C = C.p;
+        g.alpha = 1.0; g.beta = 0.0;
+        return launch_gemm(g, ar, ctx->stream);
+    }
+    Gather site_gather(int i, int j, int flip) const {
+        return Gather{Scur + (long long)i * Lx + j, (long long)N, flip, (long long)D4};
+    }
+    Op site_op(int i, int j) const {
+        const long long off = ((long long)(i * Lx + j) * 2) * D4;
+        return Op{const_cast<double*>(Ad) + off, 0, (long long)N * 2 * D4 - off};
+    }
+    Op envU(int i, int j) const {
+        if (i == 0) return ones();
+        return op(o_envU[i], s_envU[i]).at(env_off(chiU[i], Dv[i], j));
+    }
+    Op envL(int i, int j) const {
+        if (i == Ly - 1) return ones();
+        return op(o_envL[i], s_envL[i]).at(env_off(chiL[i], Dv[i + 1], j));
+    }
+    Op logU(int i) const { return op(o_logU[i], 1); }
+    Op logL(int i) const { return op(o_logL[i], 1); }
+
+#define CK(x)                                  \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+// a kernel launch: skipped in a dry run, which only walks the plan and checks bounds
+#define KL(x)                                  \
+    do {                                       \
+        if (!dry) {                            \
+            hipError_t e_ = (x);               \
+            if (e_ != hipSuccess) return e_;   \
+        }                                      \
+    } while (0)
+
+    // One truncation: new env = Trunc(Apply(env, row)), top-down (down) or bottom-up.
+    hipError_t trunc_step(bool down, int row) {
+        const Trunc& t = down ? tU[row] : tL[row];
+        const long long s_in = down ? D2 : 1, s_out = down ? 1 : D2;
+        const int pin = t.pin, p = t.p;
+        for (int j = 0; j < Lx; ++j) {
+            const int chj = t.chi[j], chj1 = t.chi[j + 1], Dl = Dh[j], Dr = Dh[j + 1];
+            const int rho = t.rho[j];
+            Op Rin = (j == 0) ? ones() : op(o_R[(j - 1) & 1], s_R);
+            const long long ldR = t.K[j];
+            Op Ein = down ? envU(row, j) : envL(row, j);
+            Op Y = op(o_Y, s_Y);
+            // Y[(a',l),(u,b)] = sum_a R[a', a*Dl+l] E[a,(u,b)]
+            CK(gemm(rho * Dl, pin * chj1, chj, Rin, I2(Dl, ldR, 1), I1(Dl), Gather{},
+                    Ein, I1((long long)pin * chj1), I1(1), Gather{},
+                    Y, I1((long long)pin * chj1), I1(1)));
+            // X[(a',d),(b,r)] (column-major) = sum_{l,u} Y[a',l,u,b] T[l,u,r,d]
+            const long long rows = (long long)rho * p;
+            Op X = op(o_X[j], s_X[j]);
+            CK(gemm(rho * chj1, Dr * p, Dl * pin, Y, I2(chj1, (long long)Dl * pin * chj1, 1),
+                    I2(pin, (long long)pin * chj1, chj1), Gather{},
+                    site_op(row, j), I2(pin, D3, s_in), I2(p, D, s_out), site_gather(row, j, 0),
+                    X, I2(chj1, p, Dr * rows), I2(p, rows, 1)));
+            if (j + 1 < Lx) {
+                if (rows * t.K[j + 1] > s_X[j] || std::min<long long>(rows, t.K[j + 1]) > s_tau[j] ||
+                    (long long)t.rho[j + 1] * t.K[j + 1] > s_R) {
+                    bounds_msg = "internal bounds check failed in qr";
+                    return hipErrorInvalidValue;
+                }
+                KL(launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R, buf(o_tau[j]),
+                             s_tau[j], Bcur, ctx->stream));
+            }
+        }
+        // right-to-left SVD sweep (bounds of every factorisation buffer checked first)
+        for (int j = 0; j < Lx; ++j) {
+            const long long mz = (long long)t.rho[j] * p;
+            const int tin = t.tau[j + 1];
+            const size_t sc = (j == 0) ? center0_scratch_doubles((int)mz, tin)
+                                       : svd_scratch_doubles((int)mz, tin, p);
+            const bool in_lds = sc * sizeof(double) <= lds_cap_bytes();
+            const long long rin = (j + 1 < Lx) ? t.rho[j + 1] : mz;     // rows of G / reflectors
+            bool ok = in_lds || (long long)sc <= s_svd;
+            ok = ok && mz * (j + 1 < Lx ? t.K[j + 1] : 1) <= s_X[j];
+            ok = ok && (j + 1 == Lx || (rin <= s_tau[j] && rin * tin <= s_G));
+            ok = ok && (long long)t.rho[j] * t.tau[j] <= s_G;
+            const std::vector<int>& chn = down ? chiU[row + 1] : chiL[row - 1];
+            ok = ok && chn[j] == t.tau[j] && chn[j + 1] == t.tau[j + 1];
+            if (!ok) {
+                bounds_msg = "internal bounds check failed in svd";
+                return hipErrorInvalidValue;
+            }
+        }
+        int cur = 0;
+        {
+            const int j = Lx - 1;
+            Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
+            const int mz = t.rho[j] * p;
+            KL(launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
+                          Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
+                          ctx->stream));
+        }
+        for (int j = Lx - 2; j >= 1; --j) {
+            Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
+            const int mz = t.rho[j] * p;
+            KL(launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
+                          t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]), s_G,
+                          buf(o_svd), s_svd, flags(), Bcur, ctx->stream));
+            cur ^= 1;
+        }
+        {
+            Op Eout = down ? envU(row + 1, 0) : envL(row - 1, 0);
+            Op lin = down ? logU(row) : logL(row);
+            Op lout = down ? logU(row + 1) : logL(row - 1);
+            KL(launch_center0(buf(o_X[0]), s_X[0], buf(o_tau[0]), s_tau[0], buf(o_G[cur]), s_G, p,
+                              t.rho[1], t.tau[1], Eout.p, Eout.bs, lin.p, lout.p, buf(o_svd), s_svd,
+                              Bcur, ctx->stream));
+        }
+        return hipSuccess;
+    }
+
+    // P_{j+1} = step(P_j) of the row-i sandwich <U_i| row i |L_i>
+    hipError_t row_fwd(int i, int j, Op P, int flip, Op Pout) {
+        const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
+        const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
+        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        CK(gemm((int)(h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * cl), Gather{},
+                envU(i, j), I1(Du * cu1), I1(1), Gather{}, T1, I1(Du * cu1), I1(1)));
+        CK(gemm((int)(cl * cu1), (int)(h1 * Dd), (int)(h * Du), T1, I2((int)cu1, Du * cu1, 1),
+                I2((int)Du, cl * Du * cu1, cu1), Gather{}, site_op(i, j), I2((int)Du, D3, D2),
+                I2((int)Dd, D, 1), site_gather(i, j, flip), T2, I1(h1 * Dd), I1(1)));
+        CK(gemm((int)(cu1 * h1), (int)cl1, (int)(cl * Dd), T2, I1(Dd), I2((int)Dd, cu1 * h1 * Dd, 1),
+                Gather{}, envL(i, j), I1(cl1), I1(1), Gather{}, Pout, I1(cl1), I1(1)));
+        return hipSuccess;
+    }
+
+    // Q_j = step(Q_{j+1}) from the right
+    hipError_t row_bwd(int i, int j, Op Q, int flip, Op Qout) {
+        const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
+        const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
+        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        CK(gemm((int)(cl * Dd), (int)(cu1 * h1), (int)cl1, envL(i, j), I1(cl1), I1(1), Gather{}, Q,
+                I1(1), I1(cl1), Gather{}, T1, I1(cu1 * h1), I1(1)));
+        CK(gemm((int)(h * Du), (int)(cl * cu1), (int)(h1 * Dd), site_op(i, j), I2((int)Du, D3, D2),
+                I2((int)Dd, D, 1), site_gather(i, j, flip), T1, I2((int)Dd, 1, cu1 * h1),
+                I2((int)cu1, Dd * cu1 * h1, h1), Gather{}, T2, I1(cl * cu1), I1(1)));
+        CK(gemm((int)cu, (int)(h * cl), (int)(Du * cu1), envU(i, j), I1(Du * cu1), I1(1), Gather{},
+                T2, I2((int)cu1, cl * cu1, 1), I2((int)cl, Du * cl * cu1, cu1), Gather{}, Qout,
+                I1(h * cl), I1(1)));
+        return hipSuccess;
+    }
+
+    // two-row sandwich <U_i| rows i, i+1 |L_{i+1}>, forward step
+    hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout) {
+        const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
+        const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
+        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T), T3 = op(o_T[2], s_T);
+        CK(gemm((int)(h * h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * h * cl), Gather{},
+                envU(i, j), I1(Du * cu1), I1(1), Gather{}, T1, I1(Du * cu1), I1(1)));
+        CK(gemm((int)(h * cl * cu1), (int)(h1 * Dm), (int)(h * Du), T1, I2((int)cu1, Du * cu1, 1),
+                I2((int)Du, h * cl * Du * cu1, cu1), Gather{}, site_op(i, j), I2((int)Du, D3, D2),
+                I2((int)Dm, D, 1), site_gather(i, j, f1), T2, I1(h1 * Dm), I1(1)));
+        CK(gemm((int)(cl * cu1 * h1), (int)(h1 * Dq), (int)(h * Dm), T2, I1(Dm),
+                I2((int)Dm, cl * cu1 * h1 * Dm, 1), Gather{}, site_op(i + 1, j), I2((int)Dm, D3, D2),
+                I2((int)Dq, D, 1), site_gather(i + 1, j, f2), T3, I1(h1 * Dq), I1(1)));
+        CK(gemm((int)(cu1 * h1 * h1), (int)cl1, (int)(cl * Dq), T3, I1(Dq),
+                I2((int)Dq, cu1 * h1 * h1 * Dq, 1), Gather{}, envL(i + 1, j), I1(cl1), I1(1),
+                Gather{}, Pout, I1(cl1), I1(1)));
+        return hipSuccess;
+    }
+
+    hipError_t pair_bwd(int i, int j, Op Q, int f1, int f2, Op Qout) {
+        const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
+        const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
+        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T), T3 = op(o_T[2], s_T);
+        CK(gemm((int)(cl * Dq), (int)(cu1 * h1 * h1), (int)cl1, envL(i + 1, j), I1(cl1), I1(1),
+                Gather{}, Q, I1(1), I1(cl1), Gather{}, T1, I1(cu1 * h1 * h1), I1(1)));
+        CK(gemm((int)(h * Dm), (int)(cl * cu1 * h1), (int)(h1 * Dq), site_op(i + 1, j),
+                I2((int)Dm, D3, D2), I2((int)Dq, D, 1), site_gather(i + 1, j, f2), T1,
+                I2((int)Dq, 1, cu1 * h1 * h1), I2((int)(cu1 * h1), Dq * cu1 * h1 * h1, h1), Gather{},
+                T2, I1(cl * cu1 * h1), I1(1)));
+        CK(gemm((int)(h * Du), (int)(h * cl * cu1), (int)(h1 * Dm), site_op(i, j), I2((int)Du, D3, D2),
+                I2((int)Dm, D, 1), site_gather(i, j, f1), T2, I2((int)Dm, 1, cl * cu1 * h1),
+                I2((int)(cl * cu1), Dm * cl * cu1 * h1, h1), Gather{}, T3, I1(h * cl * cu1), I1(1)));
+        CK(gemm((int)cu, (int)(h * h * cl), (int)(Du * cu1), envU(i, j), I1(Du * cu1), I1(1), Gather{},
+                T3, I2((int)cu1, h * cl * cu1, 1), I2((int)(h * cl), Du * h * cl * cu1, cu1), Gather{},
+                Qout, I1(h * h * cl), I1(1)));
+        return hipSuccess;
+    }
+
+    // B_m = dW_i/dT_m (unnormalised), into the per-sample Delta buffer at site m
+    hipError_t site_env(int i, int j) {
+        const long long cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
+        const long long cu = chiU[i][j];
+        const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
+        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
+        Op Q = (j + 1 == Lx) ? ones() : op(o_Q[j + 1], s_P[j + 1]);
+        CK(gemm((int)(h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * cl), Gather{},
+                envU(i, j), I1(Du * cu1), I1(1), Gather{}, T1, I1(Du * cu1), I1(1)));
+        CK(gemm((int)(cl * Dd), (int)(cu1 * h1), (int)cl1, envL(i, j), I1(cl1), I1(1), Gather{}, Q,
+                I1(1), I1(cl1), Gather{}, T2, I1(cu1 * h1), I1(1)));
+        Op Dl = op(o_delta, (long long)N * D4).at((long long)(i * Lx + j) * D4);
+        CK(gemm((int)(h * Du), (int)(h1 * Dd), (int)(cl * cu1), T1, I2((int)Du, cl * Du * cu1, cu1),
+                I2((int)cu1, Du * cu1, 1), Gather{}, T2, I2((int)cu1, Dd * cu1 * h1, h1),
+                I2((int)Dd, 1, cu1 * h1), Gather{}, Dl, I2((int)Du, D3, D2), I2((int)Dd, D, 1)));
+        if (dry) return hipSuccess;
+        return launch_grad_site(Dl.p, Dl.bs, Ad, Scur, i * Lx + j, N, D, (int)h, (int)Du, (int)h1,
+                                (int)Dd, Bcur, ctx->stream);
+    }
+
+    int8_t* flags() const { return (int8_t*)buf(o_flags); }
+
+    // ---- one chunk ----
+    hipError_t run_chunk(const int8_t* S, int Bn, double* log_abs, int8_t* sign, double* e_loc,
+                         int grad_mode, const double* weights, double* out, int8_t* flags_out,
+                         bool first_chunk) {
+        Bcur = Bn;
+        Scur = S;
+        hipStream_t st = ctx->stream;
+        KL(launch_check_configs(S, N, Bn, flags(), st));
+        KL(launch_fill(buf(o_zero), Bn, 0.0, st));
+        KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
+        for (int i = 0; i + 1 < Ly; ++i) CK(trunc_step(true, i));
+        const bool need_L = want_eloc || want_grad;
+        if (need_L) {
+            KL(launch_fill(buf(o_logL[Ly - 1]), Bn, 0.0, st));
+            for (int i = Ly - 1; i >= 1; --i) CK(trunc_step(false, i));
+        }
+        if (want_grad) KL(launch_fill(buf(o_delta), (long long)Bn * N * D4, 0.0, st));
+        const int nH = Ly * (Lx - 1), nV = (Ly - 1) * Lx, nD = (Ly - 1) * (Lx - 1);
+        const int row_first = need_L ? 0 : Ly - 1;
+        for (int i = row_first; i < Ly; ++i) {
+            // forward partials of row i
+            KL(launch_fill(buf(o_lP[0]), Bn, 0.0, st));
+            for (int j = 0; j < Lx; ++j) {
+                Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
+                Op Po = op(o_P[j + 1], s_P[j + 1]);
+                CK(row_fwd(i, j, P, 0, Po));
+                KL(launch_rescale(Po.p, Po.bs, (int)(chiU[i][j + 1] * Dh[j + 1] * chiL[i][j + 1]),
+                                  buf(o_lP[j]), buf(o_lP[j + 1]), Bn, st));
+            }
+            KL(launch_sandwich_value(buf(o_P[Lx]), s_P[Lx], buf(o_lP[Lx]), buf(o_lnW), buf(o_sgW), Bn, st));
+            if (i == Ly - 1) {
+                KL(launch_amp_out(buf(o_logU[Ly - 1]), buf(o_lnW), buf(o_sgW), flags(), log_abs,
+                                  sign, Bn, st));
+            }
+            if (!need_L) break;
+            // backward partials
+            KL(launch_fill(buf(o_lQ[Lx]), Bn, 0.0, st));
+            for (int j = Lx - 1; j >= 1; --j) {
+                Op Q = (j + 1 == Lx) ? ones() : op(o_Q[j + 1], s_P[j + 1]);
+                Op Qo = op(o_Q[j], s_P[j]);
+                CK(row_bwd(i, j, Q, 0, Qo));
+                KL(launch_rescale(Qo.p, Qo.bs, (int)(chiU[i][j] * Dh[j] * chiL[i][j]),
+                                  buf(o_lQ[j + 1]), buf(o_lQ[j]), Bn, st));
+            }
+            if (want_eloc) {
+                for (int j = 0; j + 1 < Lx; ++j) {
+                    Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
+                    Op Q = (j + 2 == Lx) ? ones() : op(o_Q[j + 2], s_P[j + 2]);
+                    Op F = op(o_F, s_F), G = op(o_Gf, s_F);
+                    CK(row_fwd(i, j, P, 1, F));
+                    CK(row_bwd(i, j + 1, Q, 1, G));
+                    const int n = (int)(chiU[i][j + 1] * Dh[j + 1] * chiL[i][j + 1]);
+                    KL(launch_ratio(F.p, F.bs, G.p, G.bs, n, buf(o_lP[j]), buf(o_lQ[j + 2]),
+                                    buf(o_lnW), buf(o_sgW), buf(o_ratio), nbonds,
+                                    i * (Lx - 1) + j, Bn, st));
+                }
+            }
+            if (want_grad)
+                for (int j = 0; j < Lx; ++j) CK(site_env(i, j));
+        }
+        if (want_eloc) {
+            for (int i = 0; i + 1 < Ly; ++i) {
+                KL(launch_fill(buf(o_lP2[0]), Bn, 0.0, st));
+                for (int j = 0; j < Lx; ++j) {
+                    Op P = (j == 0) ? ones() : op(o_P2[j], s_P2[j]);
+                    Op Po = op(o_P2[j + 1], s_P2[j + 1]);
+                    CK(pair_fwd(i, j, P, 0, 0, Po));
+                    KL(launch_rescale(Po.p, Po.bs,
+                                      (int)(chiU[i][j + 1] * Dh[j + 1] * Dh[j + 1] * chiL[i + 1][j + 1]),
+                                      buf(o_lP2[j]), buf(o_lP2[j + 1]), Bn, st));
+                }
+                KL(launch_sandwich_value(buf(o_P2[Lx]), s_P2[Lx], buf(o_lP2[Lx]), buf(o_lnW2),
+                                         buf(o_sgW2), Bn, st));
+                KL(launch_fill(buf(o_lQ2[Lx]), Bn, 0.0, st));
+                for (int j = Lx - 1; j >= 1; --j) {
+                    Op Q = (j + 1 == Lx) ? ones() : op(o_Q2[j + 1], s_P2[j + 1]);
+                    Op Qo = op(o_Q2[j], s_P2[j]);
+                    CK(pair_bwd(i, j, Q, 0, 0, Qo));
+                    KL(launch_rescale(Qo.p, Qo.bs,
+                                      (int)(chiU[i][j] * Dh[j] * Dh[j] * chiL[i + 1][j]),
+                                      buf(o_lQ2[j + 1]), buf(o_lQ2[j]), Bn, st));
+                }
+                for (int j = 0; j < Lx; ++j) {
+                    Op P = (j == 0) ? ones() : op(o_P2[j], s_P2[j]);
+                    Op F = op(o_F, s_F), G = op(o_Gf, s_F);
+                    const int n1 = (int)(chiU[i][j + 1] * Dh[j + 1] * Dh[j + 1] * chiL[i + 1][j + 1]);
+                    // vertical bond (i,j)-(i+1,j)
+                    Op Q1 = (j + 1 == Lx) ? ones() : op(o_Q2[j + 1], s_P2[j + 1]);
+                    CK(pair_fwd(i, j, P, 1, 1, F));
+                    KL(launch_ratio(F.p, F.bs, Q1.p, Q1.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 1]),
+                                    buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds, nH + i * Lx + j,
+                                    Bn, st));
+                    if (j + 1 < Lx) {
+                        Op Q2 = (j + 2 == Lx) ? ones() : op(o_Q2[j + 2], s_P2[j + 2]);
+                        // diagonal (i,j)-(i+1,j+1)
+                        CK(pair_fwd(i, j, P, 1, 0, F));
+                        CK(pair_bwd(i, j + 1, Q2, 0, 1, G));
+                        KL(launch_ratio(F.p, F.bs, G.p, G.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 2]),
+                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds,
+                                        nH + nV + i * (Lx - 1) + j, Bn, st));
+                        // anti-diagonal (i,j+1)-(i+1,j)
+                        CK(pair_fwd(i, j, P, 0, 1, F));
+                        CK(pair_bwd(i, j + 1, Q2, 1, 0, G));
+                        KL(launch_ratio(F.p, F.bs, G.p, G.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 2]),
+                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds,
+                                        nH + nV + nD + i * (Lx - 1) + j, Bn, st));
+                    }
+                }
+            }
+            ElocArgs ea;
+            ea.S = S; ea.Lx = Lx; ea.Ly = Ly; ea.J1 = lat.J1; ea.J2 = lat.J2;
+            ea.ratio = buf(o_ratio); ea.nbonds = nbonds; ea.flags = flags();
+            ea.e_loc = e_loc ? e_loc : buf(o_eloc); ea.batch = Bn;
+            KL(launch_eloc(ea, st));
+        }
+        KL(launch_nan_flagged(flags(), log_abs, sign, want_eloc ? (e_loc ? e_loc : buf(o_eloc)) : nullptr,
+                              Bn, st));
+        if (want_grad) {
+            const double* eptr = e_loc ? e_loc : buf(o_eloc);
+            if (grad_mode == 1) {
+                KL(launch_grad_store(buf(o_delta), S, N, (int)D4, flags(), out, Bn, st));
+            } else if (grad_mode == 2) {
+                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), weights, 0, !first_chunk, out,
+                                      Bn, st));
+            } else if (grad_mode == 3) {
+                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), eptr, 1, !first_chunk,
+                                      buf(o_G1), Bn, st));
+                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), nullptr, 2, !first_chunk,
+                                      buf(o_G0), Bn, st));
+                KL(launch_energy_sums(eptr, flags(), Bn, buf(o_acc), !first_chunk, st));
+            }
+        }
+        if (flags_out) KL(hipMemcpyAsync(flags_out, flags(), Bn, hipMemcpyDeviceToDevice, st));
+        return hipSuccess;
+    }
+
+    peps_ctx* ctx;
+    peps_lattice lat;
+    peps_precision prec;
+    Arith ar;
+    int Lx, Ly, D, Dc, N;
+    long long D2, D3, D4;
+    std::vector<int> Dh, Dv;
+    std::vector<std::vector<int>> chiU, chiL;
+    std::vector<Trunc> tU, tL;
+    Layout L;
+    int Bc = 0, Bcur = 0, nbonds = 0;
+    std::string bounds_msg;
+    bool dry = false;
+    bool want_eloc = false, want_grad = false;
+    const double* Ad = nullptr;
+    const int8_t* Scur = nullptr;
+    std::vector<size_t> o_envU, o_envL, o_logU, o_logL, o_X, o_tau, o_P, o_Q, o_lP, o_lQ, o_P2, o_Q2,
+        o_lP2, o_lQ2;
+    std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2;
+    size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
+        o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0;
+    long long s_R, s_Y, s_G, s_svd, s_T, s_F;
+};
+
+size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create
+size_t Runner::lds_cap_bytes() { return g_lds_cap - 1024; }
+
+}  // namespace
+
+void set_lds_cap(size_t bytes) { g_lds_cap = bytes; }
+size_t get_lds_cap() { return g_lds_cap; }
+
+}  // namespace peps
+
+using namespace peps;
+
+static peps_status fail(peps_ctx* c, peps_status s, const char* fmt, ...) {
+    char b[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(b, sizeof b, fmt, ap);
+    va_end(ap);
+    if (c) c->err = b;
+    return s;
+}
+
+static peps_status check_lat(peps_ctx* c, const peps_lattice* lat) {
+    if (!lat) return fail(c, PEPS_ERR_INVALID_ARG, "lattice is NULL");
+    if (lat->Lx < 2 || lat->Ly < 2) return fail(c, PEPS_ERR_INVALID_ARG, "Lx and Ly must be >= 2");
+    if (lat->D < 1 || lat->Dc < 1) return fail(c, PEPS_ERR_INVALID_ARG, "D and Dc must be >= 1");
+    if (lat->Lx > 4096 || lat->Ly > 4096) return fail(c, PEPS_ERR_UNSUPPORTED, "lattice too large");
+    if (lat->D > 16) return fail(c, PEPS_ERR_UNSUPPORTED, "D > 16 is not supported");
+    return PEPS_OK;
+}
+
+extern "C" {
+
+peps_status peps_create(peps_ctx** ctx, int device) {
+    if (!ctx) return PEPS_ERR_INVALID_ARG;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PEPS_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return PEPS_ERR_HIP;
+    peps_ctx* c = new peps_ctx();
+    c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        lds > 0)
+        set_lds_cap((size_t)lds);
+    if (hipMalloc(&c->ones, kOnes * sizeof(double)) != hipSuccess) {
+        delete c;
+        return PEPS_ERR_OOM;
+    }
+    launch_fill(c->ones, kOnes, 1.0, nullptr);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        hipFree(c->ones);
+        delete c;
+        return PEPS_ERR_HIP;
+    }
+    *ctx = c;
+    return PEPS_OK;
+}
+
+peps_status peps_destroy(peps_ctx* c) {
+    if (!c) return PEPS_OK;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (c->ws) hipFree(c->ws);
+    if (c->ones) hipFree(c->ones);
+    delete c;
+    return PEPS_OK;
+}
+
+peps_status peps_set_stream(peps_ctx* c, void* s) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)s;
+    return PEPS_OK;
+}
+
+peps_status peps_set_workspace_limit(peps_ctx* c, size_t bytes) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->ws_limit = bytes;
+    return PEPS_OK;
+}
+
+const char* peps_last_error(const peps_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+static size_t default_limit(peps_ctx* c) {
+    if (c->ws_limit) return c->ws_limit;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return (size_t)1 << 30;
+    return (fr + c->ws_bytes) / 4;
+}
+
+peps_status peps_workspace_query(peps_ctx* c, const peps_lattice* lat, int64_t batch,
+                                 peps_precision prec, size_t* bytes) {
+    if (!c || !bytes) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    peps_status s = check_lat(c, lat);
+    if (s != PEPS_OK) return s;
+    Runner r(c, *lat, prec);
+    r.layout((int)std::max<int64_t>(batch, 1), true, true);
+    *bytes = r.L.bytes;
+    return PEPS_OK;
+}
+
+static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                           const int8_t* S, int64_t batch, bool want_e, int grad_mode,
+                           const double* weights, double* log_abs, int8_t* sign, double* e_loc,
+                           double* out, int8_t* flags) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_lat(c, lat);
+    if (st != PEPS_OK) return st;
+    if (prec < PEPS_PREC_F64 || prec > PEPS_PREC_BF16) return fail(c, PEPS_ERR_INVALID_ARG, "bad precision");
+    if (batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
+    if (grad_mode < 0 || grad_mode > 3) return fail(c, PEPS_ERR_INVALID_ARG, "bad grad_mode");
+    if (batch == 0) return PEPS_OK;
+    if (!A || !S) return fail(c, PEPS_ERR_INVALID_ARG, "A or S is NULL");
+    if (grad_mode && !out) return fail(c, PEPS_ERR_INVALID_ARG, "gradient requested but out is NULL");
+    if (grad_mode == 2 && !weights) return fail(c, PEPS_ERR_INVALID_ARG, "weights is NULL");
+    if (grad_mode == 3) want_e = true;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
+    const bool want_g = grad_mode != 0;
+    Runner r(c, *lat, prec);
+    // chunk size from the workspace limit
+    r.layout(1, want_e, want_g);
+    const size_t per1 = r.L.bytes;
+    r.layout(2, want_e, want_g);
+    const size_t per = r.L.bytes - per1;
+    const size_t fixed = per1 > per ? per1 - per : 0;
+    const size_t limit = default_limit(c);
+    if (per + fixed > limit) return fail(c, PEPS_ERR_OOM, "one sample needs %zu bytes > limit %zu", per + fixed, limit);
+    int64_t Bc = std::min<int64_t>(batch, (int64_t)((limit - fixed) / per));
+    Bc = std::max<int64_t>(1, std::min<int64_t>(Bc, 1 << 20));
+    r.layout((int)Bc, want_e, want_g);
+    if (r.L.bytes > c->ws_bytes) {
+        if (c->ws) {
+            if (c->stream) hipStreamSynchronize(c->stream);
+            else hipDeviceSynchronize();
+            hipFree(c->ws);
+            c->ws = nullptr;
+            c->ws_bytes = 0;
+        }
+        if (hipMalloc(&c->ws, r.L.bytes) != hipSuccess) {
+            c->ws = nullptr;
+            return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", r.L.bytes);
+        }
+        c->ws_bytes = r.L.bytes;
+    }
+    r.Ad = A;
+    const int N = lat->Lx * lat->Ly;
+    const long long D4 = (long long)lat->D * lat->D * lat->D * lat->D;
+    for (int64_t b0 = 0; b0 < batch; b0 += Bc) {
+        const int Bn = (int)std::min<int64_t>(Bc, batch - b0);
+        hipError_t e = r.run_chunk(S + b0 * N, Bn, log_abs ? log_abs + b0 : nullptr,
+                                   sign ? sign + b0 : nullptr, e_loc ? e_loc + b0 : nullptr, grad_mode,
+                                   weights ? weights + b0 : nullptr,
+                                   (grad_mode == 1) ? out + b0 * N * 2 * D4 : out,
+                                   flags ? flags + b0 : nullptr, b0 == 0);
+        if (e != hipSuccess)
+            return fail(c, PEPS_ERR_HIP, "HIP error: %s %s", hipGetErrorString(e), r.bounds_msg.c_str());
+    }
+    if (grad_mode == 3) {
+        hipError_t e = launch_energy_grad_combine(r.buf(r.o_G1), r.buf(r.o_G0), r.buf(r.o_acc),
+                                                  (long long)N * 2 * D4, out, c->stream);
+        if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    }
+    return PEPS_OK;
+}
+
+peps_status peps_plan_check(const peps_lattice* lat, int64_t batch, int32_t grad_mode,
+                            int32_t want_eloc, size_t* bytes) {
+    peps_status st = check_lat(nullptr, lat);
+    if (st != PEPS_OK) return st;
+    if (batch < 1 || grad_mode < 0 || grad_mode > 3) return PEPS_ERR_INVALID_ARG;
+    peps_ctx dummy;
+    Runner r(&dummy, *lat, PEPS_PREC_F64);
+    r.dry = true;
+    const bool want_e = want_eloc || grad_mode == 3;
+    r.layout((int)std::min<int64_t>(batch, 1 << 20), want_e, grad_mode != 0);
+    if (bytes) *bytes = r.L.bytes;
+    static const double a0 = 0.0;
+    static const int8_t s0 = 0;
+    r.Ad = &a0;
+    double* dptr = (double*)&a0;
+    const int64_t Bn = std::min<int64_t>(batch, 1 << 20);
+    hipError_t e = r.run_chunk(&s0, (int)Bn, dptr, (int8_t*)&s0, want_e ? dptr : nullptr, grad_mode,
+                               dptr, dptr, nullptr, true);
+    return e == hipSuccess ? PEPS_OK : PEPS_ERR_INVALID_ARG;
+}
+
+peps_status peps_log_amplitude(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
+                               const double* A, const int8_t* S, int64_t batch, double* log_abs,
+                               int8_t* sign, int8_t* flags) {
+    return run_all(c, lat, prec, A, S, batch, false, 0, nullptr, log_abs, sign, nullptr, nullptr, flags);
+}
+
+peps_status peps_local_energy(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
+                              const double* A, const int8_t* S, int64_t batch, double* log_abs,
+                              int8_t* sign, double* e_loc, int8_t* flags) {
+    return run_all(c, lat, prec, A, S, batch, true, 0, nullptr, log_abs, sign, e_loc, nullptr, flags);
+}
+
+peps_status peps_log_derivative(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
+                                const double* A, const int8_t* S, int64_t batch,
+                                const double* weights, double* out, double* log_abs, int8_t* sign,
+                                int8_t* flags) {
+    if (!out) return fail(c, PEPS_ERR_INVALID_ARG, "out is NULL");
+    return run_all(c, lat, prec, A, S, batch, false, weights ? 2 : 1, weights, log_abs, sign, nullptr,
+                   out, flags);
+}
+
+peps_status peps_evaluate(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                          const int8_t* S, int64_t batch, int32_t grad_mode, const double* weights,
+                          double* log_abs, int8_t* sign, double* e_loc, double* out, int8_t* flags) {
+    return run_all(c, lat, prec, A, S, batch, e_loc != nullptr, grad_mode, weights, log_abs, sign, e_loc,
+                   out, flags);
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+"""ctypes binding of libpeps_hip.so (argument marshalling only) and the autograd wrapper.
+
+Every computation runs in the HIP library; torch provides device memory and the
+stream.  There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpeps_hip.so")
+
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP error",
+          4: "unsupported", 5: "numerical failure"}
+
+
+class PepsError(RuntimeError):
+    pass
+
+
+class _Lattice(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("Dc", ctypes.c_int32), ("J1", ctypes.c_double), ("J2", ctypes.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+_ctx = {}
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "peps_create": [ctypes.POINTER(_P), ctypes.c_int],
+    "peps_destroy": [_P],
+    "peps_set_stream": [_P, _P],
+    "peps_set_workspace_limit": [_P, ctypes.c_size_t],
+    "peps_workspace_query": [_P, ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_size_t)],
+    "peps_log_amplitude": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                           _P, _P, _P],
+    "peps_local_energy": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                          _P, _P, _P, _P],
+    "peps_log_derivative": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                            _P, _P, _P, _P, _P],
+    "peps_plan_check": [ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                        ctypes.POINTER(ctypes.c_size_t)],
+    "peps_evaluate": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                      ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise PepsError(f"{path} not found: build it with python -m paper_1806_03761_amd.build")
+            lib = ctypes.CDLL(path)
+            for name, args in _SIGS.items():
+                fn = getattr(lib, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+            lib.peps_last_error.argtypes = [_P]
+            lib.peps_last_error.restype = ctypes.c_char_p
+            _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS) + ["peps_last_error"]
+
+
+def _context(device: int):
+    lib = load_library()
+    with _lock:
+        c = _ctx.get(device)
+        if c is None:
+            h = _P()
+            st = lib.peps_create(ctypes.byref(h), device)
+            if st != 0:
+                raise PepsError(f"peps_create({device}) failed: {STATUS.get(st, st)}")
+            c = _ctx[device] = h
+    return lib, c
+
+
+def _check(lib, ctx, st, what):
+    if st != 0:
+        msg = lib.peps_last_error(ctx)
+        raise PepsError(f"{what}: {STATUS.get(st, st)}: {msg.decode() if msg else ''}")
+
+
+def _lat(lat) -> _Lattice:
+    return _Lattice(int(lat.Lx), int(lat.Ly), int(lat.D), int(lat.Dc), float(lat.J1), float(lat.J2))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _prep(A, S, lat):
+    if not (A.is_cuda and S.is_cuda):
+        raise PepsError("A and S must be device tensors")
+    if A.dtype != torch.float64 or S.dtype != torch.int8:
+        raise PepsError("A must be float64 and S int8")
+    N, D = lat.Lx * lat.Ly, lat.D
+    if tuple(A.shape) != (N, 2, D, D, D, D):
+        raise PepsError(f"A has shape {tuple(A.shape)}, expected {(N, 2, D, D, D, D)}")
+    if S.dim() != 2 or S.shape[1] != N:
+        raise PepsError(f"S has shape {tuple(S.shape)}, expected (batch, {N})")
+    A = A.contiguous()
+    S = S.contiguous()
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    lib, ctx = _context(dev)
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    lib.peps_set_stream(ctx, ctypes.c_void_p(stream))
+    return lib, ctx, A, S
+
+
+def plan_check(lat, batch: int, grad_mode: int = 3, want_eloc: bool = True) -> int:
+    """Host-only dry run of the launch sequence with bounds checks (no GPU needed).
+    Returns the workspace bytes of one chunk; raises if a bounds check fails."""
+    lib = load_library()
+    out = ctypes.c_size_t()
+    st = lib.peps_plan_check(ctypes.byref(_lat(lat)), int(batch), int(grad_mode), int(bool(want_eloc)),
+                             ctypes.byref(out))
+    if st != 0:
+        raise PepsError(f"peps_plan_check failed: {STATUS.get(st, st)}")
+    return int(out.value)
+
+
+def set_workspace_limit(nbytes: int, device: int = 0):
+    lib, ctx = _context(device)
+    lib.peps_set_workspace_limit(ctx, int(nbytes))
+
+
+def workspace_bytes(lat, batch: int, prec: str = "f64", device: int = 0) -> int:
+    lib, ctx = _context(device)
+    out = ctypes.c_size_t()
+    st = lib.peps_workspace_query(ctx, ctypes.byref(_lat(lat)), int(batch), PREC[prec], ctypes.byref(out))
+    _check(lib, ctx, st, "peps_workspace_query")
+    return int(out.value)
+
+
+def log_amplitude(A, S, lat, prec: str = "f64"):
+    """(log_abs float64 [B], sign int8 [B], flags int8 [B]) on A's device."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    B = S.shape[0]
+    la = torch.empty(B, dtype=torch.float64, device=A.device)
+    sg = torch.empty(B, dtype=torch.int8, device=A.device)
+    fl = torch.empty(B, dtype=torch.int8, device=A.device)
+    st = lib.peps_log_amplitude(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B,
+                                _ptr(la), _ptr(sg), _ptr(fl))
+    _check(lib, ctx, st, "peps_log_amplitude")
+    return la, sg, fl
+
+
+def local_energy(A, S, lat, prec: str = "f64"):
+    """(log_abs, sign, e_loc float64 [B], flags)."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    B = S.shape[0]
+    la = torch.empty(B, dtype=torch.float64, device=A.device)
+    sg = torch.empty(B, dtype=torch.int8, device=A.device)
+    e = torch.empty(B, dtype=torch.float64, device=A.device)
+    fl = torch.empty(B, dtype=torch.int8, device=A.device)
+    st = lib.peps_local_energy(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B,
+                               _ptr(la), _ptr(sg), _ptr(e), _ptr(fl))
+    _check(lib, ctx, st, "peps_local_energy")
+    return la, sg, e, fl
+
+
+def log_derivative(A, S, lat, prec: str = "f64", weights=None):
+    """Per-sample Delta [B][N][2][D^4] (weights None) or sum_b weights[b] Delta_b [N][2][D^4]."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    B = S.shape[0]
+    N, D4 = lat.Lx * lat.Ly, lat.D ** 4
+    if weights is not None:
+        weights = weights.to(device=A.device, dtype=torch.float64).contiguous()
+        if weights.shape != (B,):
+            raise PepsError("weights must have shape (batch,)")
+        out = torch.empty((N, 2, D4), dtype=torch.float64, device=A.device)
+    else:
+        out = torch.empty((B, N, 2, D4), dtype=torch.float64, device=A.device)
+    la = torch.empty(B, dtype=torch.float64, device=A.device)
+    sg = torch.empty(B, dtype=torch.int8, device=A.device)
+    fl = torch.empty(B, dtype=torch.int8, device=A.device)
+    st = lib.peps_log_derivative(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B,
+                                 _ptr(weights), _ptr(out), _ptr(la), _ptr(sg), _ptr(fl))
+    _check(lib, ctx, st, "peps_log_derivative")
+    return out, la, sg, fl
+
+
+def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out=None):
+    """Whole path from one set of environments: (log_abs, sign, e_loc, grad, flags).
+    grad_mode 0 none, 1 per-sample, 2 weighted sum, 3 dE/dA of the energy estimator."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    B = S.shape[0]
+    N, D4 = lat.Lx * lat.Ly, lat.D ** 4
+    dev = A.device
+    la = torch.empty(B, dtype=torch.float64, device=dev)
+    sg = torch.empty(B, dtype=torch.int8, device=dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    fl = torch.empty(B, dtype=torch.int8, device=dev)
+    if grad_mode and out is None:
+        shape = (B, N, 2, D4) if grad_mode == 1 else (N, 2, D4)
+        out = torch.empty(shape, dtype=torch.float64, device=dev)
+    if weights is not None:
+        weights = weights.to(device=dev, dtype=torch.float64).contiguous()
+    st = lib.peps_evaluate(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, grad_mode,
+                           _ptr(weights), _ptr(la), _ptr(sg), _ptr(e), _ptr(out), _ptr(fl))
+    _check(lib, ctx, st, "peps_evaluate")
+    return la, sg, e, out, fl
+
+
+class PepsLogAmp(torch.autograd.Function):
+    """ln|W(S)| as a differentiable function of A; backward calls peps_log_derivative
+    with the incoming gradient as per-sample weights (frozen environments)."""
+
+    @staticmethod
+    def forward(ctx, A, S, lat, prec="f64"):
+        la, sg, fl = log_amplitude(A, S, lat, prec)
+        ctx.save_for_backward(A, S)
+        ctx.lat = lat
+        ctx.prec = prec
+        ctx.mark_non_differentiable(sg, fl)
+        return la, sg, fl
+
+    @staticmethod
+    def backward(ctx, g, _gs=None, _gf=None):
+        A, S = ctx.saved_tensors
+        lat = ctx.lat
+        gA = None
+        if ctx.needs_input_grad[0]:
+            out, _, _, _ = log_derivative(A, S, lat, ctx.prec, weights=g)
+            gA = out.reshape(A.shape)
+        return gA, None, None, None

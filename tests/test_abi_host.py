@@ -1,0 +1,49 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every symbol
+declared in include/peps.h, rejects bad arguments before enqueueing anything, and
+every operand offset of the launch plan stays inside its buffer."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1806_03761_amd.workloads import Lattice
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _peps():
+    from paper_1806_03761_amd import peps
+    if not os.path.exists(peps.LIB_PATH):
+        pytest.skip("library not built (python -m paper_1806_03761_amd.build)")
+    return peps
+
+
+def test_exports_match_header():
+    peps = _peps()
+    hdr = open(os.path.join(ROOT, "include", "peps.h")).read()
+    declared = set(re.findall(r"\b(peps_[a-z_]+)\s*\(", hdr))
+    lib = ctypes.CDLL(peps.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(peps.exported_symbols())
+
+
+@pytest.mark.parametrize("lat,batch", [
+    (Lattice(4, 4, 2, 4), 256), (Lattice(8, 8, 4, 16), 4096), (Lattice(16, 16, 6, 36), 4),
+    (Lattice(24, 24, 8, 64), 1), (Lattice(12, 12, 6, 36), 3), (Lattice(5, 3, 3, 2), 7),
+    (Lattice(2, 2, 1, 1), 3), (Lattice(3, 7, 2, 1), 5), (Lattice(7, 2, 5, 9), 2)])
+def test_plan_bounds(lat, batch):
+    peps = _peps()
+    for grad_mode in range(4):
+        for want_e in (False, True):
+            assert peps.plan_check(lat, batch, grad_mode, want_e) > 0
+
+
+def test_plan_rejects_bad_lattice():
+    peps = _peps()
+    for lat in (Lattice(1, 4, 2, 2), Lattice(4, 4, 0, 2), Lattice(4, 4, 2, 0)):
+        with pytest.raises(peps.PepsError):
+            peps.plan_check(lat, 1)
+    with pytest.raises(peps.PepsError):
+        peps.plan_check(Lattice(4, 4, 2, 2), 0)
