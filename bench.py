@@ -37,7 +37,7 @@ def _oracle_worker(args):
     return hi - lo
 
 
-def cpu_baseline(name: str, per_core: int = 2):
+def cpu_baseline(name: str, per_core: int = 8):
     """Time the FP64 oracle (amplitude + local energy + log-derivatives, one sample per
     process) on the host cores, over a bounded sample of the workload."""
     import multiprocessing as mp
@@ -90,16 +90,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # kernels of the timed region are bracketed by HIP events on the library's stream
+    peps.profile_enable(("gemm", "qr", "svd"))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    kern = {}
+    for cls in ("svd", "qr", "gemm"):
+        kms, n, fl = peps.profile_read(cls)
+        kern[cls] = {"ms_total": kms, "launches": n, "avg_us": 1e3 * kms / max(n, 1),
+                     "tflops": fl / max(kms, 1e-12) / 1e9}
+    peps.profile_enable(())
     ms = dt * 1e3 / args.steps
     value = B * args.steps / dt
 
     res = {
-        "metric": "samples/sec (amplitude+E_loc+grad)",
+        "metric": "samples/sec (amplitude+E_loc+grad) & contraction MFMA util, batched vs plain",
         "value": value,
         "unit": "samples/s",
         "n_gpus": 1,
@@ -116,6 +124,16 @@ def main():
                    "lattice": [lat.Lx, lat.Ly], "D": lat.D, "Dc": lat.Dc, "batch": B,
                    "gemm_precision": args.prec, "factorisation_precision": "f64"},
     }
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    # peaks: MI355X fp64 vector (= fp64 matrix) 78.6 TFLOP/s; fp32 matrix 157.3;
+    # bf16 matrix 2516.6 (dense)
+    gemm_peak = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}[args.prec]
+    bound, peak = ("alu", 78.6) if dom in ("svd", "qr") else ("mfma", gemm_peak)
+    res["roofline"] = {"kernel": {"svd": "k_svd", "qr": "k_qr", "gemm": "k_gemm"}[dom],
+                       "bound": bound, "achieved": kern[dom]["tflops"], "peak": peak,
+                       "unit": "TFLOP/s", "frac": kern[dom]["tflops"] / peak, "traffic": None,
+                       "avg_launch_us": kern[dom]["avg_us"]}
+    res["kernels"] = kern
     if not args.no_plain:
         # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
         nplain = 8

@@ -122,6 +122,22 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           const double* weights, double* log_abs, int8_t* sign,
                           double* e_loc, double* out, int8_t* flags);
 
+/* Kernel classes for the profiling calls below. */
+enum { PEPS_KC_GEMM = 0, PEPS_KC_QR = 1, PEPS_KC_SVD = 2 };
+
+/* Start timing the launches of the kernel classes in `class_mask` (bit 1 << PEPS_KC_*):
+ * each such launch is bracketed by two HIP events on the context's stream, together
+ * with its algorithmic flop count (GEMM 2MNK; QR 2 r^2 (max(m,n) - r/3); SVD step:
+ * implicit-Q apply 4 t (mz r - r^2/2) plus a thin SVD 4 a b^2 + 8 b^3 plus U_t Sigma_t
+ * 2 m n t).  Clears earlier records; 0 turns timing off. */
+peps_status peps_profile_enable(peps_ctx* ctx, uint32_t class_mask);
+
+/* Synchronise the context's stream and report, for one kernel class, the summed
+ * device time (ms), the number of timed launches and their summed algorithmic flops
+ * since the last peps_profile_enable. */
+peps_status peps_profile_read(peps_ctx* ctx, int32_t kernel_class, double* total_ms,
+                              int64_t* launches, double* flops);
+
 /* Diagnostic, no device work: lay out the workspace of one chunk of `batch` samples
  * and walk the whole launch sequence of an evaluation (want_eloc, grad_mode as in
  * peps_evaluate) without launching anything, checking on the host that every

@@ -15,8 +15,18 @@
 #include "common.h"
 #include "kernels.h"
 
+// one timed launch: events recorded on the context stream around it
+struct ProfRec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+};
+
 struct peps_ctx {
     int device = 0;
+    uint32_t prof_mask = 0;          // bit per kernel class (PEPS_KC_*) to time
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -252,13 +262,14 @@ public:
             return hipErrorInvalidValue;
         if (dry) return hipSuccess;
         GemmArgs g;
+        const double fl = 2.0 * M * Nn * K * (double)Bcur;
         g.M = M; g.N = Nn; g.K = K; g.batch = Bcur;
         g.am = am; g.ak = ak; g.bk = bk; g.bn = bn; g.cm = cm; g.cn = cn;
         g.a_bs = A.bs; g.b_bs = B.bs; g.c_bs = C.bs;
         g.ga = ga; g.gb = gb; g.gc = Gather{nullptr, 0, 0, 0};
         g.A = A.p; g.B = B.p; g.C = C.p;
         g.alpha = 1.0; g.beta = 0.0;
-        return launch_gemm(g, ar, ctx->stream);
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, ar, ctx->stream); });
     }
     Gather site_gather(int i, int j, int flip) const {
         return Gather{Scur + (long long)i * Lx + j, (long long)N, flip, (long long)D4};
@@ -321,8 +332,10 @@ public:
                     bounds_msg = "internal bounds check failed in qr";
                     return hipErrorInvalidValue;
                 }
-                KL(launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R, buf(o_tau[j]),
-                             s_tau[j], Bcur, ctx->stream));
+                KL(timed(PEPS_KC_QR, Bcur * qr_flops((double)rows, t.K[j + 1]), [&] {
+                    return launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
+                                     buf(o_tau[j]), s_tau[j], Bcur, ctx->stream);
+                }));
             }
         }
         // right-to-left SVD sweep (bounds of every factorisation buffer checked first)
@@ -349,16 +362,20 @@ public:
             const int j = Lx - 1;
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
-            KL(launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
-                          Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
-                          ctx->stream));
+            KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, 0, 1, p, t.tau[j]), [&] {
+                return launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
+                                  Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
+                                  ctx->stream);
+            }));
         }
         for (int j = Lx - 2; j >= 1; --j) {
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
-            KL(launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
-                          t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]), s_G,
-                          buf(o_svd), s_svd, flags(), Bcur, ctx->stream));
+            KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, t.rho[j + 1], t.tau[j + 1], p, t.tau[j]), [&] {
+                return launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
+                                  t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]),
+                                  s_G, buf(o_svd), s_svd, flags(), Bcur, ctx->stream);
+            }));
             cur ^= 1;
         }
         {
@@ -463,6 +480,37 @@ public:
     }
 
     int8_t* flags() const { return (int8_t*)buf(o_flags); }
+
+    // launch `f` between two events when its kernel class is being profiled
+    template <class F>
+    hipError_t timed(int cls, double flops, F f) {
+        if (dry || !(ctx->prof_mask & (1u << cls))) return f();
+        hipEvent_t ev[2];
+        for (int k = 0; k < 2; ++k) {
+            if (!ctx->ev_pool.empty()) {
+                ev[k] = ctx->ev_pool.back();
+                ctx->ev_pool.pop_back();
+            } else {
+                hipError_t e = hipEventCreate(&ev[k]);
+                if (e != hipSuccess) return e;
+            }
+        }
+        hipError_t e = hipEventRecord(ev[0], ctx->stream);
+        if (e == hipSuccess) e = f();
+        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        ctx->prof.push_back(ProfRec{ev[0], ev[1], cls, flops});
+        return e;
+    }
+    // algorithmic flop models (documented in the design notes)
+    static double qr_flops(double m, double n) {
+        const double r = std::min(m, n);
+        return 2.0 * r * r * (std::max(m, n) - r / 3.0);
+    }
+    static double svd_flops(double mz, double r, double tin, double p, double tk) {
+        const double mp = mz / p, np = p * tin;
+        const double a = std::max(mp, np), b = std::min(mp, np);
+        return 4.0 * tin * (mz * r - 0.5 * r * r) + 4.0 * a * b * b + 8.0 * b * b * b + 2.0 * mp * np * tk;
+    }
 
     // ---- one chunk ----
     hipError_t run_chunk(const int8_t* S, int Bn, double* log_abs, int8_t* sign, double* e_loc,
@@ -690,6 +738,11 @@ peps_status peps_destroy(peps_ctx* c) {
     else hipDeviceSynchronize();
     if (c->ws) hipFree(c->ws);
     if (c->ones) hipFree(c->ones);
+    for (auto& r : c->prof) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) hipEventDestroy(e);
     delete c;
     return PEPS_OK;
 }
@@ -788,6 +841,38 @@ static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision 
                                                   (long long)N * 2 * D4, out, c->stream);
         if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
     }
+    return PEPS_OK;
+}
+
+peps_status peps_profile_enable(peps_ctx* c, uint32_t class_mask) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    for (auto& r : c->prof) {
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->prof.clear();
+    c->prof_mask = class_mask;
+    return PEPS_OK;
+}
+
+peps_status peps_profile_read(peps_ctx* c, int32_t kernel_class, double* total_ms, int64_t* launches,
+                              double* flops) {
+    if (!c || kernel_class < 0 || kernel_class >= 32) return PEPS_ERR_INVALID_ARG;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    double ms = 0.0, fl = 0.0;
+    int64_t n = 0;
+    for (auto& r : c->prof) {
+        if (r.cls != kernel_class) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(c, PEPS_ERR_HIP, "event timing failed");
+        ms += t;
+        fl += r.flops;
+        ++n;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (flops) *flops = fl;
     return PEPS_OK;
 }
 

@@ -48,6 +48,9 @@ _SIGS = {
                             _P, _P, _P, _P, _P],
     "peps_plan_check": [ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_size_t)],
+    "peps_profile_enable": [_P, ctypes.c_uint32],
+    "peps_profile_read": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     "peps_evaluate": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                       ctypes.c_int32, _P, _P, _P, _P, _P, _P],
 }
@@ -131,6 +134,28 @@ def plan_check(lat, batch: int, grad_mode: int = 3, want_eloc: bool = True) -> i
     if st != 0:
         raise PepsError(f"peps_plan_check failed: {STATUS.get(st, st)}")
     return int(out.value)
+
+
+KERNEL_CLASS = {"gemm": 0, "qr": 1, "svd": 2}
+
+
+def profile_enable(classes=(), device: int = 0):
+    """Time every launch of the given kernel classes ("gemm", "qr", "svd") with HIP
+    events on the context's stream; () turns timing off."""
+    lib, ctx = _context(device)
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASS[c]
+    lib.peps_profile_enable(ctx, mask)
+
+
+def profile_read(cls: str, device: int = 0):
+    """(total device ms, launches, algorithmic flops) of one kernel class since enable."""
+    lib, ctx = _context(device)
+    ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    st = lib.peps_profile_read(ctx, KERNEL_CLASS[cls], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl))
+    _check(lib, ctx, st, "peps_profile_read")
+    return ms.value, n.value, fl.value
 
 
 def set_workspace_limit(nbytes: int, device: int = 0):
