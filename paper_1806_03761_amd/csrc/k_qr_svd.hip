@@ -17,12 +17,8 @@
 namespace peps {
 
 static constexpr int NT = 256;
-static constexpr int kRelayout = 32;
-static constexpr double kTiny = 1e-292;   // Z -> X relayout through registers up to NT*kRelayout
+static constexpr double kTiny = 1e-292;   // squared-norm floor of the Jacobi rotations
 
-__host__ __device__ inline bool svd_alias(int mz, int tin) {
-    return (long long)mz * tin <= (long long)NT * kRelayout;
-}
 
 __device__ inline double wave_sum(double v, int width) {
     for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -55,11 +51,20 @@ __device__ inline double block_max(double v, double* red) {
     return s;
 }
 
-__device__ inline int npow2(int x) {
+
+// ---------------------------------------------------------------------------
+// LDS strides.  A wave reads tpc consecutive rows of several columns at once; a
+// column stride that is a multiple of 32 doubles puts every column on the same
+// banks (8- to 16-way conflicts).  Padding the stride by 4 (or 2) doubles spreads
+// the groups over the banks (2-way, the minimum for 64 lanes of 8 bytes).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int tpc_for(int ncols) {
     int p = 1;
-    while (p < x) p <<= 1;
-    return p;
+    while (p < ncols) p <<= 1;
+    const int t = NT / p;
+    return t < 1 ? 1 : (t > 64 ? 64 : t);
 }
+__host__ __device__ inline int pad_for(int tpc) { return tpc == 16 ? 2 : 4; }
 
 // ---------------------------------------------------------------------------
 // QR
@@ -74,14 +79,15 @@ __global__ __launch_bounds__(NT) void k_qr(double* X, long long xs, int m, int n
     __shared__ double s_beta, s_tau, s_scal;
     const int b = blockIdx.x, tid = threadIdx.x;
     double* Xg = X + (long long)b * xs;
+    const int ldw = use_lds ? m + 4 : m;
     double* W = use_lds ? lds : Xg;
     const int r = min(m, n);
     if (use_lds) {
-        for (int e = tid; e < m * n; e += NT) W[e] = Xg[e];
+        for (int e = tid; e < m * n; e += NT) W[(e / m) * ldw + e % m] = Xg[e];
         __syncthreads();
     }
     for (int k = 0; k < r; ++k) {
-        double* colk = W + (long long)k * m;
+        double* colk = W + (long long)k * ldw;
         double part = 0.0;
         for (int i = k + 1 + tid; i < m; i += NT) part += colk[i] * colk[i];
         const double s = block_sum(part, red);
@@ -112,13 +118,13 @@ __global__ __launch_bounds__(NT) void k_qr(double* X, long long xs, int m, int n
         if (tk != 0.0) {
             const int ncols = n - k - 1;
             if (ncols > 0) {
-                const int tpc = min(64, max(1, NT / npow2(ncols)));
+                const int tpc = tpc_for(ncols);
                 const int ngroups = NT / tpc;
                 const int g = tid / tpc, l = tid % tpc;
                 for (int c0 = k + 1; c0 < n; c0 += ngroups) {
                     const int c = c0 + g;
                     const bool act = c < n;
-                    double* colc = W + (long long)(act ? c : k) * m;
+                    double* colc = W + (long long)(act ? c : k) * ldw;
                     double dot = 0.0;
                     if (act) {
                         for (int i = k + 1 + l; i < m; i += tpc) dot += colk[i] * colc[i];
@@ -139,21 +145,21 @@ __global__ __launch_bounds__(NT) void k_qr(double* X, long long xs, int m, int n
     double* Rb = R + (long long)b * rs;
     for (int e = tid; e < r * n; e += NT) {
         const int i = e / n, c = e % n;
-        Rb[e] = (i <= c) ? W[(long long)c * m + i] : 0.0;
+        Rb[e] = (i <= c) ? W[(long long)c * ldw + i] : 0.0;
     }
     if (use_lds) {
-        for (int e = tid; e < m * n; e += NT) Xg[e] = W[e];
+        for (int e = tid; e < m * n; e += NT) Xg[e] = W[(e / m) * ldw + e % m];
     }
 }
 
 // ---------------------------------------------------------------------------
-// implicit Q: Z (column-major mz x tin) <- H_0 H_1 ... H_{r-1} Z
+// implicit Q: Z (column-major mz x tin, stride ldz) <- H_0 H_1 ... H_{r-1} Z
 // V column-major mz x r (reflector k in column k below the diagonal, unit diagonal).
 // ---------------------------------------------------------------------------
-__device__ void apply_q(const double* V, const double* tau, int mz, int r, double* Z, int tin,
-                        double* vbuf) {
+__device__ void apply_q(const double* V, const double* tau, int mz, int r, double* Z, int ldz,
+                        int tin, double* vbuf) {
     const int tid = threadIdx.x;
-    const int tpc = min(64, max(1, NT / npow2(tin)));
+    const int tpc = tpc_for(tin);
     const int ngroups = NT / tpc;
     const int g = tid / tpc, l = tid % tpc;
     for (int k = r - 1; k >= 0; --k) {
@@ -165,7 +171,7 @@ __device__ void apply_q(const double* V, const double* tau, int mz, int r, doubl
         for (int c0 = 0; c0 < tin; c0 += ngroups) {
             const int c = c0 + g;
             const bool act = c < tin;
-            double* zc = Z + (long long)(act ? c : 0) * mz;
+            double* zc = Z + (long long)(act ? c : 0) * ldz;
             double dot = 0.0;
             if (act) {
                 for (int i = k + 1 + l; i < mz; i += tpc) dot += vbuf[i] * zc[i];
@@ -182,15 +188,15 @@ __device__ void apply_q(const double* V, const double* tau, int mz, int r, doubl
     __syncthreads();
 }
 
-// Load Z = [G; 0] column-major (mz x tin) from G row-major (r x tin), then apply Q.
+// Load Z = [G; 0] column-major (mz x tin, stride ldz) from G row-major (r x tin), then apply Q.
 __device__ void form_center(const double* V, const double* tau, const double* G, int mz, int r,
-                            int tin, double* Z, double* vbuf) {
+                            int tin, double* Z, int ldz, double* vbuf) {
     for (int e = threadIdx.x; e < mz * tin; e += NT) {
         const int c = e / mz, i = e % mz;
-        Z[e] = (i < r) ? G[(long long)i * tin + c] : 0.0;
+        Z[(long long)c * ldz + i] = (i < r) ? G[(long long)i * tin + c] : 0.0;
     }
     __syncthreads();
-    if (V) apply_q(V, tau, mz, r, Z, tin, vbuf);
+    if (V) apply_q(V, tau, mz, r, Z, ldz, tin, vbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +207,10 @@ __device__ void form_center(const double* V, const double* tau, const double* G,
 // M = Z reshaped to m' x n' with m' = mz/p, n' = p*tin, M[a][d*tin+t] = Z[a*p+d][t].
 // Outputs: newU row-major tk x n' (new boundary tensor (tk, p, tin)), Gout row-major
 // m' x tk (U_t Sigma_t).  tk = min(Dc, m', n').
+//   m' >  n': one-sided Jacobi on the columns of M with the rotations accumulated
+//             in J (= V); U_t Sigma_t are the rotated columns.
+//   m' <= n': one-sided Jacobi on the columns of M^T (no accumulation): they
+//             become sigma_k v_k; U_t Sigma_t = M V_t is formed at the end.
 struct SvdArgs {
     const double* V; long long vs;
     const double* tau; long long ts;
@@ -213,55 +223,61 @@ struct SvdArgs {
     int8_t* flags;                    // set to 3 when Jacobi does not converge
 };
 
+struct SvdLayout {
+    int mp, np, caseA, len, cnt, ldz, ldx, ldj;
+    long long oZ, oX, oJ, oV, oS, oP, total;   // offsets in doubles
+};
+
+__host__ __device__ inline SvdLayout svd_layout(int mz, int tin, int p) {
+    SvdLayout L;
+    L.mp = mz / p;
+    L.np = p * tin;
+    L.caseA = L.mp > L.np;
+    L.len = L.caseA ? L.mp : L.np;
+    L.cnt = L.caseA ? L.np : L.mp;
+    L.ldz = mz + pad_for(tpc_for(tin));
+    const int npairs = (L.cnt + (L.cnt & 1)) / 2;
+    const int tpp = tpc_for(npairs);
+    L.ldx = L.len + pad_for(tpp);
+    L.ldj = L.caseA ? L.cnt + pad_for(tpp) : 0;
+    L.oZ = 0;
+    L.oX = L.oZ + (long long)L.ldz * tin;
+    L.oJ = L.oX + (long long)L.ldx * L.cnt;
+    L.oV = L.oJ + (long long)L.ldj * L.cnt;
+    L.oS = L.oV + mz;
+    L.oP = L.oS + L.cnt;
+    L.total = L.oP + (L.cnt + 1) / 2 + 2;
+    return L;
+}
+
 __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
     extern __shared__ double lds[];
     __shared__ double red[NT / 64];
     __shared__ int s_rot;
     const int b = blockIdx.x, tid = threadIdx.x;
     const int mz = a.mz, tin = a.tin, p = a.p;
-    const int mp = mz / p, np = p * tin;
-    const bool caseA = mp >= np;              // orthogonalise columns of M, else of M^T
-    const int len = caseA ? mp : np, cnt = caseA ? np : mp;
+    const SvdLayout L = svd_layout(mz, tin, p);
+    const int mp = L.mp, np = L.np, len = L.len, cnt = L.cnt, ldx = L.ldx, ldj = L.ldj, ldz = L.ldz;
+    const bool caseA = L.caseA;
     const int tk = min(a.Dc, cnt);
-    // scratch: Z (mz*tin) | X (only when Z cannot be relaid in registers) | J | vbuf | sig | perm
-    const bool alias = svd_alias(mz, tin);
     double* base = a.use_lds ? lds : a.scratch + (long long)b * a.ss;
-    double* Z = base;
-    double* X = alias ? Z : Z + (long long)mz * tin;
-    double* J = X + (long long)mz * tin;
-    double* vbuf = J + (long long)cnt * cnt;
-    double* sig = vbuf + mz;
-    int* perm = (int*)(sig + cnt);
+    double* Z = base + L.oZ;
+    double* X = base + L.oX;
+    double* J = base + L.oJ;
+    double* vbuf = base + L.oV;
+    double* sig = base + L.oS;
+    int* perm = (int*)(base + L.oP);
 
     form_center(a.V ? a.V + (long long)b * a.vs : nullptr, a.tau + (long long)b * a.ts,
-                a.G + (long long)b * a.gs, mz, a.V ? a.r : mz, tin, Z, vbuf);
-    // Z (col-major mz x tin) -> X (col-major len x cnt): M[a][d*tin+t] = Z[a*p+d][t]
-    if (alias) {
-        double tmp[kRelayout];
-        const int tot = mz * tin;
-#pragma unroll
-        for (int q = 0; q < kRelayout; ++q) {
-            const int e = q * NT + tid;
-            tmp[q] = e < tot ? Z[e] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kRelayout; ++q) {
-            const int e = q * NT + tid;
-            if (e < tot) {
-                const int t = e / mz, i = e % mz;
-                const int ar = i / p, d = i % p;
-                const int col = d * tin + t;
-                X[caseA ? (long long)col * len + ar : (long long)ar * len + col] = tmp[q];
-            }
-        }
-    } else {
-        for (int e = tid; e < mz * tin; e += NT) {
-            const int t = e / mz, i = e % mz;
-            const int ar = i / p, d = i % p;
-            const int col = d * tin + t;
-            X[caseA ? (long long)col * len + ar : (long long)ar * len + col] = Z[e];
-        }
+                a.G + (long long)b * a.gs, mz, a.V ? a.r : mz, tin, Z, ldz, vbuf);
+    // X = M (case A) or M^T, column-major with stride ldx; M[ar][d*tin+t] = Z[t][ar*p+d]
+    for (int e = tid; e < mz * tin; e += NT) {
+        const int t = e / mz, i = e % mz;
+        const int ar = i / p, d = i % p;
+        const int col = d * tin + t;
+        const double v = Z[(long long)t * ldz + i];
+        if (caseA) X[(long long)col * ldx + ar] = v;
+        else X[(long long)ar * ldx + col] = v;
     }
     __syncthreads();
     // exact power-of-two prescale so that the largest entry is in [0.5, 1): the
@@ -269,17 +285,21 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
     int ex = 0;
     {
         double mx = 0.0;
-        for (int e = tid; e < len * cnt; e += NT) mx = fmax(mx, fabs(X[e]));
+        for (int e = tid; e < len * cnt; e += NT) mx = fmax(mx, fabs(X[(e / len) * ldx + e % len]));
         mx = block_max(mx, red);
         if (mx > 0.0 && isfinite(mx)) frexp(mx, &ex);
-        for (int e = tid; e < len * cnt; e += NT) X[e] = ldexp(X[e], -ex);
+        for (int e = tid; e < len * cnt; e += NT) {
+            double* x = X + (e / len) * ldx + e % len;
+            *x = ldexp(*x, -ex);
+        }
     }
-    for (int e = tid; e < cnt * cnt; e += NT) J[e] = ((e / cnt) == (e % cnt)) ? 1.0 : 0.0;
+    if (caseA)
+        for (int e = tid; e < cnt * cnt; e += NT) J[(e / cnt) * ldj + e % cnt] = ((e / cnt) == (e % cnt)) ? 1.0 : 0.0;
     __syncthreads();
 
     const int cpad = cnt + (cnt & 1);
     const int npairs = cpad / 2;
-    const int tpp = min(64, max(1, NT / npow2(npairs)));
+    const int tpp = tpc_for(npairs);
     const int ngroups = NT / tpp;
     const int g = tid / tpp, l = tid % tpp;
     const double tol = 2.220446049250313e-16 * sqrt((double)len);
@@ -299,8 +319,8 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
                 }
                 const bool act = cp >= 0;
                 double al = 0.0, be = 0.0, ga = 0.0;
-                double* xp = X + (long long)(act ? cp : 0) * len;
-                double* xq = X + (long long)(act ? cq : 0) * len;
+                double* xp = X + (long long)(act ? cp : 0) * ldx;
+                double* xq = X + (long long)(act ? cq : 0) * ldx;
                 if (act) {
                     for (int i = l; i < len; i += tpp) {
                         const double u = xp[i], v = xq[i];
@@ -312,11 +332,10 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
                 al = wave_sum(al, tpp);
                 be = wave_sum(be, tpp);
                 ga = wave_sum(ga, tpp);
-                // sqrt(al)*sqrt(be), not sqrt(al*be): the product underflows for
-                // columns of norm ~1e-140 and the test would then never pass
-                // pairs with a squared column norm in the underflow range (< 1e-292 of
-                // the largest entry squared) are left alone: their contribution to the
-                // state is below 1e-146 and their rotations cannot be resolved
+                // sqrt(al)*sqrt(be), not sqrt(al*be): the product underflows for tiny
+                // columns.  Pairs with a squared column norm below 1e-292 of the largest
+                // entry squared are left alone: their contribution to the state is below
+                // 1e-146 and their rotations cannot be resolved.
                 if (act && al > kTiny && be > kTiny && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     // smaller root of t^2 + 2 zeta t - 1 = 0; for |zeta| > 1e150 zeta^2
@@ -330,12 +349,14 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
                         xp[i] = c * u - s * v;
                         xq[i] = s * u + c * v;
                     }
-                    double* jp = J + (long long)cp * cnt;
-                    double* jq = J + (long long)cq * cnt;
-                    for (int i = l; i < cnt; i += tpp) {
-                        const double u = jp[i], v = jq[i];
-                        jp[i] = c * u - s * v;
-                        jq[i] = s * u + c * v;
+                    if (caseA) {
+                        double* jp = J + (long long)cp * ldj;
+                        double* jq = J + (long long)cq * ldj;
+                        for (int i = l; i < cnt; i += tpp) {
+                            const double u = jp[i], v = jq[i];
+                            jp[i] = c * u - s * v;
+                            jq[i] = s * u + c * v;
+                        }
                     }
                     if (l == 0 && s != 0.0) s_rot = 1;   // an underflowed rotation changes nothing
                 }
@@ -347,9 +368,9 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
     }
     if (sweep == a.max_sweeps && tid == 0 && a.flags && a.flags[b] == 0) a.flags[b] = 3;
 
-    // singular values and descending order (ties by index)
+    // singular values (of the prescaled matrix) and descending order (ties by index)
     for (int k = tid; k < cnt; k += NT) {
-        const double* xk = X + (long long)k * len;
+        const double* xk = X + (long long)k * ldx;
         double s2 = 0.0;
         for (int i = 0; i < len; ++i) s2 += xk[i] * xk[i];
         sig[k] = sqrt(s2);
@@ -365,27 +386,35 @@ __global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
     double* U = a.newU + (long long)b * a.us;
     double* Go = a.Gout + (long long)b * a.gos;
     if (caseA) {
-        // V = J (np x np), G = X columns (mp)
+        // V = J (np x np), U_t Sigma_t = rotated columns of M (mp)
         for (int e = tid; e < tk * np; e += NT) {
             const int rr = e / np, c = e % np;
-            U[e] = J[(long long)perm[rr] * cnt + c];
+            U[e] = J[(long long)perm[rr] * ldj + c];
         }
         for (int e = tid; e < mp * tk; e += NT) {
             const int i = e / tk, rr = e % tk;
-            Go[e] = ldexp(X[(long long)perm[rr] * len + i], ex);
+            Go[e] = ldexp(X[(long long)perm[rr] * ldx + i], ex);
         }
     } else {
-        // X = M^T: columns are sigma_k v_k; U = J (mp x mp)
+        // columns of X = M^T are sigma_k v_k: V_t = normalised columns; then U_t Sigma_t = M V_t
         for (int e = tid; e < tk * np; e += NT) {
             const int rr = e / np, c = e % np;
             const int k = perm[rr];
             const double s = sig[k];
-            U[e] = s > 0.0 ? X[(long long)k * len + c] / s : 0.0;
+            const double v = s > 0.0 ? X[(long long)k * ldx + c] / s : 0.0;
+            U[e] = v;
+            X[(long long)k * ldx + c] = v;     // keep V_t in place for the product below
         }
+        __syncthreads();
         for (int e = tid; e < mp * tk; e += NT) {
-            const int i = e / tk, rr = e % tk;
-            const int k = perm[rr];
-            Go[e] = ldexp(J[(long long)k * cnt + i] * sig[k], ex);
+            const int ar = e / tk, rr = e % tk;
+            const double* vk = X + (long long)perm[rr] * ldx;
+            double acc = 0.0;
+            for (int d = 0; d < p; ++d) {
+                const double* zrow = Z + ar * p + d;   // Z[t][ar*p+d] = M[ar][d*tin+t]
+                for (int t = 0; t < tin; ++t) acc += zrow[(long long)t * ldz] * vk[d * tin + t];
+            }
+            Go[e] = acc;
         }
     }
 }
@@ -400,18 +429,22 @@ __global__ __launch_bounds__(NT) void k_center0(const double* V, long long vs, c
     extern __shared__ double lds[];
     __shared__ double red[NT / 64];
     const int b = blockIdx.x, tid = threadIdx.x;
+    const int ldz = mz + pad_for(tpc_for(tin));
     double* Z = use_lds ? lds : scratch + (long long)b * ss;
-    double* vbuf = Z + (long long)mz * tin;
+    double* vbuf = Z + (long long)ldz * tin;
     form_center(V ? V + (long long)b * vs : nullptr, tau + (long long)b * ts, G + (long long)b * gs,
-                mz, V ? r : mz, tin, Z, vbuf);
+                mz, V ? r : mz, tin, Z, ldz, vbuf);
     double part = 0.0;
-    for (int e = tid; e < mz * tin; e += NT) part += Z[e] * Z[e];
+    for (int e = tid; e < mz * tin; e += NT) {
+        const double z = Z[(long long)(e / mz) * ldz + e % mz];
+        part += z * z;
+    }
     const double nu = sqrt(block_sum(part, red));
     const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
     double* U = newU + (long long)b * us;
     for (int e = tid; e < mz * tin; e += NT) {
         const int i = e / tin, c = e % tin;
-        U[e] = Z[(long long)c * mz + i] * inv;
+        U[e] = Z[(long long)c * ldz + i] * inv;
     }
     if (tid == 0) logs_out[b] = (logs_in ? logs_in[b] : 0.0) + (nu > 0.0 ? log(nu) : -INFINITY);
 }
@@ -424,19 +457,14 @@ static size_t lds_cap() { return get_lds_cap(); }
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
-    const size_t bytes = (size_t)m * n * sizeof(double);
+    const size_t bytes = (size_t)(m + 4) * n * sizeof(double);
     const int use = bytes <= lds_cap() - 1024;
     hipLaunchKernelGGL(k_qr, dim3(batch), dim3(NT), use ? bytes : 0, st, X, xs, m, n, R, rs, tau,
                        ts, use);
     return hipGetLastError();
 }
 
-size_t svd_scratch_doubles(int mz, int tin, int p) {
-    const int mp = mz / p, np = p * tin;
-    const int cnt = mp < np ? mp : np;
-    const size_t zx = (size_t)mz * tin * (svd_alias(mz, tin) ? 1 : 2);
-    return zx + (size_t)cnt * cnt + mz + cnt + (cnt + 1) / 2 + 8;
-}
+size_t svd_scratch_doubles(int mz, int tin, int p) { return (size_t)svd_layout(mz, tin, p).total; }
 
 hipError_t launch_svd(const double* V, long long vs, const double* tau, long long ts,
                       const double* G, long long gs, int mz, int r, int tin, int p, int Dc,
@@ -454,7 +482,9 @@ hipError_t launch_svd(const double* V, long long vs, const double* tau, long lon
     return hipGetLastError();
 }
 
-size_t center0_scratch_doubles(int mz, int tin) { return (size_t)mz * tin + mz + 8; }
+size_t center0_scratch_doubles(int mz, int tin) {
+    return (size_t)(mz + pad_for(tpc_for(tin))) * tin + mz + 8;
+}
 
 hipError_t launch_center0(const double* V, long long vs, const double* tau, long long ts,
                           const double* G, long long gs, int mz, int r, int tin, double* newU,

@@ -21,6 +21,27 @@ hipError_t launch_center0(const double* V, long long vs, const double* tau, long
                           long long us, const double* logs_in, double* logs_out, double* scratch,
                           long long ss, int batch, hipStream_t st);
 
+// truncation SVD through the Gram eigenproblem (three launches, see k_eig.hip)
+struct EigLayout {
+    int mp, np, gram_right, ns, tk, ldz, lda, ldx, nv;
+    long long oZ, oA, oD, oE, oT, oX, oL, oP, oW, total, lds_prep, lds_fin;
+};
+struct EigArgs {
+    const double* V; long long vs;
+    const double* tau; long long ts;
+    const double* G; long long gs;
+    int mz, r, tin, p, Dc;
+    double* newU; long long us;
+    double* Gout; long long gos;
+    double* scratch; long long ss;
+    int batch;
+};
+size_t eig_scratch_doubles(int mz, int tin, int p, int Dc);
+hipError_t launch_eig(const double* V, long long vs, const double* tau, long long ts, const double* G,
+                      long long gs, int mz, int r, int tin, int p, int Dc, double* newU, long long us,
+                      double* Gout, long long gos, double* scratch, long long ss, int batch,
+                      hipStream_t st);
+
 // misc
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
 hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -77,6 +78,8 @@ public:
         Lx = l.Lx; Ly = l.Ly; D = l.D; Dc = l.Dc; N = Lx * Ly;
         D2 = D * D; D3 = D2 * D; D4 = D3 * D;
         ar = prec == PEPS_PREC_F64 ? Arith::F64 : (prec == PEPS_PREC_F32 ? Arith::F32 : Arith::BF16);
+        const char* sv = getenv("PEPS_SVD");
+        use_eig = !(sv && strcmp(sv, "jacobi") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -152,7 +155,8 @@ public:
                 const long long mz = rows;
                 size_t sc = (j == 0) ? center0_scratch_doubles((int)mz, tin)
                                      : svd_scratch_doubles((int)mz, tin, t.p);
-                if (sc * sizeof(double) > lds_cap_bytes()) s_svd = std::max<long long>(s_svd, sc);
+                if ((j == 0 || !use_eig) && sc * sizeof(double) > lds_cap_bytes())
+                    s_svd = std::max<long long>(s_svd, sc);
             }
         };
         for (int i = 0; i + 1 < Ly; ++i) visit(tU[i]);
@@ -167,6 +171,21 @@ public:
         o_Y = L.alloc(s_Y);
         o_G[0] = L.alloc(s_G); o_G[1] = L.alloc(s_G);
         o_svd = s_svd ? L.alloc(s_svd) : 0;
+        s_eig = 1;
+        auto visit_eig = [&](const Trunc& t) {
+            for (int j = 1; j < Lx; ++j) {
+                const int mz = t.rho[j] * t.p, tin = (j + 1 < Lx) ? t.tau[j + 1] : 1;
+                s_eig = std::max<long long>(s_eig, (long long)eig_scratch_doubles(mz, tin, t.p, Dc));
+            }
+        };
+        if (use_eig) {
+            for (int i = 0; i + 1 < Ly; ++i) visit_eig(tU[i]);
+            if (need_L)
+                for (int i = Ly - 1; i >= 1; --i) visit_eig(tL[i]);
+            o_eig = L.alloc(s_eig);
+        } else {
+            o_eig = 0;
+        }
         // single-row partials
         s_P.assign(Lx + 1, 1);
         for (int i = 0; i < Ly; ++i)
@@ -346,7 +365,9 @@ public:
                                        : svd_scratch_doubles((int)mz, tin, p);
             const bool in_lds = sc * sizeof(double) <= lds_cap_bytes();
             const long long rin = (j + 1 < Lx) ? t.rho[j + 1] : mz;     // rows of G / reflectors
-            bool ok = in_lds || (long long)sc <= s_svd;
+            bool ok = use_eig ? (j == 0 || (long long)eig_scratch_doubles((int)mz, tin, p, Dc) <= s_eig)
+                              : (in_lds || (long long)sc <= s_svd);
+            if (j == 0) ok = in_lds || (long long)sc <= s_svd;
             ok = ok && mz * (j + 1 < Lx ? t.K[j + 1] : 1) <= s_X[j];
             ok = ok && (j + 1 == Lx || (rin <= s_tau[j] && rin * tin <= s_G));
             ok = ok && (long long)t.rho[j] * t.tau[j] <= s_G;
@@ -363,6 +384,10 @@ public:
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
             KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, 0, 1, p, t.tau[j]), [&] {
+                if (use_eig)
+                    return launch_eig(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
+                                      Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_eig), s_eig, Bcur,
+                                      ctx->stream);
                 return launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
                                   Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
                                   ctx->stream);
@@ -372,6 +397,10 @@ public:
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
             KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, t.rho[j + 1], t.tau[j + 1], p, t.tau[j]), [&] {
+                if (use_eig)
+                    return launch_eig(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
+                                      t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs,
+                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, ctx->stream);
                 return launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
                                   t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]),
                                   s_G, buf(o_svd), s_svd, flags(), Bcur, ctx->stream);
@@ -669,7 +698,9 @@ public:
     std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0;
-    long long s_R, s_Y, s_G, s_svd, s_T, s_F;
+    long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
+    size_t o_eig = 0;
+    bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
 };
 
 size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create
