@@ -17,7 +17,8 @@
 namespace peps {
 
 static constexpr int NT = 256;
-static constexpr double kTiny = 1e-292;   // squared-norm floor of the Jacobi rotations
+static constexpr double kTiny = 1e-292;
+static constexpr int kQrRegMaxM = 1024;   // squared-norm floor of the Jacobi rotations
 
 
 __device__ inline double wave_sum(double v, int width) {
@@ -149,6 +150,138 @@ __global__ __launch_bounds__(NT) void k_qr(double* X, long long xs, int m, int n
     }
     if (use_lds) {
         for (int e = tid; e < m * n; e += NT) Xg[e] = W[(e / m) * ldw + e % m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident QR for matrices of up to RPT*tpc rows and up to 256 columns.
+// Column c lives in the registers of thread group c (tpc lanes, lane l holds rows
+// l, l+tpc, ...).  Step k: the group of column k has published its column (after
+// all earlier reflections), its squared norm below the diagonal and its diagonal
+// entry in a double-buffered LDS slot; every thread derives the same reflector
+// from them, groups c > k apply it to their own column, and group k+1 publishes
+// the next pivot column.  One barrier per step; the pivot column reads are LDS
+// broadcasts.  Same arithmetic as k_qr (LAPACK dlarfg convention).
+// ---------------------------------------------------------------------------
+template <int RPT, int TPC>
+__device__ inline void qr_reg_pivot(double (&a)[RPT], int k, int m, int l, double* vslot,
+                                    double* tslot, double* tau_out) {
+    // column k of this group: reflector with v_k = 1 (LAPACK dlarfg convention),
+    // published zero-padded (v_i = 0 for i < k and i >= m) together with tau
+    double s = 0.0, al = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = l + q * TPC;
+        const double x = a[q];
+        s += (i > k && i < m) ? x * x : 0.0;
+        al += (i == k) ? x : 0.0;
+    }
+    s = wave_sum(s, TPC);
+    al = wave_sum(al, TPC);
+    double tk, be, sc;
+    if (s == 0.0) {
+        tk = 0.0; be = al; sc = 0.0;
+    } else {
+        be = -copysign(sqrt(al * al + s), al);
+        tk = (be - al) / be;
+        sc = 1.0 / (al - be);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = l + q * TPC;
+        const double v = (i < k || i >= m) ? 0.0 : (i == k ? 1.0 : sc * a[q]);
+        vslot[i] = v;
+        a[q] = (i == k) ? be : ((i > k && tk != 0.0) ? v : a[q]);
+    }
+    if (l == 0) {
+        *tslot = tk;
+        *tau_out = tk;
+    }
+}
+
+// RPT rows per lane, TPC lanes per column, WG threads (WG / TPC >= n columns).
+template <int RPT, int TPC, int WG>
+__global__ __launch_bounds__(WG) void k_qr_reg(double* X, long long xs, int m, int n, double* R,
+                                               long long rs, double* tau, long long ts) {
+    __shared__ double xcol[2][RPT * TPC];
+    __shared__ double sh_t[2];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int g = tid / TPC, l = tid % TPC;
+    const int r = min(m, n);
+    double* Xg = X + (long long)b * xs;
+    double* taub = tau + (long long)b * ts;
+    const bool own = g < n;
+    double a[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = l + q * TPC;
+        a[q] = (own && i < m) ? Xg[(long long)g * m + i] : 0.0;
+    }
+    // iteration k: apply the reflector of step k-1, then group k publishes step k
+    for (int k = 0; k <= r; ++k) {
+        if (k > 0) {
+            const int bk = (k - 1) & 1;
+            const double tk = sh_t[bk];
+            if (own && g >= k && tk != 0.0) {
+                const double* vs = xcol[bk];
+                double v[RPT];
+                double dot = 0.0;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    v[q] = vs[l + q * TPC];
+                    dot += v[q] * a[q];
+                }
+                dot = wave_sum(dot, TPC);
+                const double f = tk * dot;
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) a[q] -= f * v[q];
+            }
+        }
+        if (k < r && g == k) qr_reg_pivot<RPT, TPC>(a, k, m, l, xcol[k & 1], &sh_t[k & 1], &taub[k]);
+        __syncthreads();
+    }
+    // write back: reflectors + R in X (column-major), R row-major r x n
+    if (own) {
+        double* Rb = R + (long long)b * rs;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = l + q * TPC;
+            if (i < m) Xg[(long long)g * m + i] = a[q];
+            if (i < r) Rb[(long long)i * n + g] = (i <= g) ? a[q] : 0.0;
+        }
+    }
+}
+
+template <int TPC, int WG>
+static bool launch_qr_reg_t(double* X, long long xs, int m, int n, double* R, long long rs,
+                            double* tau, long long ts, int batch, hipStream_t st) {
+    const int need = (m + TPC - 1) / TPC;
+    if (need <= 4) hipLaunchKernelGGL((k_qr_reg<4, TPC, WG>), dim3(batch), dim3(WG), 0, st, X, xs, m, n, R, rs, tau, ts);
+    else if (need <= 16) hipLaunchKernelGGL((k_qr_reg<16, TPC, WG>), dim3(batch), dim3(WG), 0, st, X, xs, m, n, R, rs, tau, ts);
+    else if (need <= 32) hipLaunchKernelGGL((k_qr_reg<32, TPC, WG>), dim3(batch), dim3(WG), 0, st, X, xs, m, n, R, rs, tau, ts);
+    else return false;
+    return true;
+}
+
+template <int WG>
+static bool launch_qr_reg_wg(double* X, long long xs, int m, int n, double* R, long long rs,
+                             double* tau, long long ts, int batch, hipStream_t st) {
+    int p2 = 1;
+    while (p2 < n) p2 <<= 1;
+    int tpc = WG / p2;
+    tpc = tpc > 64 ? 64 : tpc;
+    if ((m + tpc - 1) / tpc > 32) return false;
+    switch (tpc) {
+        case 4: return WG == 256 && launch_qr_reg_t<4, 256>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        case 8: return WG == 256 ? launch_qr_reg_t<8, 256>(X, xs, m, n, R, rs, tau, ts, batch, st)
+                                 : launch_qr_reg_t<8, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        case 16: return WG == 256 ? launch_qr_reg_t<16, 256>(X, xs, m, n, R, rs, tau, ts, batch, st)
+                                  : launch_qr_reg_t<16, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        case 32: return WG == 256 ? launch_qr_reg_t<32, 256>(X, xs, m, n, R, rs, tau, ts, batch, st)
+                                  : launch_qr_reg_t<32, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        case 64: return WG == 256 ? launch_qr_reg_t<64, 256>(X, xs, m, n, R, rs, tau, ts, batch, st)
+                                  : launch_qr_reg_t<64, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        default: return false;
     }
 }
 
@@ -457,6 +590,11 @@ static size_t lds_cap() { return get_lds_cap(); }
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
+    if (n <= 64) {
+        if (launch_qr_reg_wg<256>(X, xs, m, n, R, rs, tau, ts, batch, st) ||
+            launch_qr_reg_wg<512>(X, xs, m, n, R, rs, tau, ts, batch, st))
+            return hipGetLastError();
+    }
     const size_t bytes = (size_t)(m + 4) * n * sizeof(double);
     const int use = bytes <= lds_cap() - 1024;
     hipLaunchKernelGGL(k_qr, dim3(batch), dim3(NT), use ? bytes : 0, st, X, xs, m, n, R, rs, tau,
