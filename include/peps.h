@@ -23,11 +23,12 @@
  *          value outside {0,1}, 2 zero amplitude, 3 non-finite result.
  *          A flagged sample never aborts the batch: its outputs are NaN
  *          (flag 1, 3) or sign 0 / ln|W| = -inf / E = NaN / Delta = 0 (flag 2).
- *   prec   arithmetic of the contraction GEMMs (boundary apply, sandwiches,
- *          environment tensors).  QR, SVD, normalisation, ln|W|, sign and the
- *          energy assembly are always float64.  PEPS_PREC_F32 and
- *          PEPS_PREC_BF16 round GEMM operands to that type and accumulate in
- *          float32.
+ *   prec   arithmetic of the contraction GEMMs.  PEPS_PREC_F64: all in float64.
+ *          PEPS_PREC_F32: operands rounded to float32, float32 accumulation.
+ *          PEPS_PREC_BF16: the MPO x MPS apply GEMMs of the boundary sweeps take
+ *          bfloat16 operands with float32 accumulation; the sandwich and
+ *          environment-tensor GEMMs run in float32.  QR, SVD, normalisation,
+ *          ln|W|, sign and the energy assembly are always float64.
  *   Every buffer is owned by the caller; outputs are written asynchronously on
  *   the context's stream and are valid after that stream is synchronised.
  *   Host-detectable errors (NULL pointers, Lx < 2 or Ly < 2, D < 1, Dc < 1,

@@ -77,7 +77,10 @@ public:
         : ctx(c), lat(l), prec(pr) {
         Lx = l.Lx; Ly = l.Ly; D = l.D; Dc = l.Dc; N = Lx * Ly;
         D2 = D * D; D3 = D2 * D; D4 = D3 * D;
+        // bf16 applies to the MPO x MPS apply GEMMs of the boundary sweeps; the sandwich and
+        // environment-tensor GEMMs then run in f32 (f32 and f64 use one type throughout)
         ar = prec == PEPS_PREC_F64 ? Arith::F64 : (prec == PEPS_PREC_F32 ? Arith::F32 : Arith::BF16);
+        ar_sw = prec == PEPS_PREC_F64 ? Arith::F64 : Arith::F32;
         const char* sv = getenv("PEPS_SVD");
         use_eig = !(sv && strcmp(sv, "jacobi") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
@@ -275,6 +278,10 @@ public:
     // ---- launch helpers ----
     hipError_t gemm(int M, int Nn, int K, Op A, Idx2 am, Idx2 ak, Gather ga, Op B, Idx2 bk, Idx2 bn,
                     Gather gb, Op C, Idx2 cm, Idx2 cn) {
+        return gemm_a(ar_sw, M, Nn, K, A, am, ak, ga, B, bk, bn, gb, C, cm, cn);
+    }
+    hipError_t gemm_a(Arith arith, int M, int Nn, int K, Op A, Idx2 am, Idx2 ak, Gather ga, Op B,
+                      Idx2 bk, Idx2 bn, Gather gb, Op C, Idx2 cm, Idx2 cn) {
         if (!bounds_ok("gemm A", A, idx_max(am, M) + idx_max(ak, K), ga.sel ? ga.slice : 0) ||
             !bounds_ok("gemm B", B, idx_max(bk, K) + idx_max(bn, Nn), gb.sel ? gb.slice : 0) ||
             !bounds_ok("gemm C", C, idx_max(cm, M) + idx_max(cn, Nn), 0))
@@ -288,7 +295,7 @@ public:
         g.ga = ga; g.gb = gb; g.gc = Gather{nullptr, 0, 0, 0};
         g.A = A.p; g.B = B.p; g.C = C.p;
         g.alpha = 1.0; g.beta = 0.0;
-        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, ar, ctx->stream); });
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, arith, ctx->stream); });
     }
     Gather site_gather(int i, int j, int flip) const {
         return Gather{Scur + (long long)i * Lx + j, (long long)N, flip, (long long)D4};
@@ -335,13 +342,13 @@ public:
             Op Ein = down ? envU(row, j) : envL(row, j);
             Op Y = op(o_Y, s_Y);
             // Y[(a',l),(u,b)] = sum_a R[a', a*Dl+l] E[a,(u,b)]
-            CK(gemm(rho * Dl, pin * chj1, chj, Rin, I2(Dl, ldR, 1), I1(Dl), Gather{},
+            CK(gemm_a(ar, rho * Dl, pin * chj1, chj, Rin, I2(Dl, ldR, 1), I1(Dl), Gather{},
                     Ein, I1((long long)pin * chj1), I1(1), Gather{},
                     Y, I1((long long)pin * chj1), I1(1)));
             // X[(a',d),(b,r)] (column-major) = sum_{l,u} Y[a',l,u,b] T[l,u,r,d]
             const long long rows = (long long)rho * p;
             Op X = op(o_X[j], s_X[j]);
-            CK(gemm(rho * chj1, Dr * p, Dl * pin, Y, I2(chj1, (long long)Dl * pin * chj1, 1),
+            CK(gemm_a(ar, rho * chj1, Dr * p, Dl * pin, Y, I2(chj1, (long long)Dl * pin * chj1, 1),
                     I2(pin, (long long)pin * chj1, chj1), Gather{},
                     site_op(row, j), I2(pin, D3, s_in), I2(p, D, s_out), site_gather(row, j, 0),
                     X, I2(chj1, p, Dr * rows), I2(p, rows, 1)));
@@ -680,7 +687,7 @@ public:
     peps_ctx* ctx;
     peps_lattice lat;
     peps_precision prec;
-    Arith ar;
+    Arith ar, ar_sw;
     int Lx, Ly, D, Dc, N;
     long long D2, D3, D4;
     std::vector<int> Dh, Dv;
