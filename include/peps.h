@@ -123,6 +123,51 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           const double* weights, double* log_abs, int8_t* sign,
                           double* e_loc, double* out, int8_t* flags);
 
+/* One job of a heterogeneous batch (peps_eval_jobs): a lattice with its own tensors,
+ * configurations and outputs, with the meanings of peps_evaluate.  A NULL e_loc skips
+ * the local energy (unless grad_mode is 3). */
+typedef struct {
+    peps_lattice lat;
+    const double* A;
+    const int8_t* S;
+    int64_t batch;
+    int32_t grad_mode;
+    const double* weights;
+    double* log_abs;
+    int8_t* sign;
+    double* e_loc;
+    double* out;
+    int8_t* flags;
+} peps_job;
+
+enum { PEPS_JOBS_GRAPH = 1 };
+
+/* Evaluate several lattices (sizes, D, Dc may differ) in one call, for example the
+ * mixed batches of a Monte Carlo run over several lattices.  Every job gets its own
+ * workspace region, so the whole batch of each job must fit the workspace limit
+ * together (PEPS_ERR_OOM otherwise).  With PEPS_JOBS_GRAPH the launch sequence of all
+ * jobs is captured once into a HIP graph, one branch per job, and launched as a single
+ * graph on the context stream; a later call with the same job list (same pointers,
+ * sizes and precision) replays the cached graph.  Results equal those of separate
+ * peps_evaluate calls.  At most 64 jobs. */
+peps_status peps_eval_jobs(peps_ctx* ctx, const peps_job* jobs, int32_t njobs,
+                           peps_precision prec, uint32_t flags);
+
+/* Autotuner of the contraction GEMM tiles.  Runs one evaluation (local energy and the
+ * Eq. (5) gradient) of the given lattice and batch; every GEMM shape not yet in the
+ * context's table is launched once with each candidate tile shape, timed with HIP events
+ * (this synchronises), and the fastest tile is recorded.  All tiles accumulate in the
+ * same order, so results do not depend on the choice.  Later calls on the context use
+ * the table.  *tuned (may be NULL) receives the number of shapes added.  If the
+ * environment variable PEPS_TUNE_CACHE names a file, peps_create loads it and
+ * peps_autotune saves the table there. */
+peps_status peps_autotune(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                          const double* A, const int8_t* S, int64_t batch, int32_t* tuned);
+
+/* Save / load the tile table as text lines "M,N,K,batch,arith tile". */
+peps_status peps_tune_save(peps_ctx* ctx, const char* path);
+peps_status peps_tune_load(peps_ctx* ctx, const char* path);
+
 /* Kernel classes for the profiling calls below. */
 enum { PEPS_KC_GEMM = 0, PEPS_KC_QR = 1, PEPS_KC_SVD = 2 };
 

@@ -133,14 +133,26 @@ static hipError_t launch_t(const GemmArgs& g, Arith ar, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st) {
+hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    // tile choice: smallest square-ish tile that covers small problems
-    if (g.M <= 16 && g.N <= 16) return launch_t<16, 16, 16>(g, ar, st);
-    if (g.M <= 32 && g.N <= 32) return launch_t<32, 32, 16>(g, ar, st);
-    if (g.N <= 16) return launch_t<64, 16, 16>(g, ar, st);
-    if (g.M <= 16) return launch_t<16, 64, 16>(g, ar, st);
-    return launch_t<64, 64, 16>(g, ar, st);
+    if (tile <= 0 || tile > kGemmTiles) {
+        // heuristic: smallest tile that covers small problems
+        if (g.M <= 16 && g.N <= 16) tile = 1;
+        else if (g.M <= 32 && g.N <= 32) tile = 2;
+        else if (g.N <= 16) tile = 3;
+        else if (g.M <= 16) tile = 4;
+        else tile = 5;
+    }
+    switch (tile) {
+        case 1: return launch_t<16, 16, 16>(g, ar, st);
+        case 2: return launch_t<32, 32, 16>(g, ar, st);
+        case 3: return launch_t<64, 16, 16>(g, ar, st);
+        case 4: return launch_t<16, 64, 16>(g, ar, st);
+        case 5: return launch_t<64, 64, 16>(g, ar, st);
+        case 6: return launch_t<32, 16, 32>(g, ar, st);
+        case 7: return launch_t<16, 32, 32>(g, ar, st);
+        default: return launch_t<64, 64, 16>(g, ar, st);
+    }
 }
 
 }  // namespace peps

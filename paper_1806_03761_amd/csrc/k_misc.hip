@@ -54,6 +54,16 @@ hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
+__global__ void k_copy_i8(const int8_t* src, int8_t* dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+hipError_t launch_copy_i8(const int8_t* src, int8_t* dst, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_i8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
 // flags[b] = 1 if any S[b][m] is outside {0, 1}, else 0.
 __global__ void k_check_configs(const int8_t* S, int N, int batch, int8_t* flags) {
     const int b = blockIdx.x;

@@ -5,7 +5,9 @@
 
 namespace peps {
 
-hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st);
+// tile: 0 = heuristic choice, 1..kGemmTiles = a fixed tile shape (see k_gemm.hip)
+static constexpr int kGemmTiles = 7;
+hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();
 
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
@@ -45,6 +47,7 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
 // misc
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
 hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st);
+hipError_t launch_copy_i8(const int8_t* src, int8_t* dst, long long n, hipStream_t st);
 hipError_t launch_check_configs(const int8_t* S, int N, int batch, int8_t* flags, hipStream_t st);
 hipError_t launch_rescale(double* x, long long xs, int n, const double* lin, double* lout,
                           int batch, hipStream_t st);

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -23,8 +26,21 @@ struct ProfRec {
     double flops;
 };
 
+// a captured job list of peps_eval_jobs, replayed when the same list comes again
+struct CachedGraph {
+    std::string key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 struct peps_ctx {
     int device = 0;
+    std::vector<CachedGraph> graphs;          // captured job lists (peps_eval_jobs)
+    std::vector<hipStream_t> job_streams;
+    std::vector<hipEvent_t> job_events;
+    std::map<std::string, int> tune;          // GEMM shape -> tile (autotuner)
+    bool tune_mode = false;
+    int tuned_now = 0;
     uint32_t prof_mask = 0;          // bit per kernel class (PEPS_KC_*) to time
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
@@ -35,6 +51,14 @@ struct peps_ctx {
     double* ones = nullptr;   // 4096 ones
     std::string err;
 };
+
+static void drop_graphs(peps_ctx* c) {
+    for (auto& g : c->graphs) {
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
 
 namespace peps {
 
@@ -255,7 +279,7 @@ public:
 
     static size_t lds_cap_bytes();
 
-    double* buf(size_t off) const { return (double*)(ctx->ws + off); }
+    double* buf(size_t off) const { return (double*)(base_ + off); }
     Op op(size_t off, long long per) const { return Op{buf(off), per, per}; }
     Op ones() const { return Op{ctx->ones, 0, kOnes}; }
 
@@ -295,7 +319,40 @@ public:
         g.ga = ga; g.gb = gb; g.gc = Gather{nullptr, 0, 0, 0};
         g.A = A.p; g.B = B.p; g.C = C.p;
         g.alpha = 1.0; g.beta = 0.0;
-        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, arith, ctx->stream); });
+        char kb[96];
+        snprintf(kb, sizeof kb, "%d,%d,%d,%d,%d", M, Nn, K, Bcur, (int)arith);
+        const std::string key(kb);
+        int tile = 0;
+        auto it = ctx->tune.find(key);
+        if (it != ctx->tune.end()) {
+            tile = it->second;
+        } else if (ctx->tune_mode) {
+            // time every tile once on this very launch (all tiles give identical results)
+            hipEvent_t ev[2];
+            if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+                return hipErrorUnknown;
+            float best = 1e30f;
+            int best_t = 0;
+            for (int t = 1; t <= kGemmTiles; ++t) {
+                hipEventRecord(ev[0], st_);
+                hipError_t e = launch_gemm(g, arith, st_, t);
+                hipEventRecord(ev[1], st_);
+                if (e != hipSuccess) return e;
+                hipEventSynchronize(ev[1]);
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (ms < best) {
+                    best = ms;
+                    best_t = t;
+                }
+            }
+            hipEventDestroy(ev[0]);
+            hipEventDestroy(ev[1]);
+            ctx->tune[key] = best_t;
+            ctx->tuned_now++;
+            return hipSuccess;
+        }
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, arith, st_, tile); });
     }
     Gather site_gather(int i, int j, int flip) const {
         return Gather{Scur + (long long)i * Lx + j, (long long)N, flip, (long long)D4};
@@ -360,7 +417,7 @@ public:
                 }
                 KL(timed(PEPS_KC_QR, Bcur * qr_flops((double)rows, t.K[j + 1]), [&] {
                     return launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
-                                     buf(o_tau[j]), s_tau[j], Bcur, ctx->stream);
+                                     buf(o_tau[j]), s_tau[j], Bcur, st_);
                 }));
             }
         }
@@ -394,10 +451,10 @@ public:
                 if (use_eig)
                     return launch_eig(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
                                       Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_eig), s_eig, Bcur,
-                                      ctx->stream);
+                                      st_);
                 return launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
                                   Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
-                                  ctx->stream);
+                                  st_);
             }));
         }
         for (int j = Lx - 2; j >= 1; --j) {
@@ -407,10 +464,10 @@ public:
                 if (use_eig)
                     return launch_eig(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
                                       t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs,
-                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, ctx->stream);
+                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, st_);
                 return launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
                                   t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]),
-                                  s_G, buf(o_svd), s_svd, flags(), Bcur, ctx->stream);
+                                  s_G, buf(o_svd), s_svd, flags(), Bcur, st_);
             }));
             cur ^= 1;
         }
@@ -420,7 +477,7 @@ public:
             Op lout = down ? logU(row + 1) : logL(row - 1);
             KL(launch_center0(buf(o_X[0]), s_X[0], buf(o_tau[0]), s_tau[0], buf(o_G[cur]), s_G, p,
                               t.rho[1], t.tau[1], Eout.p, Eout.bs, lin.p, lout.p, buf(o_svd), s_svd,
-                              Bcur, ctx->stream));
+                              Bcur, st_));
         }
         return hipSuccess;
     }
@@ -512,7 +569,7 @@ public:
                 I2((int)Dd, 1, cu1 * h1), Gather{}, Dl, I2((int)Du, D3, D2), I2((int)Dd, D, 1)));
         if (dry) return hipSuccess;
         return launch_grad_site(Dl.p, Dl.bs, Ad, Scur, i * Lx + j, N, D, (int)h, (int)Du, (int)h1,
-                                (int)Dd, Bcur, ctx->stream);
+                                (int)Dd, Bcur, st_);
     }
 
     int8_t* flags() const { return (int8_t*)buf(o_flags); }
@@ -531,9 +588,9 @@ public:
                 if (e != hipSuccess) return e;
             }
         }
-        hipError_t e = hipEventRecord(ev[0], ctx->stream);
+        hipError_t e = hipEventRecord(ev[0], st_);
         if (e == hipSuccess) e = f();
-        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], st_);
         ctx->prof.push_back(ProfRec{ev[0], ev[1], cls, flops});
         return e;
     }
@@ -554,7 +611,7 @@ public:
                          bool first_chunk) {
         Bcur = Bn;
         Scur = S;
-        hipStream_t st = ctx->stream;
+        hipStream_t st = st_;
         KL(launch_check_configs(S, N, Bn, flags(), st));
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
@@ -680,7 +737,7 @@ public:
                 KL(launch_energy_sums(eptr, flags(), Bn, buf(o_acc), !first_chunk, st));
             }
         }
-        if (flags_out) KL(hipMemcpyAsync(flags_out, flags(), Bn, hipMemcpyDeviceToDevice, st));
+        if (flags_out) KL(launch_copy_i8(flags(), flags_out, Bn, st));
         return hipSuccess;
     }
 
@@ -697,6 +754,8 @@ public:
     int Bc = 0, Bcur = 0, nbonds = 0;
     std::string bounds_msg;
     bool dry = false;
+    hipStream_t st_ = nullptr;   // stream this runner enqueues on
+    char* base_ = nullptr;       // its workspace
     bool want_eloc = false, want_grad = false;
     const double* Ad = nullptr;
     const int8_t* Scur = nullptr;
@@ -765,6 +824,8 @@ peps_status peps_create(peps_ctx** ctx, int device) {
         delete c;
         return PEPS_ERR_HIP;
     }
+    const char* tp = getenv("PEPS_TUNE_CACHE");
+    if (tp && *tp) peps_tune_load(c, tp);
     *ctx = c;
     return PEPS_OK;
 }
@@ -774,6 +835,9 @@ peps_status peps_destroy(peps_ctx* c) {
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
+    drop_graphs(c);
+    for (auto s2 : c->job_streams) hipStreamDestroy(s2);
+    for (auto e2 : c->job_events) hipEventDestroy(e2);
     if (c->ws) hipFree(c->ws);
     if (c->ones) hipFree(c->ones);
     for (auto& r : c->prof) {
@@ -817,67 +881,273 @@ peps_status peps_workspace_query(peps_ctx* c, const peps_lattice* lat, int64_t b
     return PEPS_OK;
 }
 
+// One evaluation request: a lattice, its tensors and configurations, and the outputs.
+struct JobIn {
+    peps_lattice lat;
+    const double* A;
+    const int8_t* S;
+    int64_t batch;
+    bool want_e;
+    int grad_mode;
+    const double* weights;
+    double* log_abs;
+    int8_t* sign;
+    double* e_loc;
+    double* out;
+    int8_t* flags;
+};
+
+static peps_status check_job(peps_ctx* c, JobIn& j, peps_precision prec) {
+    peps_status st = check_lat(c, &j.lat);
+    if (st != PEPS_OK) return st;
+    if (prec < PEPS_PREC_F64 || prec > PEPS_PREC_BF16) return fail(c, PEPS_ERR_INVALID_ARG, "bad precision");
+    if (j.batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
+    if (j.grad_mode < 0 || j.grad_mode > 3) return fail(c, PEPS_ERR_INVALID_ARG, "bad grad_mode");
+    if (j.batch == 0) return PEPS_OK;
+    if (!j.A || !j.S) return fail(c, PEPS_ERR_INVALID_ARG, "A or S is NULL");
+    if (j.grad_mode && !j.out) return fail(c, PEPS_ERR_INVALID_ARG, "gradient requested but out is NULL");
+    if (j.grad_mode == 2 && !j.weights) return fail(c, PEPS_ERR_INVALID_ARG, "weights is NULL");
+    if (j.grad_mode == 3) j.want_e = true;
+    return PEPS_OK;
+}
+
+// bytes per sample and fixed bytes of one chunk of this job
+static void job_sizes(Runner& r, const JobIn& j, size_t* per, size_t* fixed) {
+    r.layout(1, j.want_e, j.grad_mode != 0);
+    const size_t per1 = r.L.bytes;
+    r.layout(2, j.want_e, j.grad_mode != 0);
+    *per = r.L.bytes - per1;
+    *fixed = per1 > *per ? per1 - *per : 0;
+}
+
+static peps_status ensure_ws(peps_ctx* c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return PEPS_OK;
+    if (c->ws) {
+        if (c->stream) hipStreamSynchronize(c->stream);
+        else hipDeviceSynchronize();
+        drop_graphs(c);
+        hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+        c->ws = nullptr;
+        return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    c->ws_bytes = bytes;
+    return PEPS_OK;
+}
+
+// Enqueue every chunk of one job on r.st_ (workspace r.base_, laid out for Bc samples).
+static hipError_t enqueue_job(Runner& r, const JobIn& j, int64_t Bc) {
+    const int N = j.lat.Lx * j.lat.Ly;
+    const long long D4 = (long long)j.lat.D * j.lat.D * j.lat.D * j.lat.D;
+    r.Ad = j.A;
+    for (int64_t b0 = 0; b0 < j.batch; b0 += Bc) {
+        const int Bn = (int)std::min<int64_t>(Bc, j.batch - b0);
+        hipError_t e = r.run_chunk(j.S + b0 * N, Bn, j.log_abs ? j.log_abs + b0 : nullptr,
+                                   j.sign ? j.sign + b0 : nullptr, j.e_loc ? j.e_loc + b0 : nullptr,
+                                   j.grad_mode, j.weights ? j.weights + b0 : nullptr,
+                                   (j.grad_mode == 1) ? j.out + b0 * N * 2 * D4 : j.out,
+                                   j.flags ? j.flags + b0 : nullptr, b0 == 0);
+        if (e != hipSuccess) return e;
+    }
+    if (j.grad_mode == 3)
+        return launch_energy_grad_combine(r.buf(r.o_G1), r.buf(r.o_G0), r.buf(r.o_acc),
+                                          (long long)N * 2 * D4, j.out, r.st_);
+    return hipSuccess;
+}
+
 static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
                            const int8_t* S, int64_t batch, bool want_e, int grad_mode,
                            const double* weights, double* log_abs, int8_t* sign, double* e_loc,
                            double* out, int8_t* flags) {
     if (!c) return PEPS_ERR_INVALID_ARG;
     c->err.clear();
-    peps_status st = check_lat(c, lat);
-    if (st != PEPS_OK) return st;
-    if (prec < PEPS_PREC_F64 || prec > PEPS_PREC_BF16) return fail(c, PEPS_ERR_INVALID_ARG, "bad precision");
-    if (batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
-    if (grad_mode < 0 || grad_mode > 3) return fail(c, PEPS_ERR_INVALID_ARG, "bad grad_mode");
-    if (batch == 0) return PEPS_OK;
-    if (!A || !S) return fail(c, PEPS_ERR_INVALID_ARG, "A or S is NULL");
-    if (grad_mode && !out) return fail(c, PEPS_ERR_INVALID_ARG, "gradient requested but out is NULL");
-    if (grad_mode == 2 && !weights) return fail(c, PEPS_ERR_INVALID_ARG, "weights is NULL");
-    if (grad_mode == 3) want_e = true;
+    if (!lat) return fail(c, PEPS_ERR_INVALID_ARG, "lattice is NULL");
+    JobIn j{*lat, A, S, batch, want_e, grad_mode, weights, log_abs, sign, e_loc, out, flags};
+    peps_status st = check_job(c, j, prec);
+    if (st != PEPS_OK || batch == 0) return st;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
-    const bool want_g = grad_mode != 0;
     Runner r(c, *lat, prec);
-    // chunk size from the workspace limit
-    r.layout(1, want_e, want_g);
-    const size_t per1 = r.L.bytes;
-    r.layout(2, want_e, want_g);
-    const size_t per = r.L.bytes - per1;
-    const size_t fixed = per1 > per ? per1 - per : 0;
+    size_t per, fixed;
+    job_sizes(r, j, &per, &fixed);
     const size_t limit = default_limit(c);
     if (per + fixed > limit) return fail(c, PEPS_ERR_OOM, "one sample needs %zu bytes > limit %zu", per + fixed, limit);
     int64_t Bc = std::min<int64_t>(batch, (int64_t)((limit - fixed) / per));
     Bc = std::max<int64_t>(1, std::min<int64_t>(Bc, 1 << 20));
-    r.layout((int)Bc, want_e, want_g);
-    if (r.L.bytes > c->ws_bytes) {
-        if (c->ws) {
-            if (c->stream) hipStreamSynchronize(c->stream);
-            else hipDeviceSynchronize();
-            hipFree(c->ws);
-            c->ws = nullptr;
-            c->ws_bytes = 0;
-        }
-        if (hipMalloc(&c->ws, r.L.bytes) != hipSuccess) {
-            c->ws = nullptr;
-            return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", r.L.bytes);
-        }
-        c->ws_bytes = r.L.bytes;
+    r.layout((int)Bc, j.want_e, grad_mode != 0);
+    st = ensure_ws(c, r.L.bytes);
+    if (st != PEPS_OK) return st;
+    r.st_ = c->stream;
+    r.base_ = c->ws;
+    hipError_t e = enqueue_job(r, j, Bc);
+    if (e != hipSuccess)
+        return fail(c, PEPS_ERR_HIP, "HIP error: %s %s", hipGetErrorString(e), r.bounds_msg.c_str());
+    return PEPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// heterogeneous batches: several lattices in one graph launch
+// ---------------------------------------------------------------------------
+static std::string jobs_key(const peps_job* jobs, int njobs, peps_precision prec, const void* ws) {
+    std::string k;
+    auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+    add(&prec, sizeof prec);
+    add(&ws, sizeof ws);
+    for (int i = 0; i < njobs; ++i) add(&jobs[i], sizeof(peps_job));
+    return k;
+}
+
+peps_status peps_eval_jobs(peps_ctx* c, const peps_job* jobs, int32_t njobs, peps_precision prec,
+                           uint32_t flags) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, PEPS_ERR_INVALID_ARG, "bad job list");
+    if (njobs > 64) return fail(c, PEPS_ERR_UNSUPPORTED, "at most 64 jobs per call");
+    std::vector<JobIn> js;
+    for (int i = 0; i < njobs; ++i) {
+        const peps_job& q = jobs[i];
+        JobIn j{q.lat, q.A, q.S, q.batch, q.e_loc != nullptr, q.grad_mode, q.weights, q.log_abs,
+                q.sign, q.e_loc, q.out, q.flags};
+        peps_status st = check_job(c, j, prec);
+        if (st != PEPS_OK) return fail(c, st, "job %d: %s", i, c->err.c_str());
+        if (j.batch > 0) js.push_back(j);
     }
-    r.Ad = A;
-    const int N = lat->Lx * lat->Ly;
-    const long long D4 = (long long)lat->D * lat->D * lat->D * lat->D;
-    for (int64_t b0 = 0; b0 < batch; b0 += Bc) {
-        const int Bn = (int)std::min<int64_t>(Bc, batch - b0);
-        hipError_t e = r.run_chunk(S + b0 * N, Bn, log_abs ? log_abs + b0 : nullptr,
-                                   sign ? sign + b0 : nullptr, e_loc ? e_loc + b0 : nullptr, grad_mode,
-                                   weights ? weights + b0 : nullptr,
-                                   (grad_mode == 1) ? out + b0 * N * 2 * D4 : out,
-                                   flags ? flags + b0 : nullptr, b0 == 0);
-        if (e != hipSuccess)
-            return fail(c, PEPS_ERR_HIP, "HIP error: %s %s", hipGetErrorString(e), r.bounds_msg.c_str());
+    if (js.empty()) return PEPS_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
+    // every job gets its own workspace region, sized for its whole batch in one chunk
+    std::vector<Runner> rs;
+    rs.reserve(js.size());
+    std::vector<size_t> offs;
+    size_t total = 0;
+    for (auto& j : js) {
+        rs.emplace_back(c, j.lat, prec);
+        rs.back().layout((int)std::min<int64_t>(j.batch, 1 << 20), j.want_e, j.grad_mode != 0);
+        offs.push_back(total);
+        total += (rs.back().L.bytes + 255) / 256 * 256;
     }
-    if (grad_mode == 3) {
-        hipError_t e = launch_energy_grad_combine(r.buf(r.o_G1), r.buf(r.o_G0), r.buf(r.o_acc),
-                                                  (long long)N * 2 * D4, out, c->stream);
-        if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    if (total > default_limit(c))
+        return fail(c, PEPS_ERR_OOM, "jobs need %zu bytes of workspace > limit %zu", total, default_limit(c));
+    peps_status st = ensure_ws(c, total);
+    if (st != PEPS_OK) return st;
+    const bool use_graph = (flags & PEPS_JOBS_GRAPH) != 0;
+    const std::string key = jobs_key(jobs, njobs, prec, c->ws);
+    if (use_graph) {
+        for (auto& g : c->graphs)
+            if (g.key == key) {
+                if (hipGraphLaunch(g.exec, c->stream) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipGraphLaunch failed");
+                return PEPS_OK;
+            }
+    }
+    // streams: one per job inside the capture (fork/join), or the context stream
+    hipStream_t cs = c->stream;
+    if (use_graph) {
+        while (c->job_streams.size() < js.size() + 1) {
+            hipStream_t s;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(c, PEPS_ERR_HIP, "stream");
+            c->job_streams.push_back(s);
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(c, PEPS_ERR_HIP, "event");
+            c->job_events.push_back(e);
+        }
+        cs = c->job_streams[0];
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(c, PEPS_ERR_HIP, "hipStreamBeginCapture failed");
+        hipEventRecord(c->job_events[0], cs);
+    }
+    const uint32_t saved_mask = c->prof_mask;
+    if (use_graph) c->prof_mask = 0;     // no timing events inside a captured graph
+    hipError_t err = hipSuccess;
+    for (size_t i = 0; i < js.size() && err == hipSuccess; ++i) {
+        Runner& r = rs[i];
+        r.base_ = c->ws + offs[i];
+        r.st_ = cs;
+        if (use_graph) {
+            r.st_ = c->job_streams[i + 1];
+            hipStreamWaitEvent(r.st_, c->job_events[0], 0);
+        }
+        err = enqueue_job(r, js[i], std::min<int64_t>(js[i].batch, 1 << 20));
+        if (use_graph && err == hipSuccess) {
+            hipEventRecord(c->job_events[i + 1], r.st_);
+            hipStreamWaitEvent(cs, c->job_events[i + 1], 0);
+        }
+    }
+    c->prof_mask = saved_mask;
+    if (use_graph) {
+        hipGraph_t graph = nullptr;
+        hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (err != hipSuccess || ec != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return fail(c, PEPS_ERR_HIP, "graph capture failed: %s", hipGetErrorString(err != hipSuccess ? err : ec));
+        }
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(c, PEPS_ERR_HIP, "hipGraphInstantiate failed");
+        }
+        if (c->graphs.size() >= 16) {
+            hipGraphExecDestroy(c->graphs.front().exec);
+            hipGraphDestroy(c->graphs.front().graph);
+            c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back(CachedGraph{key, graph, exec});
+        if (hipGraphLaunch(exec, c->stream) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipGraphLaunch failed");
+        return PEPS_OK;
+    }
+    if (err != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(err));
+    return PEPS_OK;
+}
+
+peps_status peps_autotune(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                          const int8_t* S, int64_t batch, int32_t* tuned) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    double* out = nullptr;
+    if (lat && batch > 0 && A && S) {
+        const long long D4 = (long long)lat->D * lat->D * lat->D * lat->D;
+        if (hipMalloc(&out, sizeof(double) * (2 * (size_t)lat->Lx * lat->Ly * D4 + 2 * (size_t)batch)) != hipSuccess)
+            return fail(c, PEPS_ERR_OOM, "autotune scratch");
+    }
+    c->tune_mode = true;
+    c->tuned_now = 0;
+    const uint32_t mask = c->prof_mask;
+    c->prof_mask = 0;
+    const long long nout = lat ? 2LL * lat->Lx * lat->Ly * lat->D * lat->D * lat->D * lat->D : 0;
+    peps_status st = run_all(c, lat, prec, A, S, batch, true, 3, nullptr, out ? out + nout : nullptr,
+                             nullptr, out ? out + nout + batch : nullptr, out, nullptr);
+    c->prof_mask = mask;
+    c->tune_mode = false;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (out) hipFree(out);
+    if (tuned) *tuned = c->tuned_now;
+    if (st == PEPS_OK) {
+        const char* path = getenv("PEPS_TUNE_CACHE");
+        if (path && *path) peps_tune_save(c, path);
+    }
+    return st;
+}
+
+peps_status peps_tune_save(peps_ctx* c, const char* path) {
+    if (!c || !path) return PEPS_ERR_INVALID_ARG;
+    std::ofstream f(path);
+    if (!f) return fail(c, PEPS_ERR_INVALID_ARG, "cannot write %s", path);
+    f << "# peps GEMM tiles: M,N,K,batch,arith tile\n";
+    for (auto& kv : c->tune) f << kv.first << " " << kv.second << "\n";
+    return PEPS_OK;
+}
+
+peps_status peps_tune_load(peps_ctx* c, const char* path) {
+    if (!c || !path) return PEPS_ERR_INVALID_ARG;
+    std::ifstream f(path);
+    if (!f) return fail(c, PEPS_ERR_INVALID_ARG, "cannot read %s", path);
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ss(line);
+        std::string key;
+        int tile = 0;
+        if (ss >> key >> tile && tile >= 1 && tile <= kGemmTiles) c->tune[key] = tile;
     }
     return PEPS_OK;
 }

@@ -28,6 +28,14 @@ class _Lattice(ctypes.Structure):
                 ("Dc", ctypes.c_int32), ("J1", ctypes.c_double), ("J2", ctypes.c_double)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("lat", _Lattice), ("A", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("batch", ctypes.c_int64), ("grad_mode", ctypes.c_int32),
+                ("weights", ctypes.c_void_p), ("log_abs", ctypes.c_void_p),
+                ("sign", ctypes.c_void_p), ("e_loc", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p)]
+
+
 _lib = None
 _lock = threading.Lock()
 _ctx = {}
@@ -51,6 +59,11 @@ _SIGS = {
     "peps_profile_enable": [_P, ctypes.c_uint32],
     "peps_profile_read": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "peps_eval_jobs": [_P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32],
+    "peps_autotune": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                      ctypes.POINTER(ctypes.c_int32)],
+    "peps_tune_save": [_P, ctypes.c_char_p],
+    "peps_tune_load": [_P, ctypes.c_char_p],
     "peps_evaluate": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                       ctypes.c_int32, _P, _P, _P, _P, _P, _P],
 }
@@ -158,6 +171,26 @@ def profile_read(cls: str, device: int = 0):
     return ms.value, n.value, fl.value
 
 
+def autotune(A, S, lat, prec: str = "f32") -> int:
+    """Pick the GEMM tile of every shape of this workload by timing (see peps_autotune)."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    n = ctypes.c_int32()
+    st = lib.peps_autotune(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), S.shape[0],
+                           ctypes.byref(n))
+    _check(lib, ctx, st, "peps_autotune")
+    return int(n.value)
+
+
+def tune_save(path: str, device: int = 0):
+    lib, ctx = _context(device)
+    _check(lib, ctx, lib.peps_tune_save(ctx, path.encode()), "peps_tune_save")
+
+
+def tune_load(path: str, device: int = 0):
+    lib, ctx = _context(device)
+    _check(lib, ctx, lib.peps_tune_load(ctx, path.encode()), "peps_tune_load")
+
+
 def set_workspace_limit(nbytes: int, device: int = 0):
     lib, ctx = _context(device)
     lib.peps_set_workspace_limit(ctx, int(nbytes))
@@ -239,6 +272,51 @@ def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out
                            _ptr(weights), _ptr(la), _ptr(sg), _ptr(e), _ptr(out), _ptr(fl))
     _check(lib, ctx, st, "peps_evaluate")
     return la, sg, e, out, fl
+
+
+def job_outputs(A, S, lat, grad_mode=3, want_eloc=True):
+    """Preallocated outputs of one job: (log_abs, sign, e_loc or None, out or None, flags)."""
+    B = S.shape[0]
+    N, D4 = lat.Lx * lat.Ly, lat.D ** 4
+    dev = A.device
+    la = torch.empty(B, dtype=torch.float64, device=dev)
+    sg = torch.empty(B, dtype=torch.int8, device=dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev) if (want_eloc or grad_mode == 3) else None
+    out = None
+    if grad_mode:
+        out = torch.empty((B, N, 2, D4) if grad_mode == 1 else (N, 2, D4), dtype=torch.float64, device=dev)
+    fl = torch.empty(B, dtype=torch.int8, device=dev)
+    return la, sg, e, out, fl
+
+
+def eval_jobs(jobs, prec: str = "f32", graph: bool = True, outputs=None):
+    """Several lattices in one call.  jobs: list of dicts with keys A, S, lat and optional
+    grad_mode (default 3), weights, want_eloc (default True).  With graph=True the whole
+    launch sequence is one HIP graph launch (replayed when the same tensors come again;
+    pass the previous return value as `outputs` to reuse the output buffers).
+    Returns one (log_abs, sign, e_loc, grad, flags) tuple per job."""
+    if not jobs:
+        return []
+    arr = (_Job * len(jobs))()
+    keep = []
+    res = []
+    lib = ctx = None
+    for i, j in enumerate(jobs):
+        lib, ctx, A, S = _prep(j["A"], j["S"], j["lat"])
+        gm = int(j.get("grad_mode", 3))
+        w = j.get("weights")
+        if w is not None:
+            w = w.to(device=A.device, dtype=torch.float64).contiguous()
+        o = outputs[i] if outputs is not None else job_outputs(A, S, j["lat"], gm, j.get("want_eloc", True))
+        la, sg, e, out, fl = o
+        keep += [A, S, w]
+        arr[i] = _Job(_lat(j["lat"]), _ptr(A), _ptr(S), S.shape[0], gm, _ptr(w), _ptr(la), _ptr(sg),
+                      _ptr(e), _ptr(out), _ptr(fl))
+        res.append(o)
+    st = lib.peps_eval_jobs(ctx, ctypes.cast(arr, ctypes.c_void_p), len(jobs), PREC[prec], 1 if graph else 0)
+    _check(lib, ctx, st, "peps_eval_jobs")
+    eval_jobs._keep = keep          # inputs must outlive the enqueued work
+    return res
 
 
 class PepsLogAmp(torch.autograd.Function):

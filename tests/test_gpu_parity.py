@@ -304,3 +304,70 @@ def test_product_state_24x24_geometry():
                 if s[m] != s[n]:
                     E += J * 0.5 * a[m, 1 - s[m]] * a[n, 1 - s[n]] / (a[m, s[m]] * a[n, s[n]])
         assert abs(e[b] - E) <= 1e-9 * max(1.0, abs(E))
+
+
+def test_eval_jobs_mixed_lattices_graph():
+    """Three lattices of different size, D and Dc in one captured HIP graph: every
+    job's outputs equal those of a separate evaluation bit for bit, and three replays
+    of the cached graph (with eager work in between) reproduce them."""
+    p = _peps()
+    specs = [("4x4_D2_Dc4", 20, 3), ("8x8_D4_Dc16", 7, 1)]
+    jobs, ref = [], []
+    for name, B, gm in specs:
+        lat, A, S, _ = make_workload(name, B)
+        Ad, Sd = _dev(A, S)
+        jobs.append({"A": Ad, "S": Sd, "lat": lat, "grad_mode": gm})
+        ref.append(_np(*[t for t in p.evaluate(Ad, Sd, lat, "f32", grad_mode=gm)]))
+    lat3 = Lattice(6, 5, 3, 9)
+    A3, S3 = make_random(lat3, 5, 4)
+    A3d, S3d = _dev(A3, S3)
+    jobs.append({"A": A3d, "S": S3d, "lat": lat3, "grad_mode": 0})
+    la, sg, fl = p.log_amplitude(A3d, S3d, lat3, "f32")
+    _, _, e3, _ = p.local_energy(A3d, S3d, lat3, "f32")
+    ref.append(_np(la, sg, e3, fl))
+    outs = p.eval_jobs(jobs, "f32", graph=True)
+    for rep in range(4):
+        for k, o in enumerate(outs):
+            la, sg, e, g, fl = o
+            r = ref[k]
+            got = _np(la, sg, e, fl) if g is None else _np(la, sg, e, g, fl)
+            want = [r[0], r[1], r[2], r[3]] if g is None else r
+            for x, y in zip(got, want):
+                assert np.array_equal(x, y, equal_nan=True), (rep, k)
+        # clear the outputs, do unrelated eager work, replay the cached graph
+        for o in outs:
+            for t in o:
+                if t is not None:
+                    t.zero_()
+        torch.cuda.synchronize()
+        _ = p.log_amplitude(jobs[0]["A"], jobs[0]["S"], jobs[0]["lat"], "f64")
+        torch.cuda.synchronize()
+        outs = p.eval_jobs(jobs, "f32", graph=True, outputs=outs)
+    # the results of the 4x4 job also match the oracle
+    lat, A, S, _ = make_workload("4x4_D2_Dc4", 20)
+    la_o, sg_o, e_o, _ = O.local_energy(A, lat, S)
+    la, sg, e, _, _ = _np(*outs[0])
+    _assert_amp(la, sg, la_o, sg_o, TOL_AMP["f32"])
+    _assert_e(e, e_o, TOL_E["f32"])
+
+
+def test_autotune_keeps_results():
+    """The tile autotuner times every candidate tile per GEMM shape; all tiles
+    accumulate in the same order, so results after tuning are bitwise unchanged."""
+    import os
+    import tempfile
+    p = _peps()
+    lat, A, S, _ = make_workload("8x8_D4_Dc16", 16)
+    Ad, Sd = _dev(A, S)
+    before = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=3))
+    n = p.autotune(Ad, Sd, lat, "f32")
+    assert n > 0
+    after = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=3))
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tiles.txt")
+        p.tune_save(path)
+        lines = [ln for ln in open(path) if not ln.startswith("#")]
+        assert len(lines) >= n
+        p.tune_load(path)
