@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the path is data-parallel over samples; "
@@ -87,6 +88,9 @@ def main():
     def step():
         return peps.evaluate(Ad, Sd, lat, args.prec, grad_mode=3, out=grad)
 
+    tuned = 0
+    if not args.no_tune:
+        tuned = peps.autotune(Ad, Sd, lat, args.prec)     # untimed: picks GEMM tiles by measurement
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -122,7 +126,8 @@ def main():
         "config": {"workload": "8x8 open J1-J2 (J2/J1=0.5), D=4, Dc=16, f32 contraction GEMMs, "
                                "f64 QR/SVD; amplitude + local energy + dE/dA",
                    "lattice": [lat.Lx, lat.Ly], "D": lat.D, "Dc": lat.Dc, "batch": B,
-                   "gemm_precision": args.prec, "factorisation_precision": "f64"},
+                   "gemm_precision": args.prec, "factorisation_precision": "f64",
+                   "autotuned_gemm_shapes": tuned},
     }
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
     # peaks: MI355X fp64 vector (= fp64 matrix) 78.6 TFLOP/s; fp32 matrix 157.3;

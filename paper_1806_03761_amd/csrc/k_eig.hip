@@ -20,11 +20,9 @@
 namespace peps {
 
 static constexpr int NT = 256;
+static constexpr int kQc = 4;    // reflectors staged per chunk in the implicit-Q phase
 
-__device__ inline double e_wave_sum(double v, int width) {
-    for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ inline double e_wave_sum(double v, int width) { return lane_group_sum(v, width); }
 __device__ inline double e_block_sum(double v, double* red) {
     v = e_wave_sum(v, 64);
     __syncthreads();
@@ -42,6 +40,13 @@ __host__ __device__ inline int e_tpc(int ncols) {
     return t < 1 ? 1 : (t > 64 ? 64 : t);
 }
 __host__ __device__ inline int e_pad(int tpc) { return tpc == 16 ? 2 : 4; }
+
+// Block order of the register-resident tridiagonalisation: the 16 x 16 thread grid holds
+// A in RB x RB blocks, so orders up to 64 stay in registers (RB = 8 would spill);
+// 0 = the LDS/global variant.
+__host__ __device__ inline int tri_rb(int ns) {
+    return ns <= 16 ? 1 : ns <= 32 ? 2 : ns <= 64 ? 4 : 0;
+}
 
 // Per-matrix global scratch (doubles): everything the three kernels hand over.
 __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) {
@@ -62,9 +67,12 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
     L.oX = L.oT + L.ns;
     L.oL = L.oX + (long long)L.ldx * L.tk;
     L.oP = L.oL + L.tk;
-    L.nv = mz > 2 * L.ns ? mz : 2 * L.ns;     // work vector of the prep kernel
+    L.nv = 3 * L.ns + 2 > kQc * mz ? 3 * L.ns + 2 : kQc * mz;   // work vectors of the prep kernel
+    if (L.nv < 48 * tri_rb(L.ns)) L.nv = 48 * tri_rb(L.ns);
     L.oW = L.oP + (long long)L.ldx * L.tk;
-    L.total = L.oW + L.nv;
+    L.nm = 0;
+    L.oM = L.oW + L.nv;
+    L.total = L.oM;
     // LDS needs of the two workgroup kernels
     L.lds_prep = (long long)L.ldz * tin + (long long)L.lda * L.ns + 3LL * L.ns + L.nv + 8;
     L.lds_fin = (long long)L.ldx * L.tk + (long long)L.lda * L.ns + L.ns + (long long)L.ldz * tin + L.tk + 8;
@@ -74,12 +82,146 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
 // ---------------------------------------------------------------------------
 // A: centre, Gram, tridiagonalisation
 // ---------------------------------------------------------------------------
-template <bool kLds>
+
+// Householder reduction of the symmetric A (order ns <= 16 RB, full storage in Am) to
+// tridiagonal form with A held in registers.  Thread (ti, tj) of the 16 x 16 grid (ti =
+// 4 wave + lane / 16, tj = lane % 16) owns rows ti RB .. ti RB + RB - 1 and the same
+// range of columns; padding rows and columns up to 16 RB stay exactly zero.  Step k:
+//   pivot   the 16 lanes of the row group holding row k (== column k) form the
+//           reflector H_k = I - tau v v^T from entries k+1.. of that row (v_{k+1} = 1);
+//   p       = tau A v, row sums reduced over the 16 lanes of a segment;
+//   update  A <- A - v w^T - w v^T with w = p - (tau/2)(p.v) v on rows, columns > k.
+// Entries beyond k+1 of v_k are stored in row k of Am for the back-transformation.
+// Two barriers per step; v and tau are double-buffered so the next pivot can run
+// while other waves still finish their update.
+template <int RB>
+__device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double* tau, double* vbuf, int ns, int lda) {
+    constexpr int W = 16 * RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ti = wave * 4 + (lane >> 4), tj = lane & 15;
+    const int r0 = ti * RB, c0 = tj * RB;
+    double* pb = vbuf + 2 * W;
+    __shared__ double s_tau2[2];
+    __shared__ double s_red[NT / 64];
+    double A[RB][RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+        for (int w = 0; w < RB; ++w)
+            A[u][w] = (r0 + u < ns && c0 + w < ns) ? Am[(long long)(c0 + w) * lda + r0 + u] : 0.0;
+    __syncthreads();   // Am rows are overwritten by reflectors below
+    auto pivot = [&](int kp) {
+        const int ku = kp - r0;
+        double rv[RB];
+#pragma unroll
+        for (int w = 0; w < RB; ++w) {
+            rv[w] = A[0][w];
+#pragma unroll
+            for (int u = 1; u < RB; ++u)
+                if (u == ku) rv[w] = A[u][w];
+        }
+        double sq = 0.0, al = 0.0;
+#pragma unroll
+        for (int w = 0; w < RB; ++w) {
+            const int j = c0 + w;
+            if (j >= kp + 2) sq = fma(rv[w], rv[w], sq);
+            if (j == kp + 1) al = rv[w];
+        }
+        sq = e_wave_sum(sq, 16);
+        al = e_wave_sum(al, 16);
+        double tk, be, sc;
+        if (sq == 0.0) {
+            tk = 0.0; be = al; sc = 0.0;
+        } else {
+            be = -copysign(sqrt(al * al + sq), al);
+            tk = (be - al) / be;
+            sc = 1.0 / (al - be);
+        }
+        double* vb = vbuf + (kp & 1) * W;
+#pragma unroll
+        for (int w = 0; w < RB; ++w) {
+            const int j = c0 + w;
+            const double v = (j >= kp + 2) ? sc * rv[w] : (j == kp + 1 ? 1.0 : 0.0);
+            vb[j] = v;
+            if (tk != 0.0 && j >= kp + 2 && j < ns) Am[(long long)kp * lda + j] = v;
+        }
+        if (tj == 0) {
+            s_tau2[kp & 1] = tk;
+            tau[kp] = tk;
+            e[kp] = be;
+        }
+    };
+    if (ns > 2 && ti == 0) pivot(0);
+    __syncthreads();
+    for (int k = 0; k + 2 < ns; ++k) {
+        const int par = k & 1;
+        const double tk = s_tau2[par];
+        if (tk != 0.0) {
+            const double* vb = vbuf + par * W;
+            double vr[RB], vc[RB], pr[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) vr[u] = vb[r0 + u];
+#pragma unroll
+            for (int w = 0; w < RB; ++w) vc[w] = vb[c0 + w];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                double acc = 0.0;
+#pragma unroll
+                for (int w = 0; w < RB; ++w) acc = fma(A[u][w], vc[w], acc);
+                pr[u] = tk * e_wave_sum(acc, 16);
+            }
+            double pv = 0.0;
+#pragma unroll
+            for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
+            pv += __shfl_xor(pv, 16, 64);
+            pv += __shfl_xor(pv, 32, 64);
+            if (lane == 0) s_red[wave] = pv;
+            if (tj == 0)
+#pragma unroll
+                for (int u = 0; u < RB; ++u) pb[r0 + u] = pr[u];
+            __syncthreads();
+            double pc[RB];
+#pragma unroll
+            for (int w = 0; w < RB; ++w) pc[w] = pb[c0 + w];
+            double sp = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / 64; ++i) sp += s_red[i];
+            const double K = 0.5 * tk * sp;
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const double wr = pr[u] - K * vr[u];
+#pragma unroll
+                for (int w = 0; w < RB; ++w) {
+                    const double wc = pc[w] - K * vc[w];
+                    if (r0 + u > k && c0 + w > k) A[u][w] -= vr[u] * wc + wr * vc[w];
+                }
+            }
+        }
+        if (k + 3 < ns && ti == (k + 1) / RB) pivot(k + 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+        for (int w = 0; w < RB; ++w) {
+            const int i = r0 + u, j = c0 + w;
+            if (i == j && i < ns) d[i] = A[u][w];
+            if (i == ns - 2 && j == ns - 1) e[ns - 2] = A[u][w];
+        }
+    if (tid == 0) {
+        if (ns >= 2) tau[ns - 2] = 0.0;
+        if (ns >= 1) tau[ns - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+template <bool kLds, int RB>
 __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, double* e, double* tau,
                           double* vbuf, const EigLayout& L, double* red) {
     const int b = blockIdx.x, tid = threadIdx.x;
     const int mz = a.mz, tin = a.tin, p = a.p, ns = L.ns, lda = L.lda, ldz = L.ldz;
-    // Z = [G; 0] then Z <- Q Z (reflectors of the QR of this column)
+    // Z = [G; 0] then Z <- Q Z (reflectors of the QR of this column, applied last to first).
+    // Group c owns column c of Z.
     const double* G = a.G + (long long)b * a.gs;
     const int r = a.V ? a.r : mz;
     for (int e2 = tid; e2 < mz * tin; e2 += NT) {
@@ -91,134 +233,182 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
         const double* V = a.V + (long long)b * a.vs;
         const double* tq = a.tau + (long long)b * a.ts;
         const int tpc = e_tpc(tin), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
-        for (int k = r - 1; k >= 0; --k) {
-            const double tk = tq[k];
-            if (tk == 0.0) continue;
+        // lane l always owns the rows i = l (mod tpc) of its group's column; reflectors
+        // are staged through LDS kQc at a time (one barrier per chunk)
+        double* vs = vbuf;                      // kQc reflectors of length mz
+        __shared__ double s_tq[kQc];
+        for (int k1 = r - 1; k1 >= 0; k1 -= kQc) {
+            const int k0 = k1 - kQc + 1 > 0 ? k1 - kQc + 1 : 0;
             __syncthreads();
-            for (int i = k + 1 + tid; i < mz; i += NT) vbuf[i] = V[(long long)k * mz + i];
+            for (int e2 = tid; e2 < (k1 - k0 + 1) * mz; e2 += NT) {
+                const int kk = e2 / mz, i = e2 % mz;
+                vs[kk * mz + i] = V[(long long)(k0 + kk) * mz + i];
+            }
+            if (tid <= k1 - k0) s_tq[tid] = tq[k0 + tid];
             __syncthreads();
             for (int c0 = 0; c0 < tin; c0 += ngroups) {
                 const int c = c0 + g;
                 const bool act = c < tin;
                 double* zc = Z + (long long)(act ? c : 0) * ldz;
-                double dot = 0.0;
-                if (act) {
-                    for (int i = k + 1 + l; i < mz; i += tpc) dot += vbuf[i] * zc[i];
-                    if (l == 0) dot += zc[k];
-                }
-                dot = e_wave_sum(dot, tpc);
-                if (act) {
-                    const double f = tk * dot;
-                    if (l == 0) zc[k] -= f;
-                    for (int i = k + 1 + l; i < mz; i += tpc) zc[i] -= f * vbuf[i];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // Gram matrix.  M[ar][col] = Z[t][ar*p+d] with col = d*tin + t.
-    // gram_right: A[c1][c2] = sum_ar M[ar][c1] M[ar][c2];  else A[a1][a2] = sum_col M[a1][col] M[a2][col]
-    for (int e2 = tid; e2 < ns * ns; e2 += NT) {
-        const int i = e2 / ns, j = e2 % ns;
-        if (j < i) continue;
-        double acc = 0.0;
-        if (L.gram_right) {
-            const int d1 = i / tin, t1 = i % tin, d2 = j / tin, t2 = j % tin;
-            const double* z1 = Z + (long long)t1 * ldz + d1;
-            const double* z2 = Z + (long long)t2 * ldz + d2;
-            for (int ar = 0; ar < L.mp; ++ar) acc += z1[ar * p] * z2[ar * p];
-        } else {
-            for (int col = 0; col < L.np; ++col) {
-                const int dd = col / tin, t = col % tin;
-                const double* zt = Z + (long long)t * ldz + dd;
-                acc += zt[i * p] * zt[j * p];
-            }
-        }
-        Am[(long long)i * lda + j] = acc;
-        Am[(long long)j * lda + i] = acc;
-    }
-    __syncthreads();
-    // Householder tridiagonalisation (lower part keeps the reflectors)
-    __shared__ double s_beta, s_tau, s_scal, s_K;
-    for (int k = 0; k + 2 < ns; ++k) {
-        double part = 0.0;
-        for (int i = k + 2 + tid; i < ns; i += NT) {
-            const double x = Am[(long long)i * lda + k];
-            part += x * x;
-        }
-        const double s = e_block_sum(part, red);
-        if (tid == 0) {
-            const double al = Am[(long long)(k + 1) * lda + k];
-            if (s == 0.0) {
-                s_tau = 0.0; s_beta = al; s_scal = 0.0;
-            } else {
-                const double be = -copysign(sqrt(al * al + s), al);
-                s_tau = (be - al) / be; s_scal = 1.0 / (al - be); s_beta = be;
-            }
-        }
-        __syncthreads();
-        const double tk = s_tau;
-        if (tid == 0) {
-            tau[k] = tk;
-            e[k] = s_beta;
-        }
-        if (tk == 0.0) {
-            __syncthreads();
-            continue;
-        }
-        // v (length ns-k-1, v[0] = 1) kept in column k below the subdiagonal
-        for (int i = k + 2 + tid; i < ns; i += NT) Am[(long long)i * lda + k] *= s_scal;
-        __syncthreads();
-        // p = tau * A22 v  (vbuf holds p), A22 = rows/cols k+1..ns-1
-        const int n2 = ns - k - 1;
-        {
-            const int tpr = e_tpc(n2), ngr = NT / tpr, g = tid / tpr, l = tid % tpr;
-            for (int i0 = 0; i0 < n2; i0 += ngr) {
-                const int ii = i0 + g;
-                const bool act = ii < n2;
-                double acc = 0.0;
-                if (act) {
-                    const double* row = Am + (long long)(k + 1 + ii) * lda + (k + 1);
-                    for (int jj = l; jj < n2; jj += tpr) {
-                        const double vj = (jj == 0) ? 1.0 : Am[(long long)(k + 1 + jj) * lda + k];
-                        acc += row[jj] * vj;
+                for (int k = k1; k >= k0; --k) {
+                    const double tk = s_tq[k - k0];
+                    if (tk == 0.0) continue;
+                    const double* vk = vs + (k - k0) * mz;
+                    const int i0 = k + (((l - k) % tpc) + tpc) % tpc;     // first own row >= k
+                    double dot = 0.0;
+                    if (act)
+                        for (int i = i0; i < mz; i += tpc) dot += ((i == k) ? 1.0 : vk[i]) * zc[i];
+                    dot = e_wave_sum(dot, tpc);
+                    if (act) {
+                        const double f = tk * dot;
+                        for (int i = i0; i < mz; i += tpc) zc[i] -= f * ((i == k) ? 1.0 : vk[i]);
                     }
                 }
-                acc = e_wave_sum(acc, tpr);
-                if (act && l == 0) vbuf[ii] = tk * acc;
             }
         }
         __syncthreads();
-        // K = tau/2 (p . v); w = p - K v
-        double pv = 0.0;
-        for (int jj = tid; jj < n2; jj += NT) {
-            const double vj = (jj == 0) ? 1.0 : Am[(long long)(k + 1 + jj) * lda + k];
-            pv += vbuf[jj] * vj;
+    }
+    // Gram matrix with 4x4 register blocks per thread, read straight from Z:
+    //   gram_right: A[c1][c2] = sum_ar M[ar][c1] M[ar][c2]   (x = column c, y = row ar)
+    //   else:       A[a1][a2] = sum_col M[a1][col] M[a2][col] (x = row a, y = column col)
+    // M[ar][col] = Z[t][ar*p+d] with col = d*tin + t, i.e. element (x, y) = Z[bx(x) + by(y)].
+    {
+        const int ny = L.gram_right ? L.mp : L.np;
+        auto bx = [&](int x) -> int {
+            return L.gram_right ? (x % tin) * ldz + x / tin : x * p;
+        };
+        auto by = [&](int y) -> int {
+            return L.gram_right ? y * p : (y % tin) * ldz + y / tin;
+        };
+        const int nb = (ns + 3) / 4;                 // 4x4 blocks per dimension
+        for (int blk = tid; blk < nb * nb; blk += NT) {
+            const int bi = blk / nb, bj = blk % nb;
+            if (bj < bi) continue;
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
+            int oi[4], oj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                oi[u] = bx(min(bi * 4 + u, ns - 1));
+                oj[u] = bx(min(bj * 4 + u, ns - 1));
+            }
+            for (int y = 0; y < ny; ++y) {
+                const double* zy = Z + by(y);
+                double a4[4], b4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a4[u] = zy[oi[u]];
+                    b4[u] = zy[oj[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) acc[u][w] = fma(a4[u], b4[w], acc[u][w]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int ii = bi * 4 + u, jj = bj * 4 + w;
+                    if (ii < ns && jj < ns && jj >= ii) {
+                        Am[(long long)ii * lda + jj] = acc[u][w];
+                        Am[(long long)jj * lda + ii] = acc[u][w];
+                    }
+                }
         }
-        pv = e_block_sum(pv, red);
-        const double K = 0.5 * tk * pv;
-        for (int jj = tid; jj < n2; jj += NT) {
-            const double vj = (jj == 0) ? 1.0 : Am[(long long)(k + 1 + jj) * lda + k];
-            vbuf[n2 + jj] = vbuf[jj] - K * vj;     // w
-        }
+    }
+    if constexpr (RB > 0) {
         __syncthreads();
-        // A22 -= v w^T + w v^T (upper triangle and diagonal, mirrored)
-        for (int e2 = tid; e2 < n2 * n2; e2 += NT) {
-            const int ii = e2 / n2, jj = e2 % n2;
-            if (jj < ii) continue;
-            const double vi = (ii == 0) ? 1.0 : Am[(long long)(k + 1 + ii) * lda + k];
-            const double vj = (jj == 0) ? 1.0 : Am[(long long)(k + 1 + jj) * lda + k];
-            const double wi = vbuf[n2 + ii], wj = vbuf[n2 + jj];
-            const double nv = Am[(long long)(k + 1 + ii) * lda + (k + 1 + jj)] - vi * wj - wi * vj;
-            Am[(long long)(k + 1 + ii) * lda + (k + 1 + jj)] = nv;
-            if (jj != ii) Am[(long long)(k + 1 + jj) * lda + (k + 1 + ii)] = nv;
+        tri_reg<RB>(Am, d, e, tau, vbuf, ns, lda);
+        return;
+    }
+    // Householder tridiagonalisation in full symmetric storage (row c == column c).
+    // At step k, group g updates column c = k+1+g (+ multiples of the group count),
+    // lane l the rows i = k+1+l (mod tpc); group 0 therefore holds column k+1 right
+    // after step k and computes the next reflector from its own lanes' rows (no
+    // cross-lane reads).  Reflector k (v_{k+1} = 1 implicit) is kept in column k,
+    // rows > k+1, for the back-transformation.  Two barriers per step.
+    __shared__ double s_tau[2];
+    double* vb0 = vbuf;                 // two reflector buffers of length ns
+    double* vb1 = vbuf + ns;
+    double* pb = vbuf + 2 * ns;         // p = tau A v
+    const int tpc = e_tpc(ns), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
+    __syncthreads();
+    auto pivot = [&](int kp, double* vb) {
+        double* ck = Am + (long long)kp * lda;
+        double sq = 0.0, al = 0.0;
+        for (int i = kp + l; i < ns; i += tpc) {
+            const double x = ck[i];
+            if (i >= kp + 2) sq += x * x;
+            if (i == kp + 1) al = x;
         }
+        sq = e_wave_sum(sq, tpc);
+        al = e_wave_sum(al, tpc);
+        double tk, be, sc;
+        if (sq == 0.0) {
+            tk = 0.0; be = al; sc = 0.0;
+        } else {
+            be = -copysign(sqrt(al * al + sq), al);
+            tk = (be - al) / be;
+            sc = 1.0 / (al - be);
+        }
+        for (int i = kp + l; i < ns; i += tpc) {
+            if (i >= kp + 2) {
+                const double v = sc * ck[i];
+                if (tk != 0.0) ck[i] = v;
+                vb[i] = v;
+            } else {
+                vb[i] = (i == kp + 1) ? 1.0 : 0.0;
+            }
+        }
+        for (int i = l; i < kp; i += tpc) vb[i] = 0.0;
+        if (l == 0) {
+            s_tau[kp & 1] = tk;
+            tau[kp] = tk;
+            e[kp] = be;
+        }
+    };
+    if (ns > 2 && g == 0) pivot(0, vb0);
+    __syncthreads();
+    for (int k = 0; k + 2 < ns; ++k) {
+        const double tk = s_tau[k & 1];
+        const double* v = (k & 1) ? vb1 : vb0;
+        if (tk != 0.0) {
+            // p_c = tau * (A v)_c for c > k
+            for (int c0 = k + 1; c0 < ns; c0 += ngroups) {
+                const int c = c0 + g;
+                const bool act = c < ns;
+                const double* col = Am + (long long)(act ? c : 0) * lda;
+                double dot = 0.0;
+                if (act)
+                    for (int i = k + 1 + l; i < ns; i += tpc) dot += col[i] * v[i];
+                dot = e_wave_sum(dot, tpc);
+                if (act && l == 0) pb[c] = tk * dot;
+            }
+            __syncthreads();
+            // K = tau/2 (p . v), w = p - K v ; column c -= v w_c + w v_c
+            double pv = 0.0;
+            for (int i = k + 1 + l; i < ns; i += tpc) pv += pb[i] * v[i];
+            pv = e_wave_sum(pv, tpc);
+            const double K = 0.5 * tk * pv;
+            for (int c0 = k + 1; c0 < ns; c0 += ngroups) {
+                const int c = c0 + g;
+                if (c >= ns) continue;
+                double* col = Am + (long long)c * lda;
+                const double vc = v[c], wc = pb[c] - K * vc;
+                for (int i = k + 1 + l; i < ns; i += tpc) col[i] -= v[i] * wc + (pb[i] - K * v[i]) * vc;
+            }
+        }
+        if (k + 3 < ns && g == 0) pivot(k + 1, (k & 1) ? vb0 : vb1);
         __syncthreads();
     }
     if (tid == 0) {
-        for (int k = ns - 2; k >= 0 && k + 2 >= ns; --k) {   // last (or only) off-diagonal
-            e[k] = Am[(long long)(k + 1) * lda + k];
-            tau[k] = 0.0;
+        if (ns >= 2) {
+            e[ns - 2] = Am[(long long)(ns - 2) * lda + (ns - 1)];
+            tau[ns - 2] = 0.0;
         }
         if (ns >= 1) tau[ns - 1] = 0.0;
     }
@@ -226,7 +416,7 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
     __syncthreads();
 }
 
-template <bool kLds>
+template <bool kLds, int RB>
 __global__ __launch_bounds__(NT) void k_eig_prep(EigArgs a) {
     extern __shared__ double lds[];
     __shared__ double red[NT / 64];
@@ -240,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_eig_prep(EigArgs a) {
         double* e = d + L.ns;
         double* tau = e + L.ns;
         double* vbuf = tau + L.ns;
-        prep_body<true>(a, Z, Am, d, e, tau, vbuf, L, red);
+        prep_body<true, RB>(a, Z, Am, d, e, tau, vbuf, L, red);
         // hand over Z, reflectors, d, e, tau
         const int tid = threadIdx.x;
         for (long long i = tid; i < (long long)L.ldz * a.tin; i += NT) gs[L.oZ + i] = Z[i];
@@ -252,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_eig_prep(EigArgs a) {
         }
     } else {
         // everything in global scratch
-        prep_body<false>(a, gs + L.oZ, gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, gs + L.oW, L, red);
+        prep_body<false, RB>(a, gs + L.oZ, gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, gs + L.oW, L, red);
     }
 }
 
@@ -264,17 +454,46 @@ __device__ inline unsigned hash_u32(unsigned x) {
     return x;
 }
 
-__global__ __launch_bounds__(64) void k_eig_tri(EigArgs a, int lanes_per_matrix) {
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix, int mats_per_block,
+                                                 int tri_lanes_in_lds) {
+    extern __shared__ double tri_lds[];
     const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
-    const int b = (int)(gid / lanes_per_matrix), l = (int)(gid % lanes_per_matrix);
-    if (b >= a.batch || l >= L.tk) return;
-    double* gs = a.scratch + (long long)b * a.ss;
-    const double* d = gs + L.oD;
-    const double* e = gs + L.oE;
-    double* x = gs + L.oX + (long long)l * L.ldx;
-    double* piv = gs + L.oP + (long long)l * L.ldx;
     const int n = L.ns;
+    const int mi = threadIdx.x / lanes_per_matrix, l = threadIdx.x % lanes_per_matrix;
+    const int b = blockIdx.x * mats_per_block + mi;
+    // d and e of this block's matrices in LDS (every Sturm step reads all of them)
+    for (int e2 = threadIdx.x; e2 < mats_per_block * n; e2 += blockDim.x) {
+        const int m2 = e2 / n, i = e2 % n;
+        const int b2 = blockIdx.x * mats_per_block + m2;
+        double dv = 0.0, ev = 0.0;
+        if (b2 < a.batch) {
+            const double* g2 = a.scratch + (long long)b2 * a.ss;
+            dv = g2[L.oD + i];
+            ev = (i + 1 < n) ? g2[L.oE + i] : 0.0;
+        }
+        tri_lds[(2 * m2) * n + i] = dv;
+        tri_lds[(2 * m2 + 1) * n + i] = ev;
+    }
+    __syncthreads();
+    if (b >= a.batch || mi >= mats_per_block || l >= L.tk) return;
+    double* gs = a.scratch + (long long)b * a.ss;
+    const double* d = tri_lds + (2 * mi) * n;
+    const double* e = tri_lds + (2 * mi + 1) * n;
+    // the lane's iterate and pivots: in LDS after the d/e block when they fit, element i of
+    // every lane side by side (stride blockDim.x) so a wave's accesses are consecutive;
+    // else in global scratch with unit stride
+    double* x;
+    double* piv;
+    int xs;
+    if (tri_lanes_in_lds) {
+        xs = blockDim.x;
+        x = tri_lds + 2LL * mats_per_block * n + threadIdx.x;
+        piv = x + (long long)n * blockDim.x;
+    } else {
+        xs = 1;
+        x = gs + L.oX + (long long)l * L.ldx;
+        piv = gs + L.oP + (long long)l * L.ldx;
+    }
     // Gershgorin interval and pivot floor
     double lo = 0.0, hi = 0.0, emax2 = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -288,7 +507,7 @@ __global__ __launch_bounds__(64) void k_eig_tri(EigArgs a, int lanes_per_matrix)
     const int kidx = n - 1 - l;   // l-th largest = kidx-th smallest
     // bisection: count(x) = number of eigenvalues < x
     for (int it = 0; it < 128; ++it) {
-        if (hi - lo <= 4.440892098500626e-16 * tnorm + pivmin) break;
+        if (hi - lo <= 1e-9 * tnorm + pivmin) break;
         const double mid = 0.5 * (lo + hi);
         int cnt = 0;
         double q = d[0] - mid;
@@ -306,32 +525,39 @@ __global__ __launch_bounds__(64) void k_eig_tri(EigArgs a, int lanes_per_matrix)
     // inverse iteration (T - lam I) x = b with T - lam I = L D L^T
     const double ptol = fmax(2.220446049250313e-16 * tnorm, 1e-300);
     for (int i = 0; i < n; ++i)
-        x[i] = (double)(hash_u32((unsigned)(l * 7919 + i * 104729 + 17)) & 0xffffff) / 16777216.0 - 0.5;
+        x[i * xs] = (double)(hash_u32((unsigned)(l * 7919 + i * 104729 + 17)) & 0xffffff) / 16777216.0 - 0.5;
     for (int it = 0; it < 3; ++it) {
         double q = d[0] - lam;
         if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-        piv[0] = q;
+        piv[0 * xs] = q;
         for (int i = 1; i < n; ++i) {
             q = d[i] - lam - e[i - 1] * e[i - 1] / q;
             if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-            piv[i] = q;
+            piv[i * xs] = q;
         }
         // L y = b (in place), then L^T x = D^-1 y
-        for (int i = 1; i < n; ++i) x[i] -= (e[i - 1] / piv[i - 1]) * x[i - 1];
-        x[n - 1] /= piv[n - 1];
-        for (int i = n - 2; i >= 0; --i) x[i] = (x[i] - e[i] * x[i + 1]) / piv[i];
+        for (int i = 1; i < n; ++i) x[i * xs] -= (e[i - 1] / piv[(i - 1) * xs]) * x[(i - 1) * xs];
+        x[(n - 1) * xs] /= piv[(n - 1) * xs];
+        for (int i = n - 2; i >= 0; --i) x[i * xs] = (x[i * xs] - e[i] * x[(i + 1) * xs]) / piv[i * xs];
         double mx = 0.0;
-        for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i]));
+        for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i * xs]));
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
         double nrm = 0.0;
         for (int i = 0; i < n; ++i) {
-            x[i] *= inv;
-            nrm += x[i] * x[i];
+            x[i * xs] *= inv;
+            nrm += x[i * xs] * x[i * xs];
         }
         const double s = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
-        for (int i = 0; i < n; ++i) x[i] *= s;
+        for (int i = 0; i < n; ++i) x[i * xs] *= s;
     }
-    gs[L.oL + l] = lam;
+    // eigenvalue from the Rayleigh quotient of the converged unit vector
+    double rq = d[0] * x[0 * xs] * x[0 * xs];
+    for (int i = 1; i < n; ++i) rq += d[i] * x[i * xs] * x[i * xs] + 2.0 * e[i - 1] * x[(i - 1) * xs] * x[i * xs];
+    gs[L.oL + l] = (fabs(rq - lam) <= 1e-8 * tnorm + pivmin) ? rq : lam;
+    if (tri_lanes_in_lds) {
+        double* xo = gs + L.oX + (long long)l * L.ldx;
+        for (int i = 0; i < n; ++i) xo[i] = x[i * xs];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -380,30 +606,31 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
             }
     }
     __syncthreads();
-    // back-transformation: X <- H_0 ... H_{ns-3} X (reflector k acts on rows k+1..)
+    // back-transformation: X <- H_0 ... H_{ns-3} X (reflector k acts on rows k+1..; its
+    // entries beyond k+1 are stored in Am row k).  Group c owns vector c, lane l the rows
+    // i = l (mod tpc), so no barrier is needed between reflectors.
     {
         const int tpc = e_tpc(tk), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
-        for (int k = ns - 3; k >= 0; --k) {
-            const double tq = tau[k];
-            if (tq == 0.0) continue;
-            for (int c0 = 0; c0 < tk; c0 += ngroups) {
-                const int c = c0 + g;
-                const bool act = c < tk;
-                double* xc = X + (long long)(act ? c : 0) * ldx;
+        for (int c0 = 0; c0 < tk; c0 += ngroups) {
+            const int c = c0 + g;
+            const bool act = c < tk;
+            double* xc = X + (long long)(act ? c : 0) * ldx;
+            for (int k = ns - 3; k >= 0; --k) {
+                const double tq = tau[k];
+                if (tq == 0.0) continue;
+                const double* vk = Am + (long long)k * lda;
+                const int i0 = (k + 1) + (((l - k - 1) % tpc) + tpc) % tpc;   // first own row > k
                 double dot = 0.0;
-                if (act) {
-                    for (int i = k + 2 + l; i < ns; i += tpc) dot += Am[(long long)i * lda + k] * xc[i];
-                    if (l == 0) dot += xc[k + 1];
-                }
+                if (act)
+                    for (int i = i0; i < ns; i += tpc) dot += ((i == k + 1) ? 1.0 : vk[i]) * xc[i];
                 dot = e_wave_sum(dot, tpc);
                 if (act) {
                     const double f = tq * dot;
-                    if (l == 0) xc[k + 1] -= f;
-                    for (int i = k + 2 + l; i < ns; i += tpc) xc[i] -= f * Am[(long long)i * lda + k];
+                    for (int i = i0; i < ns; i += tpc) xc[i] -= f * ((i == k + 1) ? 1.0 : vk[i]);
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     double* U = a.newU + (long long)b * a.us;
     double* Go = a.Gout + (long long)b * a.gos;
@@ -476,13 +703,29 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const EigLayout L = eig_layout(mz, tin, p, Dc);
     const size_t cap = get_lds_cap() - 1024;
     const size_t bp = (size_t)L.lds_prep * sizeof(double), bf = (size_t)L.lds_fin * sizeof(double);
-    if (bp <= cap) hipLaunchKernelGGL(k_eig_prep<true>, dim3(batch), dim3(NT), bp, st, a);
-    else hipLaunchKernelGGL(k_eig_prep<false>, dim3(batch), dim3(NT), 0, st, a);
+    const bool in_lds_prep = bp <= cap;
+    const size_t bpl = in_lds_prep ? bp : 0;
+    switch (tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((k_eig_prep<false, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 3: hipLaunchKernelGGL((k_eig_prep<true, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 4: hipLaunchKernelGGL((k_eig_prep<false, 2>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 5: hipLaunchKernelGGL((k_eig_prep<true, 2>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 8: hipLaunchKernelGGL((k_eig_prep<false, 4>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 9: hipLaunchKernelGGL((k_eig_prep<true, 4>), dim3(batch), dim3(NT), bpl, st, a); break;
+        case 1: hipLaunchKernelGGL((k_eig_prep<true, 0>), dim3(batch), dim3(NT), bpl, st, a); break;
+        default: hipLaunchKernelGGL((k_eig_prep<false, 0>), dim3(batch), dim3(NT), bpl, st, a); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (L.tk > NT) return hipErrorInvalidValue;   // one lane per kept value, at most NT per matrix
     const int lpm = L.tk > 0 ? L.tk : 1;
-    const long long lanes = (long long)batch * lpm;
-    hipLaunchKernelGGL(k_eig_tri, dim3((unsigned)((lanes + 63) / 64)), dim3(64), 0, st, a, lpm);
+    const int mpb = 64 / lpm > 0 ? 64 / lpm : 1;
+    size_t tri_bytes = (size_t)2 * mpb * L.ns * sizeof(double);
+    const size_t lane_bytes = (size_t)mpb * lpm * 2 * L.ns * sizeof(double);
+    const int in_lds = tri_bytes + lane_bytes <= cap ? 1 : 0;
+    if (in_lds) tri_bytes += lane_bytes;
+    hipLaunchKernelGGL(k_eig_tri, dim3((unsigned)((batch + mpb - 1) / mpb)), dim3(mpb * lpm), tri_bytes, st,
+                       a, lpm, mpb, in_lds);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (bf <= cap) hipLaunchKernelGGL(k_eig_fin<true>, dim3(batch), dim3(NT), bf, st, a);

@@ -7,10 +7,7 @@ namespace peps {
 
 static constexpr int NT = 256;
 
-__device__ inline double wsum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ inline double wsum(double v) { return lane_group_sum(v, 64); }
 __device__ inline double wmax(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;

@@ -17,14 +17,9 @@
 namespace peps {
 
 static constexpr int NT = 256;
-static constexpr double kTiny = 1e-292;
-static constexpr int kQrRegMaxM = 1024;   // squared-norm floor of the Jacobi rotations
+static constexpr double kTiny = 1e-292;    // squared-norm floor of the Jacobi rotations
 
-
-__device__ inline double wave_sum(double v, int width) {
-    for (int o = width / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ inline double wave_sum(double v, int width) { return lane_group_sum(v, width); }
 
 // Sum over the whole workgroup; every thread gets the result.
 __device__ inline double block_sum(double v, double* red) {

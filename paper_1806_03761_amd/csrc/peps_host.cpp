@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/peps.h"
+#include "peps.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -797,6 +797,7 @@ static peps_status check_lat(peps_ctx* c, const peps_lattice* lat) {
     if (lat->D < 1 || lat->Dc < 1) return fail(c, PEPS_ERR_INVALID_ARG, "D and Dc must be >= 1");
     if (lat->Lx > 4096 || lat->Ly > 4096) return fail(c, PEPS_ERR_UNSUPPORTED, "lattice too large");
     if (lat->D > 16) return fail(c, PEPS_ERR_UNSUPPORTED, "D > 16 is not supported");
+    if (lat->Dc > 256) return fail(c, PEPS_ERR_UNSUPPORTED, "Dc > 256 is not supported");
     return PEPS_OK;
 }
 
