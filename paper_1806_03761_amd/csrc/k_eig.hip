@@ -215,6 +215,127 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
     __syncthreads();
 }
 
+// Z = Q [G; 0] with Z held in registers: group g of TPC lanes owns the columns g, g + NG, ...
+// (NG = NT / TPC), lane l the row pairs (2l, 2l+1) + 2 TPC j, so one 16-byte LDS read of a
+// reflector serves CPG columns.  Reflectors are staged kc at a time through LDS, zero
+// below their first row and with the unit leading entry written out (one barrier per
+// chunk).  The result goes to the Z slot of the per-matrix scratch.
+static constexpr int kMaxKc = 32;
+
+template <int TPC>
+__device__ __forceinline__ int zq_row(int q, int l) {
+    return (q >> 1) * (2 * TPC) + 2 * l + (q & 1);
+}
+
+template <int RPT, int TPC, int CPG>
+__global__ __launch_bounds__(NT) void k_eig_applyq(EigArgs a, int kc) {
+    extern __shared__ __align__(16) double vsh[];
+    __shared__ double s_tq[kMaxKc];
+    constexpr int NG = NT / TPC, LDV = RPT * TPC;
+    const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
+    const int b = blockIdx.x, tid = threadIdx.x, g = tid / TPC, l = tid % TPC;
+    const int mz = a.mz, tin = a.tin, r = a.r, ldz = L.ldz;
+    const double* G = a.G + (long long)b * a.gs;
+    const double* V = a.V + (long long)b * a.vs;
+    const double* tq = a.tau + (long long)b * a.ts;
+    double z[CPG][RPT];
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = zq_row<TPC>(q, l);
+            z[s][q] = (c < tin && i < r) ? G[(long long)i * tin + c] : 0.0;
+        }
+    }
+    for (int k1 = r - 1; k1 >= 0; k1 -= kc) {
+        const int k0 = k1 - kc + 1 > 0 ? k1 - kc + 1 : 0, nk = k1 - k0 + 1;
+        __syncthreads();
+        for (int e = tid; e < nk * LDV; e += NT) {
+            const int kk = e / LDV, i = e % LDV, k = k0 + kk;
+            vsh[e] = (i < k || i >= mz) ? 0.0 : (i == k ? 1.0 : V[(long long)k * mz + i]);
+        }
+        if (tid < nk) s_tq[tid] = tq[k0 + tid];
+        __syncthreads();
+        for (int k = k1; k >= k0; --k) {
+            const double tk = s_tq[k - k0];
+            if (tk == 0.0) continue;
+            const double* vk = vsh + (k - k0) * LDV;
+            double v[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; q += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(vk + zq_row<TPC>(q, l));
+                v[q] = t.x;
+                v[q + 1] = t.y;
+            }
+#pragma unroll
+            for (int s = 0; s < CPG; ++s) {
+                if (g + s * NG >= tin) continue;
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int q = 0; q < RPT; q += 2) {
+                    d0 = fma(v[q], z[s][q], d0);
+                    d1 = fma(v[q + 1], z[s][q + 1], d1);
+                }
+                const double f = tk * lane_group_sum(d0 + d1, TPC);
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) z[s][q] = fma(-f, v[q], z[s][q]);
+            }
+        }
+    }
+    double* Z = a.scratch + (long long)b * a.ss + L.oZ;
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+        if (c >= tin) continue;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = zq_row<TPC>(q, l);
+            if (i < mz) Z[(long long)c * ldz + i] = z[s][q];
+        }
+    }
+}
+
+// launch k_eig_applyq for the first lane-group width (16, 32, 64) whose register
+// blocking fits mz x tin (16 measured fastest at mz = 256, tin = 16); false when none
+// does (the prep kernel then applies Q itself)
+template <int TPC>
+static bool applyq_t(const EigArgs& a, size_t cap, hipStream_t st) {
+    constexpr int NG = NT / TPC;
+    int rpt = (a.mz + TPC - 1) / TPC;
+    rpt += rpt & 1;
+    const int cpg = (a.tin + NG - 1) / NG;
+#define AQ_LAUNCH(RPT_, CPG_)                                                                   \
+    if (rpt <= RPT_ && cpg <= CPG_) {                                                             \
+        const size_t ldv = (size_t)RPT_ * TPC;                                                    \
+        int kc = (int)(cap / (ldv * sizeof(double)));                                             \
+        kc = kc > kMaxKc ? kMaxKc : kc;                                                           \
+        kc = kc > a.r ? a.r : kc;                                                                 \
+        if (kc < 1) return false;                                                                 \
+        hipLaunchKernelGGL((k_eig_applyq<RPT_, TPC, CPG_>), dim3(a.batch), dim3(NT),              \
+                           (size_t)kc * ldv * sizeof(double), st, a, kc);                         \
+        return true;                                                                              \
+    }
+    AQ_LAUNCH(2, 1)
+    AQ_LAUNCH(4, 1)
+    AQ_LAUNCH(2, 2)
+    AQ_LAUNCH(8, 1)
+    AQ_LAUNCH(4, 2)
+    AQ_LAUNCH(2, 4)
+    AQ_LAUNCH(16, 1)
+    AQ_LAUNCH(8, 2)
+    AQ_LAUNCH(4, 4)
+    AQ_LAUNCH(16, 2)
+    AQ_LAUNCH(8, 4)
+#undef AQ_LAUNCH
+    return false;
+}
+
+static bool launch_applyq(const EigArgs& a, size_t cap, hipStream_t st) {
+    if (!a.V || a.r <= 0) return false;
+    return applyq_t<16>(a, cap, st) || applyq_t<32>(a, cap, st) || applyq_t<64>(a, cap, st);
+}
+
 template <bool kLds, int RB>
 __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, double* e, double* tau,
                           double* vbuf, const EigLayout& L, double* red) {
@@ -224,12 +345,20 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
     // Group c owns column c of Z.
     const double* G = a.G + (long long)b * a.gs;
     const int r = a.V ? a.r : mz;
-    for (int e2 = tid; e2 < mz * tin; e2 += NT) {
-        const int c = e2 / mz, i = e2 % mz;
-        Z[(long long)c * ldz + i] = (i < r) ? G[(long long)i * tin + c] : 0.0;
+    if (a.z_ready) {
+        // Z = Q [G; 0] was formed by k_eig_applyq in global scratch
+        if constexpr (kLds) {
+            const double* zg = a.scratch + (long long)b * a.ss + L.oZ;
+            for (long long e2 = tid; e2 < (long long)ldz * tin; e2 += NT) Z[e2] = zg[e2];
+        }
+    } else {
+        for (int e2 = tid; e2 < mz * tin; e2 += NT) {
+            const int c = e2 / mz, i = e2 % mz;
+            Z[(long long)c * ldz + i] = (i < r) ? G[(long long)i * tin + c] : 0.0;
+        }
     }
     __syncthreads();
-    if (a.V) {
+    if (a.V && !a.z_ready) {
         const double* V = a.V + (long long)b * a.vs;
         const double* tq = a.tau + (long long)b * a.ts;
         const int tpc = e_tpc(tin), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
@@ -433,7 +562,8 @@ __global__ __launch_bounds__(NT) void k_eig_prep(EigArgs a) {
         prep_body<true, RB>(a, Z, Am, d, e, tau, vbuf, L, red);
         // hand over Z, reflectors, d, e, tau
         const int tid = threadIdx.x;
-        for (long long i = tid; i < (long long)L.ldz * a.tin; i += NT) gs[L.oZ + i] = Z[i];
+        if (!a.z_ready)
+            for (long long i = tid; i < (long long)L.ldz * a.tin; i += NT) gs[L.oZ + i] = Z[i];
         for (long long i = tid; i < (long long)L.lda * L.ns; i += NT) gs[L.oA + i] = Am[i];
         for (int i = tid; i < L.ns; i += NT) {
             gs[L.oD + i] = d[i];
@@ -699,9 +829,15 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     a.V = V; a.vs = vs; a.tau = tau; a.ts = ts; a.G = G; a.gs = gs;
     a.mz = mz; a.r = r; a.tin = tin; a.p = p; a.Dc = Dc;
     a.newU = newU; a.us = us; a.Gout = Gout; a.gos = gos;
-    a.scratch = scratch; a.ss = ss; a.batch = batch;
+    a.scratch = scratch; a.ss = ss; a.batch = batch; a.z_ready = 0;
     const EigLayout L = eig_layout(mz, tin, p, Dc);
     const size_t cap = get_lds_cap() - 1024;
+    // staging for k_eig_applyq: at most a quarter of the LDS so several blocks share a CU
+    a.z_ready = launch_applyq(a, cap / 4, st) ? 1 : 0;
+    if (a.z_ready) {
+        hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return e0;
+    }
     const size_t bp = (size_t)L.lds_prep * sizeof(double), bf = (size_t)L.lds_fin * sizeof(double);
     const bool in_lds_prep = bp <= cap;
     const size_t bpl = in_lds_prep ? bp : 0;

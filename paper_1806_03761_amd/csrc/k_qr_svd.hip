@@ -281,6 +281,179 @@ static bool launch_qr_reg_wg(double* X, long long xs, int m, int n, double* R, l
 }
 
 // ---------------------------------------------------------------------------
+// Column-group QR: each group of TPC lanes owns CPG columns (c = g, g + NG, ...; NG =
+// WG / TPC groups), lane l the row pairs (2l, 2l+1) + 2 TPC j, so one reflector read
+// (a 16-byte LDS load per row pair) serves CPG columns and every dependent chain is
+// RPT long.  Step k: groups apply reflector k-1 to their columns >= k; the group of
+// column k then forms reflector k (LAPACK dlarfg convention, v_k = 1) and publishes it
+// zero-padded with tau in a double-buffered LDS slot.  One barrier per step.
+// ---------------------------------------------------------------------------
+template <int TPC>
+__device__ __forceinline__ int qc_row(int q, int l) {
+    return (q >> 1) * (2 * TPC) + 2 * l + (q & 1);
+}
+
+template <int RPT, int TPC>
+__device__ __forceinline__ void qc_pivot(double (&a)[RPT], int k, int m, int l, double* vslot,
+                                         double* tslot, double* tau_out) {
+    double s0 = 0.0, s1 = 0.0, al = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = qc_row<TPC>(q, l);
+        const double x = (i > k) ? a[q] : 0.0;
+        if (q & 1) s1 = fma(x, x, s1);
+        else s0 = fma(x, x, s0);
+        al = (i == k) ? a[q] : al;
+    }
+    const double s = lane_group_sum(s0 + s1, TPC);
+    al = lane_group_sum(al, TPC);
+    double tk, be, sc;
+    if (s == 0.0) {
+        tk = 0.0; be = al; sc = 0.0;
+    } else {
+        be = -copysign(sqrt(al * al + s), al);
+        tk = (be - al) / be;
+        sc = 1.0 / (al - be);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; q += 2) {
+        const int i = qc_row<TPC>(q, l);
+        const double v0 = (i < k || i >= m) ? 0.0 : (i == k ? 1.0 : sc * a[q]);
+        const double v1 = (i + 1 < k || i + 1 >= m) ? 0.0 : (i + 1 == k ? 1.0 : sc * a[q + 1]);
+        *reinterpret_cast<double2*>(vslot + i) = make_double2(v0, v1);
+        a[q] = (i == k) ? be : ((i > k && tk != 0.0) ? v0 : a[q]);
+        a[q + 1] = (i + 1 == k) ? be : ((i + 1 > k && tk != 0.0) ? v1 : a[q + 1]);
+    }
+    if (l == 0) {
+        *tslot = tk;
+        *tau_out = tk;
+    }
+}
+
+template <int RPT, int TPC, int CPG, int WG>
+__global__ __launch_bounds__(WG) void k_qr_cols(double* X, long long xs, int m, int n, double* R,
+                                                long long rs, double* tau, long long ts) {
+    constexpr int NG = WG / TPC;
+    __shared__ __align__(16) double xcol[2][RPT * TPC];
+    __shared__ double sh_t[2];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int g = tid / TPC, l = tid % TPC;
+    const int r = min(m, n);
+    double* Xg = X + (long long)b * xs;
+    double* taub = tau + (long long)b * ts;
+    double a[CPG][RPT];
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = qc_row<TPC>(q, l);
+            a[s][q] = (c < n && i < m) ? Xg[(long long)c * m + i] : 0.0;
+        }
+    }
+    for (int k = 0; k <= r; ++k) {
+        if (k > 0) {
+            const int bk = (k - 1) & 1;
+            const double tk = sh_t[bk];
+            if (tk != 0.0 && g + (CPG - 1) * NG >= k) {
+                double v[RPT];
+#pragma unroll
+                for (int q = 0; q < RPT; q += 2) {
+                    const double2 t = *reinterpret_cast<const double2*>(xcol[bk] + qc_row<TPC>(q, l));
+                    v[q] = t.x;
+                    v[q + 1] = t.y;
+                }
+#pragma unroll
+                for (int s = 0; s < CPG; ++s) {
+                    const int c = g + s * NG;
+                    if (c >= k && c < n) {
+                        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                        for (int q = 0; q < RPT; q += 2) {
+                            d0 = fma(v[q], a[s][q], d0);
+                            d1 = fma(v[q + 1], a[s][q + 1], d1);
+                        }
+                        const double f = tk * lane_group_sum(d0 + d1, TPC);
+#pragma unroll
+                        for (int q = 0; q < RPT; ++q) a[s][q] = fma(-f, v[q], a[s][q]);
+                    }
+                }
+            }
+        }
+        if (k < r && g == k % NG) {
+            const int sk = k / NG;
+#pragma unroll
+            for (int s = 0; s < CPG; ++s)
+                if (s == sk) qc_pivot<RPT, TPC>(a[s], k, m, l, xcol[k & 1], &sh_t[k & 1], &taub[k]);
+        }
+        __syncthreads();
+    }
+    double* Rb = R + (long long)b * rs;
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+        if (c >= n) continue;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = qc_row<TPC>(q, l);
+            if (i < m) Xg[(long long)c * m + i] = a[s][q];
+            if (i < r) Rb[(long long)i * n + c] = (i <= c) ? a[s][q] : 0.0;
+        }
+    }
+}
+
+template <int RPT, int CPG, int TPC, int WG>
+static bool qc_try(int rpt, int cpg, double* X, long long xs, int m, int n, double* R, long long rs,
+                   double* tau, long long ts, int batch, hipStream_t st) {
+    if constexpr (WG >= 1024 && (RPT * CPG > 32 || RPT * CPG + RPT > 40)) {
+        return false;   // would spill at the 128-register limit of 1024-thread groups
+    } else {
+        if (rpt > RPT || cpg > CPG) return false;
+        hipLaunchKernelGGL((k_qr_cols<RPT, TPC, CPG, WG>), dim3(batch), dim3(WG), 0, st, X, xs, m, n, R,
+                           rs, tau, ts);
+        return true;
+    }
+}
+
+template <int TPC, int WG>
+static bool launch_qr_cols_t(double* X, long long xs, int m, int n, double* R, long long rs,
+                             double* tau, long long ts, int batch, hipStream_t st) {
+    constexpr int NG = WG / TPC;
+    const int cpg = (n + NG - 1) / NG;
+    int rpt = (m + TPC - 1) / TPC;
+    rpt += rpt & 1;
+#define QC(RPT_, CPG_) qc_try<RPT_, CPG_, TPC, WG>(rpt, cpg, X, xs, m, n, R, rs, tau, ts, batch, st)
+    return QC(4, 1) || QC(8, 1) || QC(4, 2) || QC(16, 1) || QC(8, 2) || QC(4, 4) || QC(16, 2) ||
+           QC(8, 4) || QC(32, 1) || QC(2, 8) || QC(4, 8) || QC(16, 4) || QC(8, 8);
+#undef QC
+}
+
+bool launch_qr_cols(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
+                    long long ts, int batch, int tpc, int wg, hipStream_t st) {
+    if (m <= 0 || n <= 0) return false;
+    if (wg == 256) {
+        switch (tpc) {
+            case 8: return launch_qr_cols_t<8, 256>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 16: return launch_qr_cols_t<16, 256>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 32: return launch_qr_cols_t<32, 256>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 64: return launch_qr_cols_t<64, 256>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        }
+    } else if (wg == 512) {
+        switch (tpc) {
+            case 16: return launch_qr_cols_t<16, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 32: return launch_qr_cols_t<32, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 64: return launch_qr_cols_t<64, 512>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        }
+    } else if (wg == 1024) {
+        switch (tpc) {
+            case 32: return launch_qr_cols_t<32, 1024>(X, xs, m, n, R, rs, tau, ts, batch, st);
+            case 64: return launch_qr_cols_t<64, 1024>(X, xs, m, n, R, rs, tau, ts, batch, st);
+        }
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
 // implicit Q: Z (column-major mz x tin, stride ldz) <- H_0 H_1 ... H_{r-1} Z
 // V column-major mz x r (reflector k in column k below the diagonal, unit diagonal).
 // ---------------------------------------------------------------------------
@@ -585,6 +758,7 @@ static size_t lds_cap() { return get_lds_cap(); }
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
+    if (launch_qr_cols(X, xs, m, n, R, rs, tau, ts, batch, 32, 512, st)) return hipGetLastError();
     if (n <= 64) {
         if (launch_qr_reg_wg<256>(X, xs, m, n, R, rs, tau, ts, batch, st) ||
             launch_qr_reg_wg<512>(X, xs, m, n, R, rs, tau, ts, batch, st))

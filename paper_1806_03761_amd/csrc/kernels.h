@@ -10,6 +10,10 @@ static constexpr int kGemmTiles = 7;
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();
 
+// column-group QR with TPC lanes per column group in WG-thread workgroups; false when the
+// shape does not fit that configuration (nothing launched)
+bool launch_qr_cols(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
+                    long long ts, int batch, int tpc, int wg, hipStream_t st);
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st);
 size_t svd_scratch_doubles(int mz, int tin, int p);
@@ -37,6 +41,7 @@ struct EigArgs {
     double* Gout; long long gos;
     double* scratch; long long ss;
     int batch;
+    int z_ready;   // set by the launcher: Z = Q [G; 0] already in the scratch Z slot
 };
 size_t eig_scratch_doubles(int mz, int tin, int p, int Dc);
 hipError_t launch_eig(const double* V, long long vs, const double* tau, long long ts, const double* G,
