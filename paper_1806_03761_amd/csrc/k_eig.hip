@@ -693,7 +693,122 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix
 // ---------------------------------------------------------------------------
 // C: orthonormalise, back-transform, outputs
 // ---------------------------------------------------------------------------
-template <bool kLds>
+// Orthonormalisation and back-transformation with the t vectors in registers: group g
+// of TPC lanes owns the vectors g, g + NG, ... (NG = NT / TPC), lane l the row pairs
+// (2l, 2l+1) + 2 TPC j.
+//   modified Gram-Schmidt, twice, right-looking: the group of vector j normalises it and
+//   publishes it (double-buffered LDS), every later vector then removes its component
+//   (one barrier per vector);
+//   back-transformation X <- H_0 ... H_{ns-3} X with the reflectors read from Am rows
+//   (no barriers: X stays in registers).
+// X (LDS or global, stride ldx) holds the result on return.
+template <int RPT, int TPC, int CPG>
+__device__ __forceinline__ void fin_vectors(double* X, const double* Am, const double* tau, int ns, int tk,
+                                            int ldx, int lda) {
+    constexpr int NG = NT / TPC, LDQ = RPT * TPC;
+    __shared__ __align__(16) double qbuf[2][LDQ];
+    const int tid = threadIdx.x, g = tid / TPC, l = tid % TPC;
+    double x[CPG][RPT];
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = zq_row<TPC>(q, l);
+            x[s][q] = (c < tk && i < ns) ? X[(long long)c * ldx + i] : 0.0;
+        }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < tk; ++j) {
+            double* qj = qbuf[j & 1];
+            if (g == j % NG) {
+                const int sj = j / NG;
+#pragma unroll
+                for (int s = 0; s < CPG; ++s) {
+                    if (s != sj) continue;
+                    double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < RPT; q += 2) {
+                        n0 = fma(x[s][q], x[s][q], n0);
+                        n1 = fma(x[s][q + 1], x[s][q + 1], n1);
+                    }
+                    const double nr = lane_group_sum(n0 + n1, TPC);
+                    const double sc = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+#pragma unroll
+                    for (int q = 0; q < RPT; q += 2) {
+                        x[s][q] *= sc;
+                        x[s][q + 1] *= sc;
+                        *reinterpret_cast<double2*>(qj + zq_row<TPC>(q, l)) = make_double2(x[s][q], x[s][q + 1]);
+                    }
+                }
+            }
+            __syncthreads();
+            double qv[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; q += 2) {
+                const double2 t = *reinterpret_cast<const double2*>(qj + zq_row<TPC>(q, l));
+                qv[q] = t.x;
+                qv[q + 1] = t.y;
+            }
+#pragma unroll
+            for (int s = 0; s < CPG; ++s) {
+                const int c = g + s * NG;
+                if (c <= j || c >= tk) continue;
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int q = 0; q < RPT; q += 2) {
+                    d0 = fma(qv[q], x[s][q], d0);
+                    d1 = fma(qv[q + 1], x[s][q + 1], d1);
+                }
+                const double dot = lane_group_sum(d0 + d1, TPC);
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) x[s][q] = fma(-dot, qv[q], x[s][q]);
+            }
+        }
+    }
+    // reflector k: unit entry at row k+1, entries beyond it in row k of Am
+    for (int k = ns - 3; k >= 0; --k) {
+        const double tq = tau[k];
+        if (tq == 0.0) continue;
+        const double* vk = Am + (long long)k * lda;
+        double v[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = zq_row<TPC>(q, l);
+            double vi = 0.0;
+            if (i == k + 1) vi = 1.0;
+            else if (i > k + 1 && i < ns) vi = vk[i];
+            v[q] = vi;
+        }
+#pragma unroll
+        for (int s = 0; s < CPG; ++s) {
+            if (g + s * NG >= tk) continue;
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; q += 2) {
+                d0 = fma(v[q], x[s][q], d0);
+                d1 = fma(v[q + 1], x[s][q + 1], d1);
+            }
+            const double f = tq * lane_group_sum(d0 + d1, TPC);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) x[s][q] = fma(-f, v[q], x[s][q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < CPG; ++s) {
+        const int c = g + s * NG;
+        if (c >= tk) continue;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = zq_row<TPC>(q, l);
+            if (i < ns) X[(long long)c * ldx + i] = x[s][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool kLds, int RPT, int TPC, int CPG>
 __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
     extern __shared__ double lds[];
     const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
@@ -716,51 +831,55 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
     } else {
         X = gs + L.oX; Am = gs + L.oA; tau = gs + L.oT; Z = gs + L.oZ; lam = gs + L.oL;
     }
-    // modified Gram-Schmidt, twice, by wave 0 (lanes own rows)
-    if (tid < 64) {
-        for (int pass = 0; pass < 2; ++pass)
-            for (int j = 0; j < tk; ++j) {
-                double* xj = X + (long long)j * ldx;
-                for (int i = 0; i < j; ++i) {
-                    const double* xi = X + (long long)i * ldx;
-                    double dot = 0.0;
-                    for (int r = tid; r < ns; r += 64) dot += xi[r] * xj[r];
-                    dot = e_wave_sum(dot, 64);
-                    for (int r = tid; r < ns; r += 64) xj[r] -= dot * xi[r];
+    if constexpr (RPT > 0) {
+        fin_vectors<RPT, TPC, CPG>(X, Am, tau, ns, tk, ldx, lda);
+    } else {
+        // modified Gram-Schmidt, twice, by wave 0 (lanes own rows)
+        if (tid < 64) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (int j = 0; j < tk; ++j) {
+                    double* xj = X + (long long)j * ldx;
+                    for (int i = 0; i < j; ++i) {
+                        const double* xi = X + (long long)i * ldx;
+                        double dot = 0.0;
+                        for (int r = tid; r < ns; r += 64) dot += xi[r] * xj[r];
+                        dot = e_wave_sum(dot, 64);
+                        for (int r = tid; r < ns; r += 64) xj[r] -= dot * xi[r];
+                    }
+                    double nr = 0.0;
+                    for (int r = tid; r < ns; r += 64) nr += xj[r] * xj[r];
+                    nr = e_wave_sum(nr, 64);
+                    const double s = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+                    for (int r = tid; r < ns; r += 64) xj[r] *= s;
                 }
-                double nr = 0.0;
-                for (int r = tid; r < ns; r += 64) nr += xj[r] * xj[r];
-                nr = e_wave_sum(nr, 64);
-                const double s = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-                for (int r = tid; r < ns; r += 64) xj[r] *= s;
-            }
-    }
-    __syncthreads();
-    // back-transformation: X <- H_0 ... H_{ns-3} X (reflector k acts on rows k+1..; its
-    // entries beyond k+1 are stored in Am row k).  Group c owns vector c, lane l the rows
-    // i = l (mod tpc), so no barrier is needed between reflectors.
-    {
-        const int tpc = e_tpc(tk), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
-        for (int c0 = 0; c0 < tk; c0 += ngroups) {
-            const int c = c0 + g;
-            const bool act = c < tk;
-            double* xc = X + (long long)(act ? c : 0) * ldx;
-            for (int k = ns - 3; k >= 0; --k) {
-                const double tq = tau[k];
-                if (tq == 0.0) continue;
-                const double* vk = Am + (long long)k * lda;
-                const int i0 = (k + 1) + (((l - k - 1) % tpc) + tpc) % tpc;   // first own row > k
-                double dot = 0.0;
-                if (act)
-                    for (int i = i0; i < ns; i += tpc) dot += ((i == k + 1) ? 1.0 : vk[i]) * xc[i];
-                dot = e_wave_sum(dot, tpc);
-                if (act) {
-                    const double f = tq * dot;
-                    for (int i = i0; i < ns; i += tpc) xc[i] -= f * ((i == k + 1) ? 1.0 : vk[i]);
-                }
-            }
         }
         __syncthreads();
+        // back-transformation: X <- H_0 ... H_{ns-3} X (reflector k acts on rows k+1..; its
+        // entries beyond k+1 are stored in Am row k).  Group c owns vector c, lane l the rows
+        // i = l (mod tpc), so no barrier is needed between reflectors.
+        {
+            const int tpc = e_tpc(tk), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
+            for (int c0 = 0; c0 < tk; c0 += ngroups) {
+                const int c = c0 + g;
+                const bool act = c < tk;
+                double* xc = X + (long long)(act ? c : 0) * ldx;
+                for (int k = ns - 3; k >= 0; --k) {
+                    const double tq = tau[k];
+                    if (tq == 0.0) continue;
+                    const double* vk = Am + (long long)k * lda;
+                    const int i0 = (k + 1) + (((l - k - 1) % tpc) + tpc) % tpc;   // first own row > k
+                    double dot = 0.0;
+                    if (act)
+                        for (int i = i0; i < ns; i += tpc) dot += ((i == k + 1) ? 1.0 : vk[i]) * xc[i];
+                    dot = e_wave_sum(dot, tpc);
+                    if (act) {
+                        const double f = tq * dot;
+                        for (int i = i0; i < ns; i += tpc) xc[i] -= f * ((i == k + 1) ? 1.0 : vk[i]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
     double* U = a.newU + (long long)b * a.us;
     double* Go = a.Gout + (long long)b * a.gos;
@@ -815,6 +934,29 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
     }
 }
 
+// k_eig_fin with register-resident vectors (16-lane groups) when ns and tk fit one of the
+// blockings; false when none does
+template <int RPT, int CPG>
+static bool fin_try(const EigArgs& a, int rpt, int cpg, size_t bf, size_t cap, hipStream_t st) {
+    if (rpt > RPT || cpg > CPG) return false;
+    const size_t stat = 2 * (size_t)RPT * 16 * sizeof(double);   // the qbuf double buffer
+    if (bf + stat <= cap) hipLaunchKernelGGL((k_eig_fin<true, RPT, 16, CPG>), dim3(a.batch), dim3(NT), bf, st, a);
+    else hipLaunchKernelGGL((k_eig_fin<false, RPT, 16, CPG>), dim3(a.batch), dim3(NT), 0, st, a);
+    return true;
+}
+
+static bool launch_fin_reg(const EigArgs& a, const EigLayout& L, size_t bf, size_t cap, hipStream_t st) {
+    constexpr int NG = NT / 16;
+    int rpt = (L.ns + 15) / 16;
+    rpt += rpt & 1;
+    const int cpg = (L.tk + NG - 1) / NG;
+    return fin_try<2, 1>(a, rpt, cpg, bf, cap, st) || fin_try<4, 1>(a, rpt, cpg, bf, cap, st) ||
+           fin_try<2, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 1>(a, rpt, cpg, bf, cap, st) ||
+           fin_try<4, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 2>(a, rpt, cpg, bf, cap, st) ||
+           fin_try<4, 4>(a, rpt, cpg, bf, cap, st) || fin_try<16, 1>(a, rpt, cpg, bf, cap, st) ||
+           fin_try<16, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 4>(a, rpt, cpg, bf, cap, st);
+}
+
 // ---------------------------------------------------------------------------
 size_t eig_scratch_doubles(int mz, int tin, int p, int Dc) {
     return (size_t)eig_layout(mz, tin, p, Dc).total;
@@ -864,8 +1006,10 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
                        a, lpm, mpb, in_lds);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (bf <= cap) hipLaunchKernelGGL(k_eig_fin<true>, dim3(batch), dim3(NT), bf, st, a);
-    else hipLaunchKernelGGL(k_eig_fin<false>, dim3(batch), dim3(NT), 0, st, a);
+    if (!launch_fin_reg(a, L, bf, cap, st)) {
+        if (bf <= cap) hipLaunchKernelGGL((k_eig_fin<true, 0, 0, 0>), dim3(batch), dim3(NT), bf, st, a);
+        else hipLaunchKernelGGL((k_eig_fin<false, 0, 0, 0>), dim3(batch), dim3(NT), 0, st, a);
+    }
     return hipGetLastError();
 }
 
