@@ -215,6 +215,62 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
     __syncthreads();
 }
 
+// Gram matrix of M (full symmetric storage, stride lda) with 4x4 register blocks per
+// thread, read straight from Z (column-major, stride ldz):
+//   gram_right: A[c1][c2] = sum_ar M[ar][c1] M[ar][c2]   (x = column c, y = row ar)
+//   else:       A[a1][a2] = sum_col M[a1][col] M[a2][col] (x = row a, y = column col)
+// M[ar][col] = Z[t][ar*p+d] with col = d*tin + t, i.e. element (x, y) = Z[bx(x) + by(y)].
+__device__ inline void gram_4x4(const double* Z, int ldz, double* Am, int lda, const EigLayout& L, int tin,
+                                int p) {
+    const int tid = threadIdx.x, ns = L.ns;
+    const int ny = L.gram_right ? L.mp : L.np;
+    auto bx = [&](int x) -> int {
+        return L.gram_right ? (x % tin) * ldz + x / tin : x * p;
+    };
+    auto by = [&](int y) -> int {
+        return L.gram_right ? y * p : (y % tin) * ldz + y / tin;
+    };
+    const int nb = (ns + 3) / 4;                 // 4x4 blocks per dimension
+    for (int blk = tid; blk < nb * nb; blk += NT) {
+        const int bi = blk / nb, bj = blk % nb;
+        if (bj < bi) continue;
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
+        int oi[4], oj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            oi[u] = bx(min(bi * 4 + u, ns - 1));
+            oj[u] = bx(min(bj * 4 + u, ns - 1));
+        }
+        for (int y = 0; y < ny; ++y) {
+            const double* zy = Z + by(y);
+            double a4[4], b4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a4[u] = zy[oi[u]];
+                b4[u] = zy[oj[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc[u][w] = fma(a4[u], b4[w], acc[u][w]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int ii = bi * 4 + u, jj = bj * 4 + w;
+                if (ii < ns && jj < ns && jj >= ii) {
+                    Am[(long long)ii * lda + jj] = acc[u][w];
+                    Am[(long long)jj * lda + ii] = acc[u][w];
+                }
+            }
+    }
+}
+
 // Z = Q [G; 0] with Z held in registers: group g of TPC lanes owns the columns g, g + NG, ...
 // (NG = NT / TPC), lane l the row pairs (2l, 2l+1) + 2 TPC j, so one 16-byte LDS read of a
 // reflector serves CPG columns.  Reflectors are staged kc at a time through LDS, zero
@@ -283,7 +339,9 @@ __global__ __launch_bounds__(NT) void k_eig_applyq(EigArgs a, int kc) {
             }
         }
     }
-    double* Z = a.scratch + (long long)b * a.ss + L.oZ;
+    double* gsb = a.scratch + (long long)b * a.ss;
+    double* Z = gsb + L.oZ;
+    if (a.gram_ready) __syncthreads();   // the staging buffer now takes Z
 #pragma unroll
     for (int s = 0; s < CPG; ++s) {
         const int c = g + s * NG;
@@ -291,16 +349,34 @@ __global__ __launch_bounds__(NT) void k_eig_applyq(EigArgs a, int kc) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int i = zq_row<TPC>(q, l);
-            if (i < mz) Z[(long long)c * ldz + i] = z[s][q];
+            if (i < mz) {
+                Z[(long long)c * ldz + i] = z[s][q];
+                if (a.gram_ready) vsh[(long long)c * ldz + i] = z[s][q];
+            }
         }
     }
+    if (a.gram_ready) {
+        // Gram matrix of the reshaped centre, from the LDS copy of Z, into the Am slot
+        __syncthreads();
+        gram_4x4(vsh, ldz, gsb + L.oA, L.lda, L, tin, a.p);
+    }
+}
+
+// Householder tridiagonalisation of the Gram matrix formed by k_eig_applyq (order
+// <= 16 RB), A in registers; reflectors, d, e and tau go straight to the scratch slots.
+template <int RB>
+__global__ __launch_bounds__(NT) void k_eig_tridiag(EigArgs a) {
+    __shared__ __align__(16) double vbuf[48 * RB];
+    const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
+    double* gs = a.scratch + (long long)blockIdx.x * a.ss;
+    tri_reg<RB>(gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, vbuf, L.ns, L.lda);
 }
 
 // launch k_eig_applyq for the first lane-group width (16, 32, 64) whose register
 // blocking fits mz x tin (16 measured fastest at mz = 256, tin = 16); false when none
 // does (the prep kernel then applies Q itself)
 template <int TPC>
-static bool applyq_t(const EigArgs& a, size_t cap, hipStream_t st) {
+static bool applyq_t(const EigArgs& a, size_t cap, size_t zbytes, hipStream_t st) {
     constexpr int NG = NT / TPC;
     int rpt = (a.mz + TPC - 1) / TPC;
     rpt += rpt & 1;
@@ -312,8 +388,10 @@ static bool applyq_t(const EigArgs& a, size_t cap, hipStream_t st) {
         kc = kc > kMaxKc ? kMaxKc : kc;                                                           \
         kc = kc > a.r ? a.r : kc;                                                                 \
         if (kc < 1) return false;                                                                 \
-        hipLaunchKernelGGL((k_eig_applyq<RPT_, TPC, CPG_>), dim3(a.batch), dim3(NT),              \
-                           (size_t)kc * ldv * sizeof(double), st, a, kc);                         \
+        size_t bytes = (size_t)kc * ldv * sizeof(double);                                         \
+        if (a.gram_ready && bytes < zbytes) bytes = zbytes;                                       \
+        hipLaunchKernelGGL((k_eig_applyq<RPT_, TPC, CPG_>), dim3(a.batch), dim3(NT), bytes, st,   \
+                           a, kc);                                                                \
         return true;                                                                              \
     }
     AQ_LAUNCH(2, 1)
@@ -331,9 +409,10 @@ static bool applyq_t(const EigArgs& a, size_t cap, hipStream_t st) {
     return false;
 }
 
-static bool launch_applyq(const EigArgs& a, size_t cap, hipStream_t st) {
+static bool launch_applyq(const EigArgs& a, size_t cap, size_t zbytes, hipStream_t st) {
     if (!a.V || a.r <= 0) return false;
-    return applyq_t<16>(a, cap, st) || applyq_t<32>(a, cap, st) || applyq_t<64>(a, cap, st);
+    return applyq_t<16>(a, cap, zbytes, st) || applyq_t<32>(a, cap, zbytes, st) ||
+           applyq_t<64>(a, cap, zbytes, st);
 }
 
 template <bool kLds, int RB>
@@ -397,58 +476,7 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
         }
         __syncthreads();
     }
-    // Gram matrix with 4x4 register blocks per thread, read straight from Z:
-    //   gram_right: A[c1][c2] = sum_ar M[ar][c1] M[ar][c2]   (x = column c, y = row ar)
-    //   else:       A[a1][a2] = sum_col M[a1][col] M[a2][col] (x = row a, y = column col)
-    // M[ar][col] = Z[t][ar*p+d] with col = d*tin + t, i.e. element (x, y) = Z[bx(x) + by(y)].
-    {
-        const int ny = L.gram_right ? L.mp : L.np;
-        auto bx = [&](int x) -> int {
-            return L.gram_right ? (x % tin) * ldz + x / tin : x * p;
-        };
-        auto by = [&](int y) -> int {
-            return L.gram_right ? y * p : (y % tin) * ldz + y / tin;
-        };
-        const int nb = (ns + 3) / 4;                 // 4x4 blocks per dimension
-        for (int blk = tid; blk < nb * nb; blk += NT) {
-            const int bi = blk / nb, bj = blk % nb;
-            if (bj < bi) continue;
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
-            int oi[4], oj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                oi[u] = bx(min(bi * 4 + u, ns - 1));
-                oj[u] = bx(min(bj * 4 + u, ns - 1));
-            }
-            for (int y = 0; y < ny; ++y) {
-                const double* zy = Z + by(y);
-                double a4[4], b4[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a4[u] = zy[oi[u]];
-                    b4[u] = zy[oj[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) acc[u][w] = fma(a4[u], b4[w], acc[u][w]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const int ii = bi * 4 + u, jj = bj * 4 + w;
-                    if (ii < ns && jj < ns && jj >= ii) {
-                        Am[(long long)ii * lda + jj] = acc[u][w];
-                        Am[(long long)jj * lda + ii] = acc[u][w];
-                    }
-                }
-        }
-    }
+    gram_4x4(Z, ldz, Am, lda, L, tin, p);
     if constexpr (RB > 0) {
         __syncthreads();
         tri_reg<RB>(Am, d, e, tau, vbuf, ns, lda);
@@ -971,11 +999,17 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     a.V = V; a.vs = vs; a.tau = tau; a.ts = ts; a.G = G; a.gs = gs;
     a.mz = mz; a.r = r; a.tin = tin; a.p = p; a.Dc = Dc;
     a.newU = newU; a.us = us; a.Gout = Gout; a.gos = gos;
-    a.scratch = scratch; a.ss = ss; a.batch = batch; a.z_ready = 0;
+    a.scratch = scratch; a.ss = ss; a.batch = batch; a.z_ready = 0; a.gram_ready = 0;
     const EigLayout L = eig_layout(mz, tin, p, Dc);
     const size_t cap = get_lds_cap() - 1024;
-    // staging for k_eig_applyq: at most a quarter of the LDS so several blocks share a CU
-    a.z_ready = launch_applyq(a, cap / 4, st) ? 1 : 0;
+    // staging for k_eig_applyq: at most a quarter of the LDS so several blocks share a CU;
+    // when the tridiagonalisation fits registers it also forms the Gram matrix (its
+    // staging buffer then has to hold Z)
+    const int rb = tri_rb(L.ns);
+    const size_t zbytes = (size_t)L.ldz * tin * sizeof(double);
+    a.gram_ready = (rb > 0 && zbytes <= cap / 4) ? 1 : 0;
+    a.z_ready = launch_applyq(a, cap / 4, zbytes, st) ? 1 : 0;
+    if (!a.z_ready) a.gram_ready = 0;
     if (a.z_ready) {
         hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess) return e0;
@@ -983,7 +1017,10 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const size_t bp = (size_t)L.lds_prep * sizeof(double), bf = (size_t)L.lds_fin * sizeof(double);
     const bool in_lds_prep = bp <= cap;
     const size_t bpl = in_lds_prep ? bp : 0;
-    switch (tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
+    switch (a.gram_ready ? -rb : tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
+        case -1: hipLaunchKernelGGL((k_eig_tridiag<1>), dim3(batch), dim3(NT), 0, st, a); break;
+        case -2: hipLaunchKernelGGL((k_eig_tridiag<2>), dim3(batch), dim3(NT), 0, st, a); break;
+        case -4: hipLaunchKernelGGL((k_eig_tridiag<4>), dim3(batch), dim3(NT), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_eig_prep<false, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
         case 3: hipLaunchKernelGGL((k_eig_prep<true, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
         case 4: hipLaunchKernelGGL((k_eig_prep<false, 2>), dim3(batch), dim3(NT), bpl, st, a); break;

@@ -41,7 +41,8 @@ struct EigArgs {
     double* Gout; long long gos;
     double* scratch; long long ss;
     int batch;
-    int z_ready;   // set by the launcher: Z = Q [G; 0] already in the scratch Z slot
+    int z_ready;      // set by the launcher: Z = Q [G; 0] already in the scratch Z slot
+    int gram_ready;   // set by the launcher: the Gram matrix already in the scratch Am slot
 };
 size_t eig_scratch_doubles(int mz, int tin, int p, int Dc);
 hipError_t launch_eig(const double* V, long long vs, const double* tau, long long ts, const double* G,
