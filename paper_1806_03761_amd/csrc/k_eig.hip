@@ -612,14 +612,26 @@ __device__ inline unsigned hash_u32(unsigned x) {
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix, int mats_per_block,
-                                                 int tri_lanes_in_lds) {
+// 1/q by the hardware reciprocal estimate refined with one Newton-Raphson step
+// (r <- r + r (1 - q r)), which roughly doubles the estimate's correct bits.  Used only
+// in the Sturm recurrence, whose sign count is backward stable to such rounding.
+__device__ inline double sturm_rcp(double q) {
+    const double r = __builtin_amdgcn_rcp(q);
+    return fma(fma(-q, r, 1.0), r, r);
+}
+
+// Block = mats_per_block matrices x tk eigenvalues x S sub-lanes.  The S sub-lanes of an
+// eigenvalue (aligned, consecutive lanes) evaluate the Sturm count at S interior points
+// of the common interval, which therefore shrinks by S + 1 per step (multisection); all
+// of them then hold the same interval.  Sub-lane 0 runs the inverse iteration.
+__global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_block, int tri_lanes_in_lds) {
     extern __shared__ double tri_lds[];
     const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
-    const int n = L.ns;
-    const int mi = threadIdx.x / lanes_per_matrix, l = threadIdx.x % lanes_per_matrix;
+    const int n = L.ns, tk = L.tk;
+    const int lpm = tk * S;
+    const int mi = threadIdx.x / lpm, le = threadIdx.x % lpm, l = le / S, sub = le % S;
     const int b = blockIdx.x * mats_per_block + mi;
-    // d and e of this block's matrices in LDS (every Sturm step reads all of them)
+    // d, e and e^2 of this block's matrices in LDS (every Sturm step reads them)
     for (int e2 = threadIdx.x; e2 < mats_per_block * n; e2 += blockDim.x) {
         const int m2 = e2 / n, i = e2 % n;
         const int b2 = blockIdx.x * mats_per_block + m2;
@@ -629,57 +641,77 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix
             dv = g2[L.oD + i];
             ev = (i + 1 < n) ? g2[L.oE + i] : 0.0;
         }
-        tri_lds[(2 * m2) * n + i] = dv;
-        tri_lds[(2 * m2 + 1) * n + i] = ev;
+        tri_lds[(3 * m2) * n + i] = dv;
+        tri_lds[(3 * m2 + 1) * n + i] = ev;
+        tri_lds[(3 * m2 + 2) * n + i] = ev * ev;
     }
     __syncthreads();
-    if (b >= a.batch || mi >= mats_per_block || l >= L.tk) return;
+    if (b >= a.batch || mi >= mats_per_block) return;
     double* gs = a.scratch + (long long)b * a.ss;
-    const double* d = tri_lds + (2 * mi) * n;
-    const double* e = tri_lds + (2 * mi + 1) * n;
-    // the lane's iterate and pivots: in LDS after the d/e block when they fit, element i of
-    // every lane side by side (stride blockDim.x) so a wave's accesses are consecutive;
-    // else in global scratch with unit stride
-    double* x;
-    double* piv;
-    int xs;
-    if (tri_lanes_in_lds) {
-        xs = blockDim.x;
-        x = tri_lds + 2LL * mats_per_block * n + threadIdx.x;
-        piv = x + (long long)n * blockDim.x;
-    } else {
-        xs = 1;
-        x = gs + L.oX + (long long)l * L.ldx;
-        piv = gs + L.oP + (long long)l * L.ldx;
-    }
+    const double* d = tri_lds + (3 * mi) * n;
+    const double* e = tri_lds + (3 * mi + 1) * n;
+    const double* e2 = tri_lds + (3 * mi + 2) * n;
     // Gershgorin interval and pivot floor
     double lo = 0.0, hi = 0.0, emax2 = 0.0;
     for (int i = 0; i < n; ++i) {
         const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
         lo = (i == 0) ? d[i] - r : fmin(lo, d[i] - r);
         hi = (i == 0) ? d[i] + r : fmax(hi, d[i] + r);
-        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+        if (i + 1 < n) emax2 = fmax(emax2, e2[i]);
     }
     const double tnorm = fmax(fabs(lo), fabs(hi));
     const double pivmin = 1e-300 * fmax(1.0, emax2);
     const int kidx = n - 1 - l;   // l-th largest = kidx-th smallest
-    // bisection: count(x) = number of eigenvalues < x
+    const int base = threadIdx.x - sub;
+    // count(x) = number of eigenvalues < x
     for (int it = 0; it < 128; ++it) {
         if (hi - lo <= 1e-9 * tnorm + pivmin) break;
-        const double mid = 0.5 * (lo + hi);
+        const double h = (hi - lo) / (double)(S + 1);
+        const double x = lo + (double)(sub + 1) * h;
         int cnt = 0;
-        double q = d[0] - mid;
+        double q = d[0] - x;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
         for (int i = 1; i < n; ++i) {
-            q = d[i] - mid - e[i - 1] * e[i - 1] / q;
+            q = d[i] - x - e2[i - 1] * sturm_rcp(q);
             if (fabs(q) < pivmin) q = -pivmin;
             cnt += q < 0.0;
         }
-        if (cnt > kidx) hi = mid;
-        else lo = mid;
+        // the first point with more than kidx eigenvalues below it bounds lambda above
+        double nlo = lo, nhi = hi;
+        bool found = false;
+        for (int s2 = 0; s2 < S; ++s2) {
+            const int c2 = __shfl(cnt, base + s2, 64);
+            const double x2 = lo + (double)(s2 + 1) * h;
+            if (!found) {
+                if (c2 > kidx) {
+                    nhi = x2;
+                    found = true;
+                } else {
+                    nlo = x2;
+                }
+            }
+        }
+        lo = nlo;
+        hi = nhi;
     }
+    if (sub != 0 || l >= tk) return;
     const double lam = 0.5 * (lo + hi);
+    // the lane's iterate and pivots: in LDS after the d/e block when they fit, element i of
+    // every vector lane side by side (stride mats_per_block * tk); else in global scratch
+    const int vl = mi * tk + l, nvl = mats_per_block * tk;
+    double* x;
+    double* piv;
+    int xs;
+    if (tri_lanes_in_lds) {
+        xs = nvl;
+        x = tri_lds + 3LL * mats_per_block * n + vl;
+        piv = x + (long long)n * nvl;
+    } else {
+        xs = 1;
+        x = gs + L.oX + (long long)l * L.ldx;
+        piv = gs + L.oP + (long long)l * L.ldx;
+    }
     // inverse iteration (T - lam I) x = b with T - lam I = L D L^T
     const double ptol = fmax(2.220446049250313e-16 * tnorm, 1e-300);
     for (int i = 0; i < n; ++i)
@@ -687,16 +719,16 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix
     for (int it = 0; it < 3; ++it) {
         double q = d[0] - lam;
         if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-        piv[0 * xs] = q;
+        piv[0] = 1.0 / q;
         for (int i = 1; i < n; ++i) {
-            q = d[i] - lam - e[i - 1] * e[i - 1] / q;
+            q = d[i] - lam - e2[i - 1] * piv[(i - 1) * xs];
             if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-            piv[i * xs] = q;
+            piv[i * xs] = 1.0 / q;
         }
-        // L y = b (in place), then L^T x = D^-1 y
-        for (int i = 1; i < n; ++i) x[i * xs] -= (e[i - 1] / piv[(i - 1) * xs]) * x[(i - 1) * xs];
-        x[(n - 1) * xs] /= piv[(n - 1) * xs];
-        for (int i = n - 2; i >= 0; --i) x[i * xs] = (x[i * xs] - e[i] * x[(i + 1) * xs]) / piv[i * xs];
+        // L y = b (in place), then L^T x = D^-1 y; piv holds the reciprocal pivots
+        for (int i = 1; i < n; ++i) x[i * xs] -= (e[i - 1] * piv[(i - 1) * xs]) * x[(i - 1) * xs];
+        x[(n - 1) * xs] *= piv[(n - 1) * xs];
+        for (int i = n - 2; i >= 0; --i) x[i * xs] = (x[i * xs] - e[i] * x[(i + 1) * xs]) * piv[i * xs];
         double mx = 0.0;
         for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i * xs]));
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
@@ -705,11 +737,11 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int lanes_per_matrix
             x[i * xs] *= inv;
             nrm += x[i * xs] * x[i * xs];
         }
-        const double s = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
-        for (int i = 0; i < n; ++i) x[i * xs] *= s;
+        const double sn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
+        for (int i = 0; i < n; ++i) x[i * xs] *= sn;
     }
     // eigenvalue from the Rayleigh quotient of the converged unit vector
-    double rq = d[0] * x[0 * xs] * x[0 * xs];
+    double rq = d[0] * x[0] * x[0];
     for (int i = 1; i < n; ++i) rq += d[i] * x[i * xs] * x[i * xs] + 2.0 * e[i - 1] * x[(i - 1) * xs] * x[i * xs];
     gs[L.oL + l] = (fabs(rq - lam) <= 1e-8 * tnorm + pivmin) ? rq : lam;
     if (tri_lanes_in_lds) {
@@ -1033,14 +1065,16 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (L.tk > NT) return hipErrorInvalidValue;   // one lane per kept value, at most NT per matrix
-    const int lpm = L.tk > 0 ? L.tk : 1;
+    const int tkk = L.tk > 0 ? L.tk : 1;
+    const int S = 4 * tkk <= 64 ? 4 : (2 * tkk <= 64 ? 2 : 1);   // multisection sub-lanes
+    const int lpm = tkk * S;
     const int mpb = 64 / lpm > 0 ? 64 / lpm : 1;
-    size_t tri_bytes = (size_t)2 * mpb * L.ns * sizeof(double);
-    const size_t lane_bytes = (size_t)mpb * lpm * 2 * L.ns * sizeof(double);
+    size_t tri_bytes = (size_t)3 * mpb * L.ns * sizeof(double);
+    const size_t lane_bytes = (size_t)mpb * tkk * 2 * L.ns * sizeof(double);
     const int in_lds = tri_bytes + lane_bytes <= cap ? 1 : 0;
     if (in_lds) tri_bytes += lane_bytes;
     hipLaunchKernelGGL(k_eig_tri, dim3((unsigned)((batch + mpb - 1) / mpb)), dim3(mpb * lpm), tri_bytes, st,
-                       a, lpm, mpb, in_lds);
+                       a, S, mpb, in_lds);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!launch_fin_reg(a, L, bf, cap, st)) {
