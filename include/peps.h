@@ -164,7 +164,8 @@ peps_status peps_eval_jobs(peps_ctx* ctx, const peps_job* jobs, int32_t njobs,
 peps_status peps_autotune(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
                           const double* A, const int8_t* S, int64_t batch, int32_t* tuned);
 
-/* Save / load the tile table as text lines "M,N,K,batch,arith tile". */
+/* Save / load the tile table as text lines "M,N,K,batch,arith,f32mask tile" (f32mask: bit 0/1/2
+   set when operand A/B/C is a float32 temporary). */
 peps_status peps_tune_save(peps_ctx* ctx, const char* path);
 peps_status peps_tune_load(peps_ctx* ctx, const char* path);
 

@@ -38,6 +38,9 @@ struct GemmArgs {
     const double* B;
     double* C;
     double alpha, beta;
+    // storage type of each operand: 0 = float64, 1 = float32 (the pointer then addresses
+    // floats and every offset above counts floats)
+    int a_f32, b_f32, c_f32;
 };
 
 __host__ __device__ inline long long idx_off(const Idx2& x, int i) {

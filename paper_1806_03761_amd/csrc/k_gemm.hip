@@ -48,9 +48,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles
     const int tid = threadIdx.x;
     if (b >= g.batch) return;
 
-    const double* Ab = g.A + (long long)b * g.a_bs + gather_off(g.ga, b);
-    const double* Bb = g.B + (long long)b * g.b_bs + gather_off(g.gb, b);
-    double* Cb = g.C + (long long)b * g.c_bs + gather_off(g.gc, b);
+    // element offsets of this batch entry (in the operand's own storage type)
+    const long long a0 = (long long)b * g.a_bs + gather_off(g.ga, b);
+    const long long b0 = (long long)b * g.b_bs + gather_off(g.gb, b);
+    const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
+    const double* Ab = g.A + a0;
+    const double* Bb = g.B + b0;
+    double* Cb = g.C + c0;
+    const float* Af = reinterpret_cast<const float*>(g.A) + a0;
+    const float* Bf = reinterpret_cast<const float*>(g.B) + b0;
+    float* Cf = reinterpret_cast<float*>(g.C) + c0;
 
     for (int i = tid; i < TM; i += 256) {
         int m = m0 + i;
@@ -83,12 +90,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles
         for (int e = tid; e < TK * TM; e += 256) {
             int kk = e / TM, mm = e % TM;
             long long om = aoff_m[mm], ok = aoff_k[kk];
-            As[kk][mm] = (om >= 0 && ok >= 0) ? to_in<AR>(Ab[om + ok]) : In(0);
+            As[kk][mm] = (om >= 0 && ok >= 0) ? to_in<AR>(g.a_f32 ? (double)Af[om + ok] : Ab[om + ok]) : In(0);
         }
         for (int e = tid; e < TK * TN; e += 256) {
             int kk = e / TN, nn = e % TN;
             long long on = boff_n[nn], ok = boff_k[kk];
-            Bs[kk][nn] = (on >= 0 && ok >= 0) ? to_in<AR>(Bb[on + ok]) : In(0);
+            Bs[kk][nn] = (on >= 0 && ok >= 0) ? to_in<AR>(g.b_f32 ? (double)Bf[on + ok] : Bb[on + ok]) : In(0);
         }
         __syncthreads();
 #pragma unroll 4
@@ -113,8 +120,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles
             long long on = coff_n[tx + 16 * j];
             if (on < 0) continue;
             double v = g.alpha * (double)acc[i][j];
-            if (g.beta != 0.0) v += g.beta * Cb[om + on];
-            Cb[om + on] = v;
+            if (g.c_f32) {
+                if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
+                Cf[om + on] = (float)v;
+            } else {
+                if (g.beta != 0.0) v += g.beta * Cb[om + on];
+                Cb[om + on] = v;
+            }
         }
     }
 }

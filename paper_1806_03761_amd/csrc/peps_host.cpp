@@ -70,9 +70,13 @@ constexpr int kOnes = 4096;
 
 struct Op {
     double* p;
-    long long bs;    // batch stride in doubles
-    long long ext;   // doubles addressable from p for one sample (host-side bounds check)
-    Op at(long long off) const { return Op{p + off, bs, ext - off}; }
+    long long bs;      // batch stride in elements
+    long long ext;     // elements addressable from p for one sample (host-side bounds check)
+    bool f32 = false;  // float32 storage (GEMM temporaries): p then addresses floats
+    Op at(long long off) const {
+        double* q = f32 ? reinterpret_cast<double*>(reinterpret_cast<float*>(p) + off) : p + off;
+        return Op{q, bs, ext - off, f32};
+    }
 };
 
 inline Idx2 I1(long long s) { return Idx2{1 << 30, 0, s}; }
@@ -281,6 +285,9 @@ public:
 
     double* buf(size_t off) const { return (double*)(base_ + off); }
     Op op(size_t off, long long per) const { return Op{buf(off), per, per}; }
+    // a GEMM-to-GEMM temporary: float32 storage when its GEMMs accumulate in float32 (their
+    // outputs are then exact float32 values, so nothing is rounded by the narrower storage)
+    Op tmp(size_t off, long long per, Arith a) const { return Op{buf(off), per, per, a != Arith::F64}; }
     Op ones() const { return Op{ctx->ones, 0, kOnes}; }
 
     // largest element offset an Idx2 can produce over [0, n) (an upper bound)
@@ -319,8 +326,10 @@ public:
         g.ga = ga; g.gb = gb; g.gc = Gather{nullptr, 0, 0, 0};
         g.A = A.p; g.B = B.p; g.C = C.p;
         g.alpha = 1.0; g.beta = 0.0;
+        g.a_f32 = A.f32; g.b_f32 = B.f32; g.c_f32 = C.f32;
         char kb[96];
-        snprintf(kb, sizeof kb, "%d,%d,%d,%d,%d", M, Nn, K, Bcur, (int)arith);
+        snprintf(kb, sizeof kb, "%d,%d,%d,%d,%d,%d", M, Nn, K, Bcur, (int)arith,
+                 (int)A.f32 | ((int)B.f32 << 1) | ((int)C.f32 << 2));
         const std::string key(kb);
         int tile = 0;
         auto it = ctx->tune.find(key);
@@ -397,7 +406,7 @@ public:
             Op Rin = (j == 0) ? ones() : op(o_R[(j - 1) & 1], s_R);
             const long long ldR = t.K[j];
             Op Ein = down ? envU(row, j) : envL(row, j);
-            Op Y = op(o_Y, s_Y);
+            Op Y = tmp(o_Y, s_Y, ar);
             // Y[(a',l),(u,b)] = sum_a R[a', a*Dl+l] E[a,(u,b)]
             CK(gemm_a(ar, rho * Dl, pin * chj1, chj, Rin, I2(Dl, ldR, 1), I1(Dl), Gather{},
                     Ein, I1((long long)pin * chj1), I1(1), Gather{},
@@ -486,7 +495,7 @@ public:
     hipError_t row_fwd(int i, int j, Op P, int flip, Op Pout) {
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
-        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
         CK(gemm((int)(h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * cl), Gather{},
                 envU(i, j), I1(Du * cu1), I1(1), Gather{}, T1, I1(Du * cu1), I1(1)));
         CK(gemm((int)(cl * cu1), (int)(h1 * Dd), (int)(h * Du), T1, I2((int)cu1, Du * cu1, 1),
@@ -501,7 +510,7 @@ public:
     hipError_t row_bwd(int i, int j, Op Q, int flip, Op Qout) {
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
-        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
         CK(gemm((int)(cl * Dd), (int)(cu1 * h1), (int)cl1, envL(i, j), I1(cl1), I1(1), Gather{}, Q,
                 I1(1), I1(cl1), Gather{}, T1, I1(cu1 * h1), I1(1)));
         CK(gemm((int)(h * Du), (int)(cl * cu1), (int)(h1 * Dd), site_op(i, j), I2((int)Du, D3, D2),
@@ -517,7 +526,7 @@ public:
     hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout) {
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
-        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T), T3 = op(o_T[2], s_T);
+        Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
         CK(gemm((int)(h * h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * h * cl), Gather{},
                 envU(i, j), I1(Du * cu1), I1(1), Gather{}, T1, I1(Du * cu1), I1(1)));
         CK(gemm((int)(h * cl * cu1), (int)(h1 * Dm), (int)(h * Du), T1, I2((int)cu1, Du * cu1, 1),
@@ -535,7 +544,7 @@ public:
     hipError_t pair_bwd(int i, int j, Op Q, int f1, int f2, Op Qout) {
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
-        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T), T3 = op(o_T[2], s_T);
+        Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
         CK(gemm((int)(cl * Dq), (int)(cu1 * h1 * h1), (int)cl1, envL(i + 1, j), I1(cl1), I1(1),
                 Gather{}, Q, I1(1), I1(cl1), Gather{}, T1, I1(cu1 * h1 * h1), I1(1)));
         CK(gemm((int)(h * Dm), (int)(cl * cu1 * h1), (int)(h1 * Dq), site_op(i + 1, j),
@@ -556,7 +565,7 @@ public:
         const long long cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long cu = chiU[i][j];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
-        Op T1 = op(o_T[0], s_T), T2 = op(o_T[1], s_T);
+        Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
         Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
         Op Q = (j + 1 == Lx) ? ones() : op(o_Q[j + 1], s_P[j + 1]);
         CK(gemm((int)(h * cl), (int)(Du * cu1), (int)cu, P, I1(1), I1(h * cl), Gather{},
@@ -1133,7 +1142,7 @@ peps_status peps_tune_save(peps_ctx* c, const char* path) {
     if (!c || !path) return PEPS_ERR_INVALID_ARG;
     std::ofstream f(path);
     if (!f) return fail(c, PEPS_ERR_INVALID_ARG, "cannot write %s", path);
-    f << "# peps GEMM tiles: M,N,K,batch,arith tile\n";
+    f << "# peps GEMM tiles: M,N,K,batch,arith,float32-operand-mask tile\n";
     for (auto& kv : c->tune) f << kv.first << " " << kv.second << "\n";
     return PEPS_OK;
 }
