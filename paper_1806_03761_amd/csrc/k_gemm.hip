@@ -131,6 +131,133 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles
     }
 }
 
+// Row kernel for skinny products (N <= 64, K <= kRowsMaxK): the TPR threads of a row own
+// CPT consecutive columns each and accumulate them in registers, reading the A row
+// straight from memory with KC loads in flight (k in order, as in the tiled kernel, so
+// the results are identical); B is staged once per block and C leaves through LDS so
+// that consecutive threads store consecutive columns.
+static constexpr int kRowsMaxK = 64;
+
+template <int CPT, int TPR, Arith AR>
+__global__ __launch_bounds__(256) void k_gemm_rows(GemmArgs g, int blocks_m) {
+    using In = typename ArithT<AR>::In;
+    using Acc = typename ArithT<AR>::Acc;
+    constexpr int KC = 16;               // A loads in flight per thread
+    constexpr int RPB = 256 / TPR;       // rows per block
+    constexpr int NC = CPT * TPR;        // columns per block
+    __shared__ In Bs[kRowsMaxK][NC];
+    __shared__ Acc Cs[RPB][NC + 1];
+    __shared__ long long koff[kRowsMaxK], coff_n[NC], coff_m[RPB];
+    const int b = blockIdx.x / blocks_m, m0 = (blockIdx.x % blocks_m) * RPB, tid = threadIdx.x;
+    if (b >= g.batch) return;
+    const long long a0 = (long long)b * g.a_bs + gather_off(g.ga, b);
+    const long long b0 = (long long)b * g.b_bs + gather_off(g.gb, b);
+    const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
+    for (int e = tid; e < g.K * NC; e += 256) {
+        const int k = e / NC, n = e % NC;
+        In v = In(0);
+        if (n < g.N) {
+            const long long o = b0 + idx_off(g.bk, k) + idx_off(g.bn, n);
+            v = to_in<AR>(g.b_f32 ? (double)reinterpret_cast<const float*>(g.B)[o] : g.B[o]);
+        }
+        Bs[k][n] = v;
+    }
+    for (int k = tid; k < g.K; k += 256) koff[k] = idx_off(g.ak, k);
+    for (int n = tid; n < NC; n += 256) coff_n[n] = n < g.N ? idx_off(g.cn, n) : 0;
+    const int r = tid / TPR, cg = (tid % TPR) * CPT;
+    const int m = m0 + r;
+    if (tid < RPB) coff_m[tid] = m0 + tid < g.M ? idx_off(g.cm, m0 + tid) : 0;
+    __syncthreads();
+    Acc acc[CPT];
+#pragma unroll
+    for (int n = 0; n < CPT; ++n) acc[n] = Acc(0);
+    if (m < g.M) {
+        const long long am = a0 + idx_off(g.am, m);
+        const float* Af = reinterpret_cast<const float*>(g.A) + am;
+        const double* Ad = g.A + am;
+        for (int k0 = 0; k0 < g.K; k0 += KC) {
+            In av[KC];
+            if (g.a_f32) {
+                float x[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) x[u] = Af[koff[k0 + u < g.K ? k0 + u : 0]];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) av[u] = k0 + u < g.K ? to_in<AR>((double)x[u]) : In(0);
+            } else {
+                double x[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) x[u] = Ad[koff[k0 + u < g.K ? k0 + u : 0]];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) av[u] = k0 + u < g.K ? to_in<AR>(x[u]) : In(0);
+            }
+#pragma unroll
+            for (int u = 0; u < KC; ++u) {
+                if (k0 + u >= g.K) break;
+#pragma unroll
+                for (int n = 0; n < CPT; ++n) acc[n] = fma((Acc)av[u], (Acc)Bs[k0 + u][cg + n], acc[n]);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < CPT; ++n) Cs[r][cg + n] = acc[n];
+    __syncthreads();
+    float* Cf = reinterpret_cast<float*>(g.C) + c0;
+    double* Cd = g.C + c0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int e = tid + 256 * j, rr = e / NC, n = e % NC;
+        if (n >= g.N || m0 + rr >= g.M) continue;
+        const long long o = coff_m[rr] + coff_n[n];
+        double v = g.alpha * (double)Cs[rr][n];
+        if (g.c_f32) {
+            if (g.beta != 0.0) v += g.beta * (double)Cf[o];
+            Cf[o] = (float)v;
+        } else {
+            if (g.beta != 0.0) v += g.beta * Cd[o];
+            Cd[o] = v;
+        }
+    }
+}
+
+template <int CPT, int TPR>
+static hipError_t launch_rows_t(const GemmArgs& g, Arith ar, hipStream_t st) {
+    constexpr int RPB = 256 / TPR;
+    const int bm = (g.M + RPB - 1) / RPB;
+    const long long blocks = (long long)bm * g.batch;
+    if (blocks == 0) return hipSuccess;
+    switch (ar) {
+        case Arith::F64: hipLaunchKernelGGL((k_gemm_rows<CPT, TPR, Arith::F64>), dim3((unsigned)blocks), dim3(256), 0, st, g, bm); break;
+        case Arith::F32: hipLaunchKernelGGL((k_gemm_rows<CPT, TPR, Arith::F32>), dim3((unsigned)blocks), dim3(256), 0, st, g, bm); break;
+        case Arith::BF16: hipLaunchKernelGGL((k_gemm_rows<CPT, TPR, Arith::BF16>), dim3((unsigned)blocks), dim3(256), 0, st, g, bm); break;
+    }
+    return hipGetLastError();
+}
+
+bool gemm_rows_fits(const GemmArgs& g) { return g.N <= 64 && g.K <= kRowsMaxK; }
+
+hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (!gemm_rows_fits(g)) return hipErrorInvalidValue;
+    if (g.N <= 4) return launch_rows_t<4, 1>(g, ar, st);
+    if (g.N <= 8) return launch_rows_t<8, 1>(g, ar, st);
+    if (g.N <= 16) return launch_rows_t<16, 1>(g, ar, st);
+    if (g.N <= 32) return launch_rows_t<16, 2>(g, ar, st);
+    return launch_rows_t<16, 4>(g, ar, st);
+}
+
+// the same product as C^T = B^T A^T (M and N, A and B swapped)
+static GemmArgs transposed(const GemmArgs& g) {
+    GemmArgs t = g;
+    t.M = g.N; t.N = g.M;
+    t.A = g.B; t.B = g.A;
+    t.am = g.bn; t.ak = g.bk; t.bk = g.ak; t.bn = g.am;
+    t.cm = g.cn; t.cn = g.cm;
+    t.a_bs = g.b_bs; t.b_bs = g.a_bs;
+    t.ga = g.gb; t.gb = g.ga;
+    t.a_f32 = g.b_f32; t.b_f32 = g.a_f32;
+    return t;
+}
+
 template <int TM, int TN, int TK>
 static hipError_t launch_t(const GemmArgs& g, Arith ar, hipStream_t st) {
     int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
@@ -147,6 +274,14 @@ static hipError_t launch_t(const GemmArgs& g, Arith ar, hipStream_t st) {
 
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    // 14: row kernel; 15: row kernel on the transposed product (each falls back to the
+    // heuristic tile when the shape does not fit it)
+    if (tile == 14 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
+    if (tile == 15) {
+        const GemmArgs t = transposed(g);
+        if (gemm_rows_fits(t)) return launch_gemm_rows(t, ar, st);
+    }
+    if (tile >= 14) tile = 0;
     if (tile <= 0 || tile > kGemmTiles) {
         // heuristic: smallest tile that covers small problems
         if (g.M <= 16 && g.N <= 16) tile = 1;
@@ -163,6 +298,12 @@ hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         case 5: return launch_t<64, 64, 16>(g, ar, st);
         case 6: return launch_t<32, 16, 32>(g, ar, st);
         case 7: return launch_t<16, 32, 32>(g, ar, st);
+        case 8: return launch_t<128, 16, 16>(g, ar, st);
+        case 9: return launch_t<256, 16, 16>(g, ar, st);
+        case 10: return launch_t<16, 128, 16>(g, ar, st);
+        case 11: return launch_t<16, 256, 16>(g, ar, st);
+        case 12: return launch_t<128, 32, 16>(g, ar, st);
+        case 13: return launch_t<32, 128, 16>(g, ar, st);
         default: return launch_t<64, 64, 16>(g, ar, st);
     }
 }

@@ -6,7 +6,11 @@
 namespace peps {
 
 // tile: 0 = heuristic choice, 1..kGemmTiles = a fixed tile shape (see k_gemm.hip)
-static constexpr int kGemmTiles = 7;
+static constexpr int kGemmTiles = 15;
+// row kernel for skinny products: N <= 64 and K <= 64 (gemm_rows_fits); same results as
+// launch_gemm
+bool gemm_rows_fits(const GemmArgs& g);
+hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();
 
