@@ -55,6 +55,21 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
                       hipStream_t st);
 
 // misc
+// fused two-row sandwich step (float32, legs <= 4, boundary bonds <= 16; see k_pair.hip)
+struct PairArgs {
+    int cu, cu1, cl, cl1, Du, Dm, Dq, h, h1;
+    const double* X; long long xs;       // incoming partial (P forward, Q backward)
+    const double* U; long long us;       // upper environment [cu][Du][cu1]
+    const double* L; long long ls;       // lower environment [cl][Dq][cl1]
+    const double* site1;                 // site (i, j): two spin slices, slice apart
+    const double* site2;                 // site (i+1, j)
+    long long D, D2, D3, slice;          // site tensor strides [left][up][right][down]
+    const int8_t* sel1; const int8_t* sel2; long long sel_bs; int flip1, flip2;
+    double* Y; long long ys;             // outgoing partial
+    int batch;
+};
+bool pair_step_fits(const PairArgs& a);
+hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st);
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
 hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st);
 hipError_t launch_copy_i8(const int8_t* src, int8_t* dst, long long n, hipStream_t st);

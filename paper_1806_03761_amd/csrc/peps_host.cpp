@@ -111,6 +111,9 @@ public:
         ar_sw = prec == PEPS_PREC_F64 ? Arith::F64 : Arith::F32;
         const char* sv = getenv("PEPS_SVD");
         use_eig = !(sv && strcmp(sv, "jacobi") == 0);
+        // fused two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the four-GEMM form)
+        const char* fz = getenv("PEPS_FUSE");
+        fuse_pairs = ar_sw == Arith::F32 && !(fz && strcmp(fz, "0") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -523,7 +526,39 @@ public:
     }
 
     // two-row sandwich <U_i| rows i, i+1 |L_{i+1}>, forward step
+    // the two-row step as one fused kernel when it fits (done = false: use the GEMMs)
+    hipError_t pair_fused(int i, int j, Op X, int f1, int f2, Op Y, bool fwd, bool& done) {
+        done = false;
+        if (!fuse_pairs) return hipSuccess;
+        PairArgs a;
+        a.cu = chiU[i][j]; a.cu1 = chiU[i][j + 1]; a.cl = chiL[i + 1][j]; a.cl1 = chiL[i + 1][j + 1];
+        a.Du = Dv[i]; a.Dm = Dv[i + 1]; a.Dq = Dv[i + 2]; a.h = Dh[j]; a.h1 = Dh[j + 1];
+        if (!pair_step_fits(a)) return hipSuccess;
+        const long long nl = (long long)a.cu * a.h * a.h * a.cl, nr = (long long)a.cu1 * a.h1 * a.h1 * a.cl1;
+        const Op U = envU(i, j), L = envL(i + 1, j), s1 = site_op(i, j), s2 = site_op(i + 1, j);
+        if (!bounds_ok("pair in", X, (fwd ? nl : nr) - 1, 0) || !bounds_ok("pair out", Y, (fwd ? nr : nl) - 1, 0) ||
+            !bounds_ok("pair U", U, (long long)a.cu * a.Du * a.cu1 - 1, 0) ||
+            !bounds_ok("pair L", L, (long long)a.cl * a.Dq * a.cl1 - 1, 0) ||
+            !bounds_ok("pair site", s1, D4 - 1, D4) || !bounds_ok("pair site", s2, D4 - 1, D4))
+            return hipErrorInvalidValue;
+        if (X.f32 || Y.f32) return hipSuccess;
+        done = true;
+        if (dry) return hipSuccess;
+        a.X = X.p; a.xs = X.bs; a.U = U.p; a.us = U.bs; a.L = L.p; a.ls = L.bs;
+        a.site1 = s1.p; a.site2 = s2.p; a.D = D; a.D2 = D2; a.D3 = D3; a.slice = D4;
+        a.sel1 = Scur + (long long)i * Lx + j; a.sel2 = Scur + (long long)(i + 1) * Lx + j; a.sel_bs = N;
+        a.flip1 = f1; a.flip2 = f2;
+        a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
+        const double fl = 2.0 * Bcur *
+                          ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
+                           (double)a.cl * a.cu1 * a.h1 * a.h1 * a.Dq * a.h * a.Dm + (double)a.cu1 * a.h1 * a.h1 * a.cl1 * a.cl * a.Dq);
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_pair_step(a, fwd, st_); });
+    }
+
     hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout) {
+        bool done = false;
+        CK(pair_fused(i, j, P, f1, f2, Pout, true, done));
+        if (done) return hipSuccess;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
@@ -542,6 +577,9 @@ public:
     }
 
     hipError_t pair_bwd(int i, int j, Op Q, int f1, int f2, Op Qout) {
+        bool done = false;
+        CK(pair_fused(i, j, Q, f1, f2, Qout, false, done));
+        if (done) return hipSuccess;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
@@ -776,6 +814,7 @@ public:
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
     size_t o_eig = 0;
     bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
+    bool fuse_pairs = false;
 };
 
 size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create

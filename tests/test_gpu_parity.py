@@ -371,3 +371,25 @@ def test_autotune_keeps_results():
         lines = [ln for ln in open(path) if not ln.startswith("#")]
         assert len(lines) >= n
         p.tune_load(path)
+
+
+def test_fused_pair_step_matches_gemm_path():
+    """The fused two-row sandwich step accumulates every product in the order of its
+    four unfused GEMMs (float32 operands, fma, k ascending), so amplitudes, local
+    energies and log-derivatives equal those of the GEMM path exactly."""
+    import os
+    p = _peps()
+    lat, A, S, _ = make_workload("8x8_D4_Dc16", 37)
+    Ad, Sd = _dev(A, S)
+    fused = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
+    old = os.environ.get("PEPS_FUSE")
+    os.environ["PEPS_FUSE"] = "0"
+    try:
+        plain = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
+    finally:
+        if old is None:
+            del os.environ["PEPS_FUSE"]
+        else:
+            os.environ["PEPS_FUSE"] = old
+    for x, y in zip(fused, plain):
+        assert np.array_equal(x, y)
