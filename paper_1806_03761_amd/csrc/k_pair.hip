@@ -4,11 +4,13 @@
 //
 // Unfused, the step is four batched GEMMs whose three temporaries (each Dc^2 D^3 per
 // sample) make the round trip through HBM.  Here one workgroup owns one sample: the
-// incoming partial, the two environment tensors and the two spin-selected site tensors
-// are staged once into LDS, thread (l, c') (lower-left and upper-right boundary bonds,
-// the indices that stay free through the first three contractions) keeps its D^3 slice
-// of each temporary in registers, and the last contraction, which sums over l (forward)
-// or c' (backward), goes through an LDS copy of the third temporary.  Every product
+// incoming partial and the two environment tensors are staged once into LDS, thread
+// (l, c') (lower-left and upper-right boundary bonds, the indices that stay free through
+// the first three contractions) keeps its D^3 slice of each temporary in registers, the
+// spin-selected site tensors come from a zero-padded float32 table through the scalar
+// cache (uniform operands, no LDS traffic), and the last contraction, which sums over l
+// (forward) or c' (backward), goes through an LDS copy of the third temporary with each
+// thread producing a 4 x 4 block of outputs.  Every product
 // accumulates in the order its unfused GEMM uses (fma, k ascending, operands rounded
 // to float32 first), so the result equals the unfused float32 path value for value.
 //
@@ -23,7 +25,7 @@ namespace peps {
 
 static constexpr int kPD = 4;    // PEPS legs (horizontal and vertical) of the fused path
 static constexpr int kPX = 16;   // boundary bonds of the fused path
-static constexpr int kPairLds = 2 * 256 + 2 * 1024 + 16384;   // floats
+static constexpr int kPairLds = 2 * 1024 + 16384;   // floats
 
 bool pair_step_fits(const PairArgs& a) {
     const int legs[5] = {a.h, a.h1, a.Du, a.Dm, a.Dq};
@@ -35,40 +37,53 @@ bool pair_step_fits(const PairArgs& a) {
     return kPairLds * sizeof(float) <= get_lds_cap() - 1024;
 }
 
+// Site tensors of the whole lattice as float32, zero padded to 4 per leg, in the two
+// leg orders the fused step reads: [left][up][right][down] and [right][down][left][up].
+// T[((site * 2 + spin) * 2 + order) * 256 + index].
+__global__ void k_site_tables(const double* A, float* T, int Lx, int Ly, int D) {
+    const int s = blockIdx.x, tid = threadIdx.x;   // 256 threads: one padded entry each
+    const int i = s / Lx, j = s % Lx;
+    const int left = j == 0 ? 1 : D, right = j == Lx - 1 ? 1 : D;
+    const int up = i == 0 ? 1 : D, down = i == Ly - 1 ? 1 : D;
+    const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
+    const int x0 = tid >> 6, x1 = (tid >> 4) & 3, x2 = (tid >> 2) & 3, x3 = tid & 3;
+    for (int sp = 0; sp < 2; ++sp) {
+        const double* a = A + ((long long)s * 2 + sp) * D4;
+        float* t = T + ((long long)s * 2 + sp) * 512;
+        // natural order: (x0, x1, x2, x3) = (left, up, right, down)
+        t[tid] = (x0 < left && x1 < up && x2 < right && x3 < down) ? (float)a[x0 * D3 + x1 * D2 + x2 * D + x3] : 0.f;
+        // second order: (x0, x1, x2, x3) = (right, down, left, up)
+        t[256 + tid] = (x2 < left && x3 < up && x0 < right && x1 < down)
+                           ? (float)a[x2 * D3 + x3 * D2 + x0 * D + x1] : 0.f;
+    }
+}
+
+hipError_t launch_site_tables(const double* A, float* T, int Lx, int Ly, int D, hipStream_t st) {
+    if (D > kPD) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_site_tables, dim3(Lx * Ly), dim3(256), 0, st, A, T, Lx, Ly, D);
+    return hipGetLastError();
+}
+
 __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     extern __shared__ __align__(16) float sm[];
-    float* Sa = sm;              // site (i,j), 4^4, zero padded
-    float* Sb = Sa + 256;        // site (i+1,j)
-    float* Ue = Sb + 256;        // upper environment, 16 x 16 x 4
+    float* Ue = sm;              // upper environment, 16 x 16 x 4
     float* Le = Ue + 1024;       // lower environment
     float* Big = Le + 1024;      // incoming partial, later the third temporary
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
-    const int Du = a.Du, Dm = a.Dm, Dq = a.Dq, h = a.h, h1 = a.h1;
+    const int Du = a.Du, Dq = a.Dq, h = a.h, h1 = a.h1;
     const double* X = a.X + (long long)b * a.xs;
     const double* U = a.U + (long long)b * a.us;
     const double* L = a.L + (long long)b * a.ls;
-    const double* s1 = a.site1 + (long long)((a.sel1[(long long)b * a.sel_bs] ^ a.flip1) & 1) * a.slice;
-    const double* s2 = a.site2 + (long long)((a.sel2[(long long)b * a.sel_bs] ^ a.flip2) & 1) * a.slice;
+    // block-uniform site tables: FWD reads the natural order, BWD the second one
+    const float* S1 = a.site1 + (long long)((a.sel1[(long long)b * a.sel_bs] ^ a.flip1) & 1) * 512 + (FWD ? 0 : 256);
+    const float* S2 = a.site2 + (long long)((a.sel2[(long long)b * a.sel_bs] ^ a.flip2) & 1) * 512 + (FWD ? 0 : 256);
 
     // ---- staging (float32, zero padded) ----
-    {
-        const int x0 = tid >> 6, x1 = (tid >> 4) & 3, x2 = (tid >> 2) & 3, x3 = tid & 3;
-        // FWD: Sa[b][u][a][m], Sb[b'][m][a'][q];  BWD: Sa[a][m][b][u], Sb[a'][q][b'][m]
-        int lb, up, rt, dn;
-        if (FWD) { lb = x0; up = x1; rt = x2; dn = x3; }
-        else { rt = x0; dn = x1; lb = x2; up = x3; }
-        Sa[tid] = (lb < h && up < Du && rt < h1 && dn < Dm)
-                      ? (float)s1[lb * a.D3 + up * a.D2 + rt * a.D + dn] : 0.f;
-        if (FWD) { lb = x0; up = x1; rt = x2; dn = x3; }
-        else { rt = x0; dn = x1; lb = x2; up = x3; }
-        Sb[tid] = (lb < h && up < Dm && rt < h1 && dn < Dq)
-                      ? (float)s2[lb * a.D3 + up * a.D2 + rt * a.D + dn] : 0.f;
-    }
     for (int e = tid; e < 1024; e += 256) {
         int c, u, cp;
         if (FWD) { c = e >> 6; cp = (e >> 2) & 15; u = e & 3; }     // Ue[c][c'][u]
@@ -145,31 +160,26 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
 #pragma unroll
             for (int z = 0; z < kPD; ++z) T2[x][y][z] = 0.f;
     // FWD: T2[b'][a][m] = sum_{b,u} T1[b][b'][u] S1[b][u][a][m]
-    // BWD: T2[b'][m][a] = sum_{a',q} S2[b'][m][a'][q] T1[q][a][a']
+    // BWD: T2[b'][m][a] = sum_{a',q} S2[a'][q][b'][m] T1[q][a][a']   (S2 in the second order)
 #pragma unroll
     for (int x = 0; x < kPD; ++x)
 #pragma unroll
         for (int y = 0; y < kPD; ++y) {
-            float sv[kPD][kPD];
-            const float* sp = (FWD ? Sa : Sb) + (x * kPD + y) * 16;
-#pragma unroll
-            for (int r = 0; r < kPD; ++r) {
-                const float4 t = ld4(sp + r * kPD);
-                sv[r][0] = t.x; sv[r][1] = t.y; sv[r][2] = t.z; sv[r][3] = t.w;
-            }
+            const float* sp = (FWD ? S1 : S2) + (x * kPD + y) * 16;
 #pragma unroll
             for (int p = 0; p < kPD; ++p)
 #pragma unroll
                 for (int r = 0; r < kPD; ++r)
 #pragma unroll
                     for (int s = 0; s < kPD; ++s) {
-                        if (FWD) T2[p][r][s] = fmaf(T1[x][p][y], sv[r][s], T2[p][r][s]);
-                        else T2[r][s][p] = fmaf(sv[r][s], T1[y][p][x], T2[r][s][p]);
+                        const float sv = sp[r * kPD + s];
+                        if (FWD) T2[p][r][s] = fmaf(T1[x][p][y], sv, T2[p][r][s]);
+                        else T2[r][s][p] = fmaf(sv, T1[y][p][x], T2[r][s][p]);
                     }
         }
-    // reuse T1 for the third temporary
+    // the third temporary reuses T1
     // FWD: T3[a][a'][q] = sum_{b',m} T2[b'][a][m] S2[b'][m][a'][q]
-    // BWD: T3[b][u][b'] = sum_{a,m} S1[b][u][a][m] T2[b'][m][a]
+    // BWD: T3[b][u][b'] = sum_{a,m} S1[a][m][b][u] T2[b'][m][a]     (S1 in the second order)
 #pragma unroll
     for (int x = 0; x < kPD; ++x)
 #pragma unroll
@@ -180,98 +190,96 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     for (int x = 0; x < kPD; ++x)
 #pragma unroll
         for (int y = 0; y < kPD; ++y) {
-            float sv[kPD][kPD];
-            const float* sp = (FWD ? Sb : Sa) + (x * kPD + y) * 16;
-#pragma unroll
-            for (int r = 0; r < kPD; ++r) {
-                const float4 t = ld4(sp + r * kPD);
-                sv[r][0] = t.x; sv[r][1] = t.y; sv[r][2] = t.z; sv[r][3] = t.w;
-            }
+            const float* sp = (FWD ? S2 : S1) + (x * kPD + y) * 16;
 #pragma unroll
             for (int p = 0; p < kPD; ++p)
 #pragma unroll
                 for (int r = 0; r < kPD; ++r)
 #pragma unroll
                     for (int s = 0; s < kPD; ++s) {
-                        if (FWD) T1[p][r][s] = fmaf(T2[x][p][y], sv[r][s], T1[p][r][s]);
-                        else T1[r][s][p] = fmaf(sv[r][s], T2[p][y][x], T1[r][s][p]);
+                        const float sv = sp[r * kPD + s];
+                        if (FWD) T1[p][r][s] = fmaf(T2[x][p][y], sv, T1[p][r][s]);
+                        else T1[r][s][p] = fmaf(sv, T2[p][y][x], T1[r][s][p]);
                     }
         }
     __syncthreads();   // everyone is done with the incoming partial
-    // ---- third temporary to LDS ----
+    // ---- third temporary to LDS, laid out so that the readers below take consecutive
+    // 16-byte chunks ----
     if (FWD) {
-        // Big[l][c'][a][a'][q]
-        float* dst = Big + (l * kPX + cp) * 64;
+        // Big[l][q][c'][a][a']
 #pragma unroll
         for (int x = 0; x < kPD; ++x)
 #pragma unroll
-            for (int y = 0; y < kPD; ++y)
-                *reinterpret_cast<float4*>(dst + (x * kPD + y) * kPD) =
-                    make_float4(T1[x][y][0], T1[x][y][1], T1[x][y][2], T1[x][y][3]);
+            for (int q = 0; q < kPD; ++q)
+                *reinterpret_cast<float4*>(Big + ((l * kPD + q) * kPX + cp) * 16 + x * kPD) =
+                    make_float4(T1[x][0][q], T1[x][1][q], T1[x][2][q], T1[x][3][q]);
     } else {
-        // Big[l][b][b'][u][c']
+        // Big[u][c'][l][b][b']
 #pragma unroll
         for (int x = 0; x < kPD; ++x)
 #pragma unroll
             for (int y = 0; y < kPD; ++y)
-#pragma unroll
-                for (int z = 0; z < kPD; ++z) Big[(((l * kPD + x) * kPD + z) * kPD + y) * kPX + cp] = T1[x][y][z];
+                *reinterpret_cast<float4*>(Big + ((y * kPX + cp) * kPX + l) * 16 + x * kPD) =
+                    make_float4(T1[x][y][0], T1[x][y][1], T1[x][y][2], T1[x][y][3]);
     }
     __syncthreads();
-    // ---- last contraction ----
+    // ---- last contraction: each thread a 4 x 4 block of outputs ----
     double* Y = a.Y + (long long)b * a.ys;
-    float acc[kPX];
+    float acc[kPD][kPD];
 #pragma unroll
-    for (int n = 0; n < kPX; ++n) acc[n] = 0.f;
+    for (int x = 0; x < kPD; ++x)
+#pragma unroll
+        for (int y = 0; y < kPD; ++y) acc[x][y] = 0.f;
     if (FWD) {
-        // thread (c', a, a'): Pout[c'][a][a'][l'] = sum_{l,q} T3[l][c'][a][a'][q] L[l][q][l']
-        const int c2 = tid >> 4, aa = (tid >> 2) & 3, ap = tid & 3;
+        // thread (c', a, l' group): Pout[c'][a][a'][l'] = sum_{l,q} T3[l][c'][a][a'][q] L[l][q][l']
+        const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;
         for (int l2 = 0; l2 < cl; ++l2) {
-            const float4 t = ld4(Big + ((l2 * kPX + c2) * kPD + aa) * 16 + ap * kPD);
-            const float tv[kPD] = {t.x, t.y, t.z, t.w};
 #pragma unroll
             for (int q = 0; q < kPD; ++q) {
-                const float* lr = Le + (l2 * kPD + q) * kPX;
+                const float4 t = ld4(Big + ((l2 * kPD + q) * kPX + c2) * 16 + aa * kPD);
+                const float4 lv = ld4(Le + (l2 * kPD + q) * kPX + lg * kPD);
+                const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {lv.x, lv.y, lv.z, lv.w};
 #pragma unroll
-                for (int n4 = 0; n4 < kPX / 4; ++n4) {
-                    const float4 lv = ld4(lr + n4 * 4);
-                    acc[n4 * 4 + 0] = fmaf(tv[q], lv.x, acc[n4 * 4 + 0]);
-                    acc[n4 * 4 + 1] = fmaf(tv[q], lv.y, acc[n4 * 4 + 1]);
-                    acc[n4 * 4 + 2] = fmaf(tv[q], lv.z, acc[n4 * 4 + 2]);
-                    acc[n4 * 4 + 3] = fmaf(tv[q], lv.w, acc[n4 * 4 + 3]);
-                }
+                for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                    for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(tv[x], wv[y], acc[x][y]);
             }
         }
-        if (c2 < cu1 && aa < h1 && ap < h1) {
-            double* yo = Y + (((long long)c2 * h1 + aa) * h1 + ap) * cl1;
+        if (c2 < cu1 && aa < h1) {
 #pragma unroll
-            for (int n = 0; n < kPX; ++n)
-                if (n < cl1) yo[n] = (double)acc[n];
+            for (int x = 0; x < kPD; ++x) {
+                if (x >= h1) break;
+                double* yo = Y + (((long long)c2 * h1 + aa) * h1 + x) * cl1;
+#pragma unroll
+                for (int y = 0; y < kPD; ++y)
+                    if (lg * kPD + y < cl1) yo[lg * kPD + y] = (double)acc[x][y];
+            }
         }
     } else {
-        // thread (b, b', l): Qout[c][b][b'][l] = sum_{u,c'} U[c][u][c'] T3[b][u][b'][l][c']
-        const int bb = tid >> 6, bp = (tid >> 4) & 3, l2 = tid & 15;
+        // thread (b, l, c group): Qout[c][b][b'][l] = sum_{u,c'} U[c][u][c'] T3[b][u][b'][l][c']
+        const int bb = tid >> 6, l2 = (tid >> 2) & 15, cg = tid & 3;
 #pragma unroll
         for (int u = 0; u < kPD; ++u) {
-            const float* tr = Big + ((l2 * kPD + bb) * kPD + bp) * 64 + u * kPX;
             for (int c2 = 0; c2 < cu1; ++c2) {
-                const float tv = tr[c2];
-                const float* ur = Ue + (u * kPX + c2) * kPX;
+                const float4 t = ld4(Big + ((u * kPX + c2) * kPX + l2) * 16 + bb * kPD);
+                const float4 uv = ld4(Ue + (u * kPX + c2) * kPX + cg * kPD);
+                const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {uv.x, uv.y, uv.z, uv.w};
 #pragma unroll
-                for (int n4 = 0; n4 < kPX / 4; ++n4) {
-                    const float4 uv = ld4(ur + n4 * 4);
-                    acc[n4 * 4 + 0] = fmaf(uv.x, tv, acc[n4 * 4 + 0]);
-                    acc[n4 * 4 + 1] = fmaf(uv.y, tv, acc[n4 * 4 + 1]);
-                    acc[n4 * 4 + 2] = fmaf(uv.z, tv, acc[n4 * 4 + 2]);
-                    acc[n4 * 4 + 3] = fmaf(uv.w, tv, acc[n4 * 4 + 3]);
-                }
+                for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                    for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(wv[y], tv[x], acc[x][y]);
             }
         }
-        if (bb < h && bp < h && l2 < cl) {
-            const long long m = ((long long)bb * h + bp) * cl + l2, ms = (long long)h * h * cl;
+        if (bb < h && l2 < cl) {
+            const long long ms = (long long)h * h * cl;
 #pragma unroll
-            for (int n = 0; n < kPX; ++n)
-                if (n < cu) Y[(long long)n * ms + m] = (double)acc[n];
+            for (int y = 0; y < kPD; ++y) {
+                const int c = cg * kPD + y;
+                if (c >= cu) break;
+#pragma unroll
+                for (int x = 0; x < kPD; ++x)
+                    if (x < h) Y[(long long)c * ms + ((long long)bb * h + x) * cl + l2] = (double)acc[x][y];
+            }
         }
     }
 }

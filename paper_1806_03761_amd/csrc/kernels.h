@@ -61,14 +61,15 @@ struct PairArgs {
     const double* X; long long xs;       // incoming partial (P forward, Q backward)
     const double* U; long long us;       // upper environment [cu][Du][cu1]
     const double* L; long long ls;       // lower environment [cl][Dq][cl1]
-    const double* site1;                 // site (i, j): two spin slices, slice apart
-    const double* site2;                 // site (i+1, j)
-    long long D, D2, D3, slice;          // site tensor strides [left][up][right][down]
+    const float* site1;                  // site tables (launch_site_tables) of (i, j)
+    const float* site2;                  // and (i+1, j)
     const int8_t* sel1; const int8_t* sel2; long long sel_bs; int flip1, flip2;
     double* Y; long long ys;             // outgoing partial
     int batch;
 };
 bool pair_step_fits(const PairArgs& a);
+// float32 site tables of the fused step: 512 floats per (site, spin), see k_pair.hip
+hipError_t launch_site_tables(const double* A, float* T, int Lx, int Ly, int D, hipStream_t st);
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st);
 hipError_t launch_fill(double* x, long long n, double v, hipStream_t st);
 hipError_t launch_fill_i8(int8_t* x, long long n, int8_t v, hipStream_t st);

@@ -113,7 +113,7 @@ public:
         use_eig = !(sv && strcmp(sv, "jacobi") == 0);
         // fused two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the four-GEMM form)
         const char* fz = getenv("PEPS_FUSE");
-        fuse_pairs = ar_sw == Arith::F32 && !(fz && strcmp(fz, "0") == 0);
+        fuse_pairs = ar_sw == Arith::F32 && D <= 4 && !(fz && strcmp(fz, "0") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -274,6 +274,7 @@ public:
         o_lnW2 = L.alloc(1); o_sgW2 = L.alloc(1);
         o_lnWf = L.alloc(1); o_sgWf = L.alloc(1);
         o_zero = L.alloc(1);
+        o_site32 = fuse_pairs ? L.alloc(0, (long long)N * 512) : 0;   // float32 site tables
         nbonds = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
         o_ratio = want_e ? L.alloc(nbonds) : 0;
         o_delta = want_g ? L.alloc((long long)N * D4) : 0;
@@ -535,17 +536,18 @@ public:
         a.Du = Dv[i]; a.Dm = Dv[i + 1]; a.Dq = Dv[i + 2]; a.h = Dh[j]; a.h1 = Dh[j + 1];
         if (!pair_step_fits(a)) return hipSuccess;
         const long long nl = (long long)a.cu * a.h * a.h * a.cl, nr = (long long)a.cu1 * a.h1 * a.h1 * a.cl1;
-        const Op U = envU(i, j), L = envL(i + 1, j), s1 = site_op(i, j), s2 = site_op(i + 1, j);
+        const Op U = envU(i, j), L = envL(i + 1, j);
         if (!bounds_ok("pair in", X, (fwd ? nl : nr) - 1, 0) || !bounds_ok("pair out", Y, (fwd ? nr : nl) - 1, 0) ||
             !bounds_ok("pair U", U, (long long)a.cu * a.Du * a.cu1 - 1, 0) ||
-            !bounds_ok("pair L", L, (long long)a.cl * a.Dq * a.cl1 - 1, 0) ||
-            !bounds_ok("pair site", s1, D4 - 1, D4) || !bounds_ok("pair site", s2, D4 - 1, D4))
+            !bounds_ok("pair L", L, (long long)a.cl * a.Dq * a.cl1 - 1, 0))
             return hipErrorInvalidValue;
         if (X.f32 || Y.f32) return hipSuccess;
         done = true;
         if (dry) return hipSuccess;
         a.X = X.p; a.xs = X.bs; a.U = U.p; a.us = U.bs; a.L = L.p; a.ls = L.bs;
-        a.site1 = s1.p; a.site2 = s2.p; a.D = D; a.D2 = D2; a.D3 = D3; a.slice = D4;
+        const float* tab = reinterpret_cast<const float*>(buf(o_site32));
+        a.site1 = tab + ((long long)i * Lx + j) * 1024;
+        a.site2 = tab + ((long long)(i + 1) * Lx + j) * 1024;
         a.sel1 = Scur + (long long)i * Lx + j; a.sel2 = Scur + (long long)(i + 1) * Lx + j; a.sel_bs = N;
         a.flip1 = f1; a.flip2 = f2;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
@@ -661,6 +663,7 @@ public:
         hipStream_t st = st_;
         KL(launch_check_configs(S, N, Bn, flags(), st));
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
+        if (fuse_pairs && want_eloc) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
         for (int i = 0; i + 1 < Ly; ++i) CK(trunc_step(true, i));
         const bool need_L = want_eloc || want_grad;
@@ -809,6 +812,7 @@ public:
     std::vector<size_t> o_envU, o_envL, o_logU, o_logL, o_X, o_tau, o_P, o_Q, o_lP, o_lQ, o_P2, o_Q2,
         o_lP2, o_lQ2;
     std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2;
+    size_t o_site32 = 0;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0;
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
