@@ -25,7 +25,7 @@ namespace peps {
 
 static constexpr int kPD = 4;    // PEPS legs (horizontal and vertical) of the fused path
 static constexpr int kPX = 16;   // boundary bonds of the fused path
-static constexpr int kPairLds = 2 * 1024 + 16384;   // floats
+static constexpr int kPairLds = 2 * 1024 + 8192;   // floats
 
 bool pair_step_fits(const PairArgs& a) {
     const int legs[5] = {a.h, a.h1, a.Du, a.Dm, a.Dq};
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     extern __shared__ __align__(16) float sm[];
     float* Ue = sm;              // upper environment, 16 x 16 x 4
     float* Le = Ue + 1024;       // lower environment
-    float* Big = Le + 1024;      // incoming partial, later the third temporary
+    float* Big = Le + 1024;      // incoming partial, later half of the third temporary
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
@@ -118,15 +118,22 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
             for (int z = 0; z < kPD; ++z) T1[x][y][z] = 0.f;
     if (FWD) {
         // T1[b][b'][u] = sum_c P[c][b][b'][l] U[c][u][c']
+        float4 pn[kPD], un;   // operands of the next c, loaded one iteration ahead
+#pragma unroll
+        for (int x = 0; x < kPD; ++x) pn[x] = ld4(Big + (l * kPD + x) * kPD);
+        un = ld4(Ue + cp * kPD);
         for (int c = 0; c < cu; ++c) {
             float pv[kPD][kPD];
 #pragma unroll
             for (int x = 0; x < kPD; ++x) {
-                const float4 t = ld4(Big + ((c * kPX + l) * kPD + x) * kPD);
-                pv[x][0] = t.x; pv[x][1] = t.y; pv[x][2] = t.z; pv[x][3] = t.w;
+                pv[x][0] = pn[x].x; pv[x][1] = pn[x].y; pv[x][2] = pn[x].z; pv[x][3] = pn[x].w;
             }
-            const float4 uu = ld4(Ue + (c * kPX + cp) * kPD);
-            const float uv[kPD] = {uu.x, uu.y, uu.z, uu.w};
+            const float uv[kPD] = {un.x, un.y, un.z, un.w};
+            if (c + 1 < cu) {
+#pragma unroll
+                for (int x = 0; x < kPD; ++x) pn[x] = ld4(Big + (((c + 1) * kPX + l) * kPD + x) * kPD);
+                un = ld4(Ue + ((c + 1) * kPX + cp) * kPD);
+            }
 #pragma unroll
             for (int x = 0; x < kPD; ++x)
 #pragma unroll
@@ -136,15 +143,22 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
         }
     } else {
         // T1[q][a][a'] = sum_l' L[l][q][l'] Q[c'][a][a'][l']
+        float4 qn[kPD], ln;
+#pragma unroll
+        for (int x = 0; x < kPD; ++x) qn[x] = ld4(Big + (cp * kPD + x) * kPD);
+        ln = ld4(Le + l * kPD);
         for (int lp = 0; lp < cl1; ++lp) {
             float qv[kPD][kPD];
 #pragma unroll
             for (int x = 0; x < kPD; ++x) {
-                const float4 t = ld4(Big + ((lp * kPX + cp) * kPD + x) * kPD);
-                qv[x][0] = t.x; qv[x][1] = t.y; qv[x][2] = t.z; qv[x][3] = t.w;
+                qv[x][0] = qn[x].x; qv[x][1] = qn[x].y; qv[x][2] = qn[x].z; qv[x][3] = qn[x].w;
             }
-            const float4 ll = ld4(Le + (lp * kPX + l) * kPD);
-            const float lv[kPD] = {ll.x, ll.y, ll.z, ll.w};
+            const float lv[kPD] = {ln.x, ln.y, ln.z, ln.w};
+            if (lp + 1 < cl1) {
+#pragma unroll
+                for (int x = 0; x < kPD; ++x) qn[x] = ld4(Big + (((lp + 1) * kPX + cp) * kPD + x) * kPD);
+                ln = ld4(Le + ((lp + 1) * kPX + l) * kPD);
+            }
 #pragma unroll
             for (int x = 0; x < kPD; ++x)
 #pragma unroll
@@ -202,49 +216,78 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
                         else T1[r][s][p] = fmaf(sv, T2[p][y][x], T1[r][s][p]);
                     }
         }
-    __syncthreads();   // everyone is done with the incoming partial
-    // ---- third temporary to LDS, laid out so that the readers below take consecutive
-    // 16-byte chunks ----
-    if (FWD) {
-        // Big[l][q][c'][a][a']
-#pragma unroll
-        for (int x = 0; x < kPD; ++x)
-#pragma unroll
-            for (int q = 0; q < kPD; ++q)
-                *reinterpret_cast<float4*>(Big + ((l * kPD + q) * kPX + cp) * 16 + x * kPD) =
-                    make_float4(T1[x][0][q], T1[x][1][q], T1[x][2][q], T1[x][3][q]);
-    } else {
-        // Big[u][c'][l][b][b']
-#pragma unroll
-        for (int x = 0; x < kPD; ++x)
-#pragma unroll
-            for (int y = 0; y < kPD; ++y)
-                *reinterpret_cast<float4*>(Big + ((y * kPX + cp) * kPX + l) * 16 + x * kPD) =
-                    make_float4(T1[x][y][0], T1[x][y][1], T1[x][y][2], T1[x][y][3]);
-    }
-    __syncthreads();
-    // ---- last contraction: each thread a 4 x 4 block of outputs ----
-    double* Y = a.Y + (long long)b * a.ys;
+    // ---- last contraction, each thread a 4 x 4 block of outputs, over the third
+    // temporary staged in LDS in two halves of its contracted index (l forward, u
+    // backward; the halves keep the ascending order of every sum) ----
     float acc[kPD][kPD];
 #pragma unroll
     for (int x = 0; x < kPD; ++x)
 #pragma unroll
         for (int y = 0; y < kPD; ++y) acc[x][y] = 0.f;
-    if (FWD) {
-        // thread (c', a, l' group): Pout[c'][a][a'][l'] = sum_{l,q} T3[l][c'][a][a'][q] L[l][q][l']
-        const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;
-        for (int l2 = 0; l2 < cl; ++l2) {
-#pragma unroll
-            for (int q = 0; q < kPD; ++q) {
-                const float4 t = ld4(Big + ((l2 * kPD + q) * kPX + c2) * 16 + aa * kPD);
-                const float4 lv = ld4(Le + (l2 * kPD + q) * kPX + lg * kPD);
-                const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {lv.x, lv.y, lv.z, lv.w};
+    const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;        // FWD roles
+    const int bb = tid >> 6, l2 = (tid >> 2) & 15, cg = tid & 3;        // BWD roles
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();   // the previous readers of Big are done
+        if (FWD) {
+            // Big[l - 8 half][q][c'][a][a']
+            if ((l >> 3) == half) {
 #pragma unroll
                 for (int x = 0; x < kPD; ++x)
 #pragma unroll
-                    for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(tv[x], wv[y], acc[x][y]);
+                    for (int q = 0; q < kPD; ++q)
+                        *reinterpret_cast<float4*>(Big + (((l & 7) * kPD + q) * kPX + cp) * 16 + x * kPD) =
+                            make_float4(T1[x][0][q], T1[x][1][q], T1[x][2][q], T1[x][3][q]);
+            }
+        } else {
+            // Big[u - 2 half][c'][l][b][b']
+#pragma unroll
+            for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    *reinterpret_cast<float4*>(Big + ((y * kPX + cp) * kPX + l) * 16 + x * kPD) =
+                        make_float4(T1[x][y + 2 * half][0], T1[x][y + 2 * half][1], T1[x][y + 2 * half][2],
+                                    T1[x][y + 2 * half][3]);
+        }
+        __syncthreads();
+        if (FWD) {
+            // Pout[c'][a][a'][l'] = sum_{l,q} T3[l][c'][a][a'][q] L[l][q][l']
+            const int lend = cl < 8 * half + 8 ? cl : 8 * half + 8;
+            for (int lw = 8 * half; lw < lend; ++lw) {
+                float4 t[kPD], lv[kPD];
+#pragma unroll
+                for (int q = 0; q < kPD; ++q) {
+                    t[q] = ld4(Big + (((lw & 7) * kPD + q) * kPX + c2) * 16 + aa * kPD);
+                    lv[q] = ld4(Le + (lw * kPD + q) * kPX + lg * kPD);
+                }
+#pragma unroll
+                for (int q = 0; q < kPD; ++q) {
+                    const float tv[kPD] = {t[q].x, t[q].y, t[q].z, t[q].w};
+                    const float wv[kPD] = {lv[q].x, lv[q].y, lv[q].z, lv[q].w};
+#pragma unroll
+                    for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                        for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(tv[x], wv[y], acc[x][y]);
+                }
+            }
+        } else {
+            // Qout[c][b][b'][l] = sum_{u,c'} U[c][u][c'] T3[b][u][b'][l][c']
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int u = y + 2 * half;
+                for (int cc = 0; cc < cu1; ++cc) {
+                    const float4 t = ld4(Big + ((y * kPX + cc) * kPX + l2) * 16 + bb * kPD);
+                    const float4 uv = ld4(Ue + (u * kPX + cc) * kPX + cg * kPD);
+                    const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+                    for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                        for (int z = 0; z < kPD; ++z) acc[x][z] = fmaf(wv[z], tv[x], acc[x][z]);
+                }
             }
         }
+    }
+    double* Y = a.Y + (long long)b * a.ys;
+    if (FWD) {
         if (c2 < cu1 && aa < h1) {
 #pragma unroll
             for (int x = 0; x < kPD; ++x) {
@@ -256,20 +299,6 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
             }
         }
     } else {
-        // thread (b, l, c group): Qout[c][b][b'][l] = sum_{u,c'} U[c][u][c'] T3[b][u][b'][l][c']
-        const int bb = tid >> 6, l2 = (tid >> 2) & 15, cg = tid & 3;
-#pragma unroll
-        for (int u = 0; u < kPD; ++u) {
-            for (int c2 = 0; c2 < cu1; ++c2) {
-                const float4 t = ld4(Big + ((u * kPX + c2) * kPX + l2) * 16 + bb * kPD);
-                const float4 uv = ld4(Ue + (u * kPX + c2) * kPX + cg * kPD);
-                const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-                for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                    for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(wv[y], tv[x], acc[x][y]);
-            }
-        }
         if (bb < h && l2 < cl) {
             const long long ms = (long long)h * h * cl;
 #pragma unroll
