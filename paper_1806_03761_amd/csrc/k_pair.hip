@@ -313,6 +313,174 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     }
 }
 
+// Fused single-row sandwich step (three GEMMs: environment, site, environment) in
+// float32, same scheme as the two-row step: thread (l, c') holds its D^2 slices of the
+// two temporaries in registers, the last contraction goes through LDS, every sum keeps
+// the order of its unfused GEMM.
+//   FWD: P[c][b][l] -> Pout[c'][a][l'];  BWD: Q[c'][a][l'] -> Qout[c][b][l]
+//   U[c][u][c'], L[l][d][l'], S[b][u][a][d] site (i,j) (left, up, right, down).
+static constexpr int kRowLds = 3 * 1024 + 4096;   // floats
+
+bool row_step_fits(const RowArgs& a) {
+    const int legs[4] = {a.h, a.h1, a.Du, a.Dd};
+    const int bonds[4] = {a.cu, a.cu1, a.cl, a.cl1};
+    for (int v : legs)
+        if (v < 1 || v > kPD) return false;
+    for (int v : bonds)
+        if (v < 1 || v > kPX) return false;
+    return true;
+}
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
+    extern __shared__ __align__(16) float sm[];
+    float* Xs = sm;              // incoming partial
+    float* Ue = Xs + 1024;       // upper environment
+    float* Le = Ue + 1024;       // lower environment
+    float* Ts = Le + 1024;       // second temporary
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (b >= a.batch) return;
+    const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1, Du = a.Du, Dd = a.Dd, h = a.h, h1 = a.h1;
+    const double* X = a.X + (long long)b * a.xs;
+    const double* U = a.U + (long long)b * a.us;
+    const double* L = a.L + (long long)b * a.ls;
+    const float* S = a.site + (long long)((a.sel[(long long)b * a.sel_bs] ^ a.flip) & 1) * 512 + (FWD ? 0 : 256);
+    for (int e = tid; e < 1024; e += 256) {
+        if (FWD) {
+            {   // Xs[c][l][b] = P[c][b][l]
+                const int c = e >> 6, l = (e >> 2) & 15, bb = e & 3;
+                Xs[e] = (c < cu && l < cl && bb < h) ? (float)X[((long long)c * h + bb) * cl + l] : 0.f;
+            }
+            {   // Ue[c][c'][u]
+                const int c = e >> 6, cp = (e >> 2) & 15, u = e & 3;
+                Ue[e] = (c < cu && cp < cu1 && u < Du) ? (float)U[((long long)c * Du + u) * cu1 + cp] : 0.f;
+            }
+            {   // Le[l][d][l']
+                const int l = e >> 6, d = (e >> 4) & 3, lp = e & 15;
+                Le[e] = (l < cl && d < Dd && lp < cl1) ? (float)L[((long long)l * Dd + d) * cl1 + lp] : 0.f;
+            }
+        } else {
+            {   // Xs[l'][c'][a] = Q[c'][a][l']
+                const int lp = e >> 6, cp = (e >> 2) & 15, aa = e & 3;
+                Xs[e] = (lp < cl1 && cp < cu1 && aa < h1) ? (float)X[((long long)cp * h1 + aa) * cl1 + lp] : 0.f;
+            }
+            {   // Ue[u][c'][c]
+                const int u = e >> 8, cp = (e >> 4) & 15, c = e & 15;
+                Ue[e] = (c < cu && cp < cu1 && u < Du) ? (float)U[((long long)c * Du + u) * cu1 + cp] : 0.f;
+            }
+            {   // Le[l'][l][d]
+                const int lp = e >> 6, l = (e >> 2) & 15, d = e & 3;
+                Le[e] = (l < cl && d < Dd && lp < cl1) ? (float)L[((long long)l * Dd + d) * cl1 + lp] : 0.f;
+            }
+        }
+    }
+    __syncthreads();
+    const int l = tid >> 4, cp = tid & 15;
+    float T1[kPD][kPD], T2[kPD][kPD];
+#pragma unroll
+    for (int x = 0; x < kPD; ++x)
+#pragma unroll
+        for (int y = 0; y < kPD; ++y) T1[x][y] = T2[x][y] = 0.f;
+    if (FWD) {
+        // T1[b][u] = sum_c P[c][b][l] U[c][u][c']
+        for (int c = 0; c < cu; ++c) {
+            const float4 p4 = ld4(Xs + (c * kPX + l) * kPD), u4 = ld4(Ue + (c * kPX + cp) * kPD);
+            const float pv[kPD] = {p4.x, p4.y, p4.z, p4.w}, uv[kPD] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+            for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                for (int y = 0; y < kPD; ++y) T1[x][y] = fmaf(pv[x], uv[y], T1[x][y]);
+        }
+        // T2[a][d] = sum_{b,u} T1[b][u] S[b][u][a][d]
+#pragma unroll
+        for (int x = 0; x < kPD; ++x)
+#pragma unroll
+            for (int y = 0; y < kPD; ++y) {
+                const float* sp = S + (x * kPD + y) * 16;
+#pragma unroll
+                for (int r = 0; r < kPD; ++r)
+#pragma unroll
+                    for (int q = 0; q < kPD; ++q) T2[r][q] = fmaf(T1[x][y], sp[r * kPD + q], T2[r][q]);
+            }
+        // Ts[l][d][c'][a]
+#pragma unroll
+        for (int q = 0; q < kPD; ++q)
+            *reinterpret_cast<float4*>(Ts + ((l * kPD + q) * kPX + cp) * kPD) = make_float4(T2[0][q], T2[1][q], T2[2][q], T2[3][q]);
+    } else {
+        // T1[d][a] = sum_l' L[l][d][l'] Q[c'][a][l']
+        for (int lp = 0; lp < cl1; ++lp) {
+            const float4 q4 = ld4(Xs + (lp * kPX + cp) * kPD), l4 = ld4(Le + (lp * kPX + l) * kPD);
+            const float qv[kPD] = {q4.x, q4.y, q4.z, q4.w}, lv[kPD] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+            for (int x = 0; x < kPD; ++x)
+#pragma unroll
+                for (int y = 0; y < kPD; ++y) T1[x][y] = fmaf(lv[x], qv[y], T1[x][y]);
+        }
+        // T2[b][u] = sum_{a,d} S[b][u][a][d] T1[d][a]   (S in the order [a][d][b][u])
+#pragma unroll
+        for (int x = 0; x < kPD; ++x)
+#pragma unroll
+            for (int y = 0; y < kPD; ++y) {
+                const float* sp = S + (x * kPD + y) * 16;
+#pragma unroll
+                for (int r = 0; r < kPD; ++r)
+#pragma unroll
+                    for (int q = 0; q < kPD; ++q) T2[r][q] = fmaf(sp[r * kPD + q], T1[y][x], T2[r][q]);
+            }
+        // Ts[u][c'][l][b]
+#pragma unroll
+        for (int q = 0; q < kPD; ++q)
+            *reinterpret_cast<float4*>(Ts + ((q * kPX + cp) * kPX + l) * kPD) = make_float4(T2[0][q], T2[1][q], T2[2][q], T2[3][q]);
+    }
+    __syncthreads();
+    float acc[kPD] = {0.f, 0.f, 0.f, 0.f};
+    double* Y = a.Y + (long long)b * a.ys;
+    if (FWD) {
+        // thread (c', a, l' group): Pout[c'][a][l'] = sum_{l,d} T2[l][c'][a][d] L[l][d][l']
+        const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;
+        for (int l2 = 0; l2 < cl; ++l2)
+#pragma unroll
+            for (int d = 0; d < kPD; ++d) {
+                const float t = Ts[((l2 * kPD + d) * kPX + c2) * kPD + aa];
+                const float4 w = ld4(Le + (l2 * kPD + d) * kPX + lg * kPD);
+                acc[0] = fmaf(t, w.x, acc[0]);
+                acc[1] = fmaf(t, w.y, acc[1]);
+                acc[2] = fmaf(t, w.z, acc[2]);
+                acc[3] = fmaf(t, w.w, acc[3]);
+            }
+        if (c2 < cu1 && aa < h1)
+#pragma unroll
+            for (int y = 0; y < kPD; ++y)
+                if (lg * kPD + y < cl1) Y[((long long)c2 * h1 + aa) * cl1 + lg * kPD + y] = (double)acc[y];
+    } else {
+        // thread (l, b, c group): Qout[c][b][l] = sum_{u,c'} U[c][u][c'] T2[b][u][l][c']
+        const int l2 = tid >> 4, bb = (tid >> 2) & 3, cg = tid & 3;
+#pragma unroll
+        for (int u = 0; u < kPD; ++u)
+            for (int c2 = 0; c2 < cu1; ++c2) {
+                const float t = Ts[((u * kPX + c2) * kPX + l2) * kPD + bb];
+                const float4 w = ld4(Ue + (u * kPX + c2) * kPX + cg * kPD);
+                acc[0] = fmaf(w.x, t, acc[0]);
+                acc[1] = fmaf(w.y, t, acc[1]);
+                acc[2] = fmaf(w.z, t, acc[2]);
+                acc[3] = fmaf(w.w, t, acc[3]);
+            }
+        if (bb < h && l2 < cl)
+#pragma unroll
+            for (int y = 0; y < kPD; ++y)
+                if (cg * kPD + y < cu) Y[((long long)(cg * kPD + y) * h + bb) * cl + l2] = (double)acc[y];
+    }
+}
+
+hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    if (!row_step_fits(a)) return hipErrorInvalidValue;
+    const size_t bytes = kRowLds * sizeof(float);
+    if (fwd) hipLaunchKernelGGL(k_row_step<true>, dim3(a.batch), dim3(256), bytes, st, a);
+    else hipLaunchKernelGGL(k_row_step<false>, dim3(a.batch), dim3(256), bytes, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (!pair_step_fits(a)) return hipErrorInvalidValue;

@@ -68,6 +68,19 @@ struct PairArgs {
     int batch;
 };
 bool pair_step_fits(const PairArgs& a);
+// fused single-row sandwich step (float32, legs <= 4, boundary bonds <= 16)
+struct RowArgs {
+    int cu, cu1, cl, cl1, Du, Dd, h, h1;
+    const double* X; long long xs;       // incoming partial (P forward, Q backward)
+    const double* U; long long us;       // upper environment [cu][Du][cu1]
+    const double* L; long long ls;       // lower environment [cl][Dd][cl1]
+    const float* site;                   // site table of (i, j)
+    const int8_t* sel; long long sel_bs; int flip;
+    double* Y; long long ys;
+    int batch;
+};
+bool row_step_fits(const RowArgs& a);
+hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st);
 // float32 site tables of the fused step: 512 floats per (site, spin), see k_pair.hip
 hipError_t launch_site_tables(const double* A, float* T, int Lx, int Ly, int D, hipStream_t st);
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st);

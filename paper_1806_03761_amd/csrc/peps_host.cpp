@@ -111,7 +111,7 @@ public:
         ar_sw = prec == PEPS_PREC_F64 ? Arith::F64 : Arith::F32;
         const char* sv = getenv("PEPS_SVD");
         use_eig = !(sv && strcmp(sv, "jacobi") == 0);
-        // fused two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the four-GEMM form)
+        // fused single- and two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the GEMM form)
         const char* fz = getenv("PEPS_FUSE");
         fuse_pairs = ar_sw == Arith::F32 && D <= 4 && !(fz && strcmp(fz, "0") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
@@ -495,8 +495,38 @@ public:
         return hipSuccess;
     }
 
+    // the single-row step as one fused kernel when it fits (done = false: use the GEMMs)
+    hipError_t row_fused(int i, int j, Op X, int flip, Op Y, bool fwd, bool& done) {
+        done = false;
+        if (!fuse_pairs) return hipSuccess;
+        RowArgs a;
+        a.cu = chiU[i][j]; a.cu1 = chiU[i][j + 1]; a.cl = chiL[i][j]; a.cl1 = chiL[i][j + 1];
+        a.Du = Dv[i]; a.Dd = Dv[i + 1]; a.h = Dh[j]; a.h1 = Dh[j + 1];
+        if (!row_step_fits(a)) return hipSuccess;
+        const long long nl = (long long)a.cu * a.h * a.cl, nr = (long long)a.cu1 * a.h1 * a.cl1;
+        const Op U = envU(i, j), L = envL(i, j);
+        if (!bounds_ok("row in", X, (fwd ? nl : nr) - 1, 0) || !bounds_ok("row out", Y, (fwd ? nr : nl) - 1, 0) ||
+            !bounds_ok("row U", U, (long long)a.cu * a.Du * a.cu1 - 1, 0) ||
+            !bounds_ok("row L", L, (long long)a.cl * a.Dd * a.cl1 - 1, 0))
+            return hipErrorInvalidValue;
+        if (X.f32 || Y.f32) return hipSuccess;
+        done = true;
+        if (dry) return hipSuccess;
+        a.X = X.p; a.xs = X.bs; a.U = U.p; a.us = U.bs; a.L = L.p; a.ls = L.bs;
+        a.site = reinterpret_cast<const float*>(buf(o_site32)) + ((long long)i * Lx + j) * 1024;
+        a.sel = Scur + (long long)i * Lx + j; a.sel_bs = N; a.flip = flip;
+        a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
+        const double fl = 2.0 * Bcur *
+                          ((double)a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.cl * a.cu1 * a.h1 * a.Dd * a.h * a.Du +
+                           (double)a.cu1 * a.h1 * a.cl1 * a.cl * a.Dd);
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_row_step(a, fwd, st_); });
+    }
+
     // P_{j+1} = step(P_j) of the row-i sandwich <U_i| row i |L_i>
     hipError_t row_fwd(int i, int j, Op P, int flip, Op Pout) {
+        bool done = false;
+        CK(row_fused(i, j, P, flip, Pout, true, done));
+        if (done) return hipSuccess;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
@@ -512,6 +542,9 @@ public:
 
     // Q_j = step(Q_{j+1}) from the right
     hipError_t row_bwd(int i, int j, Op Q, int flip, Op Qout) {
+        bool done = false;
+        CK(row_fused(i, j, Q, flip, Qout, false, done));
+        if (done) return hipSuccess;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
@@ -663,7 +696,7 @@ public:
         hipStream_t st = st_;
         KL(launch_check_configs(S, N, Bn, flags(), st));
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
-        if (fuse_pairs && want_eloc) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
+        if (fuse_pairs) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
         for (int i = 0; i + 1 < Ly; ++i) CK(trunc_step(true, i));
         const bool need_L = want_eloc || want_grad;
