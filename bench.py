@@ -55,6 +55,25 @@ def cpu_baseline(name: str, per_core: int = 8):
                       f"{cores} processes, numpy single-threaded; wall {dt:.1f} s"}
 
 
+# HBM traffic per launch of each kernel class, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
+# 256 MiB device copy (command and figures in profiles/); valid only for the kernel
+# sources they were taken on (hash below), otherwise reported as null.
+TRAFFIC = {"sources": "714fed1354dcbf1a",
+           "bytes_per_launch": {"svd": 524684024, "qr": 460542419, "gemm": 143302544, "fused": 102284016}}
+
+
+def _sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_1806_03761_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,14 +127,15 @@ def main():
         step()
     torch.cuda.synchronize()
     # kernels of the timed region are bracketed by HIP events on the library's stream
-    peps.profile_enable(("gemm", "qr", "svd"))
+    classes = ("gemm", "fused", "qr", "svd")
+    peps.profile_enable(classes)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern = {}
-    for cls in ("svd", "qr", "gemm"):
+    for cls in classes:
         kms, n, fl = peps.profile_read(cls)
         kern[cls] = {"ms_total": kms, "launches": n, "avg_us": 1e3 * kms / max(n, 1),
                      "tflops": fl / max(kms, 1e-12) / 1e9}
@@ -143,14 +163,19 @@ def main():
                    "autotuned_gemm_shapes": tuned},
     }
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
-    # peaks: MI355X fp64 vector (= fp64 matrix) 78.6 TFLOP/s; fp32 matrix 157.3;
-    # bf16 matrix 2516.6 (dense)
-    gemm_peak = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}[args.prec]
-    bound, peak = ("alu", 78.6) if dom in ("svd", "qr") else ("mfma", gemm_peak)
-    res["roofline"] = {"kernel": {"svd": "k_svd", "qr": "k_qr", "gemm": "k_gemm"}[dom],
-                       "bound": bound, "achieved": kern[dom]["tflops"], "peak": peak,
-                       "unit": "TFLOP/s", "frac": kern[dom]["tflops"] / peak, "traffic": None,
-                       "avg_launch_us": kern[dom]["avg_us"]}
+    # every class runs on the vector ALUs (fma), none on the matrix cores: MI355X vector
+    # peaks fp64 78.6 TFLOP/s, fp32 157.3 TFLOP/s.  The factorisations are fp64; the
+    # contractions compute in fp32 for f32 and bf16 (bf16 only rounds the apply inputs)
+    con_peak = 78.6 if args.prec == "f64" else 157.3
+    peak = 78.6 if dom in ("svd", "qr") else con_peak
+    names = {"svd": "truncation step (k_eig_applyq + k_eig_tridiag + k_eig_tri + k_eig_fin)",
+             "qr": "k_qr_cols", "gemm": "k_gemm / k_gemm_rows", "fused": "k_pair_step / k_row_step"}
+    traffic = None
+    if TRAFFIC["sources"] == _sources_hash() and args.prec == "f32" and B == 4096:
+        traffic = TRAFFIC["bytes_per_launch"].get(dom)
+    res["roofline"] = {"kernel": names[dom], "bound": "alu", "achieved": kern[dom]["tflops"],
+                       "peak": peak, "unit": "TFLOP/s", "frac": kern[dom]["tflops"] / peak,
+                       "traffic": traffic, "avg_launch_us": kern[dom]["avg_us"]}
     res["kernels"] = kern
     if not args.no_plain:
         # plain path: the same library, batch 1, f64 GEMMs, one sample at a time

@@ -170,13 +170,14 @@ peps_status peps_tune_save(peps_ctx* ctx, const char* path);
 peps_status peps_tune_load(peps_ctx* ctx, const char* path);
 
 /* Kernel classes for the profiling calls below. */
-enum { PEPS_KC_GEMM = 0, PEPS_KC_QR = 1, PEPS_KC_SVD = 2 };
+enum { PEPS_KC_GEMM = 0, PEPS_KC_QR = 1, PEPS_KC_SVD = 2, PEPS_KC_FUSED = 3 };
 
 /* Start timing the launches of the kernel classes in `class_mask` (bit 1 << PEPS_KC_*):
  * each such launch is bracketed by two HIP events on the context's stream, together
- * with its algorithmic flop count (GEMM 2MNK; QR 2 r^2 (max(m,n) - r/3); SVD step:
- * implicit-Q apply 4 t (mz r - r^2/2) plus a thin SVD 4 a b^2 + 8 b^3 plus U_t Sigma_t
- * 2 m n t).  Clears earlier records; 0 turns timing off. */
+ * with its algorithmic flop count (GEMM 2MNK; fused single-/two-row sandwich step: the
+ * 2MNK of the three / four GEMMs it replaces; QR 2 r^2 (max(m,n) - r/3); truncation
+ * step: implicit-Q apply 4 t (mz r - r^2/2) plus a thin SVD 4 a b^2 + 8 b^3 plus
+ * U_t Sigma_t 2 m n t).  Clears earlier records; 0 turns timing off. */
 peps_status peps_profile_enable(peps_ctx* ctx, uint32_t class_mask);
 
 /* Synchronise the context's stream and report, for one kernel class, the summed

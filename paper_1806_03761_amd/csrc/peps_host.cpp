@@ -519,7 +519,7 @@ public:
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.cl * a.cu1 * a.h1 * a.Dd * a.h * a.Du +
                            (double)a.cu1 * a.h1 * a.cl1 * a.cl * a.Dd);
-        return timed(PEPS_KC_GEMM, fl, [&] { return launch_row_step(a, fwd, st_); });
+        return timed(PEPS_KC_FUSED, fl, [&] { return launch_row_step(a, fwd, st_); });
     }
 
     // P_{j+1} = step(P_j) of the row-i sandwich <U_i| row i |L_i>
@@ -587,7 +587,7 @@ public:
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
                            (double)a.cl * a.cu1 * a.h1 * a.h1 * a.Dq * a.h * a.Dm + (double)a.cu1 * a.h1 * a.h1 * a.cl1 * a.cl * a.Dq);
-        return timed(PEPS_KC_GEMM, fl, [&] { return launch_pair_step(a, fwd, st_); });
+        return timed(PEPS_KC_FUSED, fl, [&] { return launch_pair_step(a, fwd, st_); });
     }
 
     hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout) {

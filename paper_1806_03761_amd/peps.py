@@ -149,11 +149,11 @@ def plan_check(lat, batch: int, grad_mode: int = 3, want_eloc: bool = True) -> i
     return int(out.value)
 
 
-KERNEL_CLASS = {"gemm": 0, "qr": 1, "svd": 2}
+KERNEL_CLASS = {"gemm": 0, "qr": 1, "svd": 2, "fused": 3}
 
 
 def profile_enable(classes=(), device: int = 0):
-    """Time every launch of the given kernel classes ("gemm", "qr", "svd") with HIP
+    """Time every launch of the given kernel classes ("gemm", "qr", "svd", "fused") with HIP
     events on the context's stream; () turns timing off."""
     lib, ctx = _context(device)
     mask = 0
