@@ -66,6 +66,23 @@ hipError_t launch_site_tables(const double* A, float* T, int Lx, int Ly, int D, 
 
 __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+// Max-abs rescaling of the step's output, as the separate rescale kernel does it: the
+// largest |entry| of the sample over the whole workgroup, entries multiplied by its
+// reciprocal, its log added to the running log.  Returns the factor (1 when the max is
+// 0 or not finite).
+__device__ inline double step_rescale(double local_max, const double* lin, double* lout, int b,
+                                      double* red) {
+    double m = local_max;
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const bool ok = m > 0.0 && isfinite(m);
+    if (threadIdx.x == 0) lout[b] = (lin ? lin[b] : 0.0) + (ok ? log(m) : 0.0);
+    return ok ? 1.0 / m : 1.0;
+}
+
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     extern __shared__ __align__(16) float sm[];
@@ -287,6 +304,17 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
         }
     }
     double* Y = a.Y + (long long)b * a.ys;
+    double scale = 1.0;
+    if (a.lout) {
+        // padding entries are exact zeros, so the max over all of acc is the sample's max
+        double mx = 0.0;
+#pragma unroll
+        for (int x = 0; x < kPD; ++x)
+#pragma unroll
+            for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[x][y]));
+        __shared__ double red[4];
+        scale = step_rescale(mx, a.lin, a.lout, b, red);
+    }
     if (FWD) {
         if (c2 < cu1 && aa < h1) {
 #pragma unroll
@@ -295,7 +323,7 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
                 double* yo = Y + (((long long)c2 * h1 + aa) * h1 + x) * cl1;
 #pragma unroll
                 for (int y = 0; y < kPD; ++y)
-                    if (lg * kPD + y < cl1) yo[lg * kPD + y] = (double)acc[x][y];
+                    if (lg * kPD + y < cl1) yo[lg * kPD + y] = (double)acc[x][y] * scale;
             }
         }
     } else {
@@ -307,7 +335,7 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
                 if (c >= cu) break;
 #pragma unroll
                 for (int x = 0; x < kPD; ++x)
-                    if (x < h) Y[(long long)c * ms + ((long long)bb * h + x) * cl + l2] = (double)acc[x][y];
+                    if (x < h) Y[(long long)c * ms + ((long long)bb * h + x) * cl + l2] = (double)acc[x][y] * scale;
             }
         }
     }
@@ -435,6 +463,7 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
     __syncthreads();
     float acc[kPD] = {0.f, 0.f, 0.f, 0.f};
     double* Y = a.Y + (long long)b * a.ys;
+    __shared__ double red[4];
     if (FWD) {
         // thread (c', a, l' group): Pout[c'][a][l'] = sum_{l,d} T2[l][c'][a][d] L[l][d][l']
         const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;
@@ -448,10 +477,17 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
                 acc[2] = fmaf(t, w.z, acc[2]);
                 acc[3] = fmaf(t, w.w, acc[3]);
             }
+        double scale = 1.0;
+        if (a.lout) {
+            double mx = 0.0;
+#pragma unroll
+            for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[y]));
+            scale = step_rescale(mx, a.lin, a.lout, b, red);
+        }
         if (c2 < cu1 && aa < h1)
 #pragma unroll
             for (int y = 0; y < kPD; ++y)
-                if (lg * kPD + y < cl1) Y[((long long)c2 * h1 + aa) * cl1 + lg * kPD + y] = (double)acc[y];
+                if (lg * kPD + y < cl1) Y[((long long)c2 * h1 + aa) * cl1 + lg * kPD + y] = (double)acc[y] * scale;
     } else {
         // thread (l, b, c group): Qout[c][b][l] = sum_{u,c'} U[c][u][c'] T2[b][u][l][c']
         const int l2 = tid >> 4, bb = (tid >> 2) & 3, cg = tid & 3;
@@ -465,10 +501,17 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
                 acc[2] = fmaf(w.z, t, acc[2]);
                 acc[3] = fmaf(w.w, t, acc[3]);
             }
+        double scale = 1.0;
+        if (a.lout) {
+            double mx = 0.0;
+#pragma unroll
+            for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[y]));
+            scale = step_rescale(mx, a.lin, a.lout, b, red);
+        }
         if (bb < h && l2 < cl)
 #pragma unroll
             for (int y = 0; y < kPD; ++y)
-                if (cg * kPD + y < cu) Y[((long long)(cg * kPD + y) * h + bb) * cl + l2] = (double)acc[y];
+                if (cg * kPD + y < cu) Y[((long long)(cg * kPD + y) * h + bb) * cl + l2] = (double)acc[y] * scale;
     }
 }
 

@@ -65,6 +65,7 @@ struct PairArgs {
     const float* site2;                  // and (i+1, j)
     const int8_t* sel1; const int8_t* sel2; long long sel_bs; int flip1, flip2;
     double* Y; long long ys;             // outgoing partial
+    const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
 };
 bool pair_step_fits(const PairArgs& a);
@@ -77,6 +78,7 @@ struct RowArgs {
     const float* site;                   // site table of (i, j)
     const int8_t* sel; long long sel_bs; int flip;
     double* Y; long long ys;
+    const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
 };
 bool row_step_fits(const RowArgs& a);

@@ -496,8 +496,10 @@ public:
     }
 
     // the single-row step as one fused kernel when it fits (done = false: use the GEMMs)
-    hipError_t row_fused(int i, int j, Op X, int flip, Op Y, bool fwd, bool& done) {
+    hipError_t row_fused(int i, int j, Op X, int flip, Op Y, bool fwd, bool& done, const double* lin,
+                         double* lout) {
         done = false;
+        step_rescaled = false;
         if (!fuse_pairs) return hipSuccess;
         RowArgs a;
         a.cu = chiU[i][j]; a.cu1 = chiU[i][j + 1]; a.cl = chiL[i][j]; a.cl1 = chiL[i][j + 1];
@@ -516,6 +518,8 @@ public:
         a.site = reinterpret_cast<const float*>(buf(o_site32)) + ((long long)i * Lx + j) * 1024;
         a.sel = Scur + (long long)i * Lx + j; a.sel_bs = N; a.flip = flip;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
+        a.lin = lin; a.lout = lout;
+        step_rescaled = lout != nullptr;
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.cl * a.cu1 * a.h1 * a.Dd * a.h * a.Du +
                            (double)a.cu1 * a.h1 * a.cl1 * a.cl * a.Dd);
@@ -523,10 +527,12 @@ public:
     }
 
     // P_{j+1} = step(P_j) of the row-i sandwich <U_i| row i |L_i>
-    hipError_t row_fwd(int i, int j, Op P, int flip, Op Pout) {
+    hipError_t row_fwd(int i, int j, Op P, int flip, Op Pout, const double* lin = nullptr,
+                       double* lout = nullptr) {
         bool done = false;
-        CK(row_fused(i, j, P, flip, Pout, true, done));
+        CK(row_fused(i, j, P, flip, Pout, true, done, lin, lout));
         if (done) return hipSuccess;
+        step_rescaled = false;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
@@ -541,10 +547,12 @@ public:
     }
 
     // Q_j = step(Q_{j+1}) from the right
-    hipError_t row_bwd(int i, int j, Op Q, int flip, Op Qout) {
+    hipError_t row_bwd(int i, int j, Op Q, int flip, Op Qout, const double* lin = nullptr,
+                       double* lout = nullptr) {
         bool done = false;
-        CK(row_fused(i, j, Q, flip, Qout, false, done));
+        CK(row_fused(i, j, Q, flip, Qout, false, done, lin, lout));
         if (done) return hipSuccess;
+        step_rescaled = false;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i][j], cl1 = chiL[i][j + 1];
         const long long Du = Dv[i], Dd = Dv[i + 1], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw);
@@ -561,8 +569,10 @@ public:
 
     // two-row sandwich <U_i| rows i, i+1 |L_{i+1}>, forward step
     // the two-row step as one fused kernel when it fits (done = false: use the GEMMs)
-    hipError_t pair_fused(int i, int j, Op X, int f1, int f2, Op Y, bool fwd, bool& done) {
+    hipError_t pair_fused(int i, int j, Op X, int f1, int f2, Op Y, bool fwd, bool& done, const double* lin,
+                          double* lout) {
         done = false;
+        step_rescaled = false;
         if (!fuse_pairs) return hipSuccess;
         PairArgs a;
         a.cu = chiU[i][j]; a.cu1 = chiU[i][j + 1]; a.cl = chiL[i + 1][j]; a.cl1 = chiL[i + 1][j + 1];
@@ -584,16 +594,20 @@ public:
         a.sel1 = Scur + (long long)i * Lx + j; a.sel2 = Scur + (long long)(i + 1) * Lx + j; a.sel_bs = N;
         a.flip1 = f1; a.flip2 = f2;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
+        a.lin = lin; a.lout = lout;
+        step_rescaled = lout != nullptr;
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
                            (double)a.cl * a.cu1 * a.h1 * a.h1 * a.Dq * a.h * a.Dm + (double)a.cu1 * a.h1 * a.h1 * a.cl1 * a.cl * a.Dq);
         return timed(PEPS_KC_FUSED, fl, [&] { return launch_pair_step(a, fwd, st_); });
     }
 
-    hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout) {
+    hipError_t pair_fwd(int i, int j, Op P, int f1, int f2, Op Pout, const double* lin = nullptr,
+                        double* lout = nullptr) {
         bool done = false;
-        CK(pair_fused(i, j, P, f1, f2, Pout, true, done));
+        CK(pair_fused(i, j, P, f1, f2, Pout, true, done, lin, lout));
         if (done) return hipSuccess;
+        step_rescaled = false;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
@@ -611,10 +625,12 @@ public:
         return hipSuccess;
     }
 
-    hipError_t pair_bwd(int i, int j, Op Q, int f1, int f2, Op Qout) {
+    hipError_t pair_bwd(int i, int j, Op Q, int f1, int f2, Op Qout, const double* lin = nullptr,
+                        double* lout = nullptr) {
         bool done = false;
-        CK(pair_fused(i, j, Q, f1, f2, Qout, false, done));
+        CK(pair_fused(i, j, Q, f1, f2, Qout, false, done, lin, lout));
         if (done) return hipSuccess;
+        step_rescaled = false;
         const long long cu = chiU[i][j], cu1 = chiU[i][j + 1], cl = chiL[i + 1][j], cl1 = chiL[i + 1][j + 1];
         const long long Du = Dv[i], Dm = Dv[i + 1], Dq = Dv[i + 2], h = Dh[j], h1 = Dh[j + 1];
         Op T1 = tmp(o_T[0], s_T, ar_sw), T2 = tmp(o_T[1], s_T, ar_sw), T3 = tmp(o_T[2], s_T, ar_sw);
@@ -713,9 +729,10 @@ public:
             for (int j = 0; j < Lx; ++j) {
                 Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
                 Op Po = op(o_P[j + 1], s_P[j + 1]);
-                CK(row_fwd(i, j, P, 0, Po));
-                KL(launch_rescale(Po.p, Po.bs, (int)(chiU[i][j + 1] * Dh[j + 1] * chiL[i][j + 1]),
-                                  buf(o_lP[j]), buf(o_lP[j + 1]), Bn, st));
+                CK(row_fwd(i, j, P, 0, Po, buf(o_lP[j]), buf(o_lP[j + 1])));
+                if (!step_rescaled)
+                    KL(launch_rescale(Po.p, Po.bs, (int)(chiU[i][j + 1] * Dh[j + 1] * chiL[i][j + 1]),
+                                      buf(o_lP[j]), buf(o_lP[j + 1]), Bn, st));
             }
             KL(launch_sandwich_value(buf(o_P[Lx]), s_P[Lx], buf(o_lP[Lx]), buf(o_lnW), buf(o_sgW), Bn, st));
             if (i == Ly - 1) {
@@ -728,9 +745,10 @@ public:
             for (int j = Lx - 1; j >= 1; --j) {
                 Op Q = (j + 1 == Lx) ? ones() : op(o_Q[j + 1], s_P[j + 1]);
                 Op Qo = op(o_Q[j], s_P[j]);
-                CK(row_bwd(i, j, Q, 0, Qo));
-                KL(launch_rescale(Qo.p, Qo.bs, (int)(chiU[i][j] * Dh[j] * chiL[i][j]),
-                                  buf(o_lQ[j + 1]), buf(o_lQ[j]), Bn, st));
+                CK(row_bwd(i, j, Q, 0, Qo, buf(o_lQ[j + 1]), buf(o_lQ[j])));
+                if (!step_rescaled)
+                    KL(launch_rescale(Qo.p, Qo.bs, (int)(chiU[i][j] * Dh[j] * chiL[i][j]),
+                                      buf(o_lQ[j + 1]), buf(o_lQ[j]), Bn, st));
             }
             if (want_eloc) {
                 for (int j = 0; j + 1 < Lx; ++j) {
@@ -754,10 +772,11 @@ public:
                 for (int j = 0; j < Lx; ++j) {
                     Op P = (j == 0) ? ones() : op(o_P2[j], s_P2[j]);
                     Op Po = op(o_P2[j + 1], s_P2[j + 1]);
-                    CK(pair_fwd(i, j, P, 0, 0, Po));
-                    KL(launch_rescale(Po.p, Po.bs,
-                                      (int)(chiU[i][j + 1] * Dh[j + 1] * Dh[j + 1] * chiL[i + 1][j + 1]),
-                                      buf(o_lP2[j]), buf(o_lP2[j + 1]), Bn, st));
+                    CK(pair_fwd(i, j, P, 0, 0, Po, buf(o_lP2[j]), buf(o_lP2[j + 1])));
+                    if (!step_rescaled)
+                        KL(launch_rescale(Po.p, Po.bs,
+                                          (int)(chiU[i][j + 1] * Dh[j + 1] * Dh[j + 1] * chiL[i + 1][j + 1]),
+                                          buf(o_lP2[j]), buf(o_lP2[j + 1]), Bn, st));
                 }
                 KL(launch_sandwich_value(buf(o_P2[Lx]), s_P2[Lx], buf(o_lP2[Lx]), buf(o_lnW2),
                                          buf(o_sgW2), Bn, st));
@@ -765,10 +784,11 @@ public:
                 for (int j = Lx - 1; j >= 1; --j) {
                     Op Q = (j + 1 == Lx) ? ones() : op(o_Q2[j + 1], s_P2[j + 1]);
                     Op Qo = op(o_Q2[j], s_P2[j]);
-                    CK(pair_bwd(i, j, Q, 0, 0, Qo));
-                    KL(launch_rescale(Qo.p, Qo.bs,
-                                      (int)(chiU[i][j] * Dh[j] * Dh[j] * chiL[i + 1][j]),
-                                      buf(o_lQ2[j + 1]), buf(o_lQ2[j]), Bn, st));
+                    CK(pair_bwd(i, j, Q, 0, 0, Qo, buf(o_lQ2[j + 1]), buf(o_lQ2[j])));
+                    if (!step_rescaled)
+                        KL(launch_rescale(Qo.p, Qo.bs,
+                                          (int)(chiU[i][j] * Dh[j] * Dh[j] * chiL[i + 1][j]),
+                                          buf(o_lQ2[j + 1]), buf(o_lQ2[j]), Bn, st));
                 }
                 for (int j = 0; j < Lx; ++j) {
                     Op P = (j == 0) ? ones() : op(o_P2[j], s_P2[j]);
@@ -852,6 +872,7 @@ public:
     size_t o_eig = 0;
     bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
     bool fuse_pairs = false;
+    bool step_rescaled = false;   // the last sandwich step also applied the max-abs rescale
 };
 
 size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create
