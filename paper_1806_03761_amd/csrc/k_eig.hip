@@ -90,7 +90,11 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
 //   pivot   the 16 lanes of the row group holding row k (== column k) form the
 //           reflector H_k = I - tau v v^T from entries k+1.. of that row (v_{k+1} = 1);
 //   p       = tau A v, row sums reduced over the 16 lanes of a segment;
-//   update  A <- A - v w^T - w v^T with w = p - (tau/2)(p.v) v on rows, columns > k.
+//   update  A <- A - v w^T - w v^T with w = p - (tau/2)(p.v) v on the whole register
+//           matrix.  That is the similarity H A H: it leaves the finished diagonal
+//           entries alone (v vanishes on indices <= k) and takes the rest of row and
+//           column k to (e_k, 0, ...) up to rounding; those entries are never read
+//           again, and the live trailing block gets exactly the masked update's values.
 // Entries beyond k+1 of v_k are stored in row k of Am for the back-transformation.
 // Two barriers per step; v and tau are double-buffered so the next pivot can run
 // while other waves still finish their update.
@@ -193,7 +197,7 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
 #pragma unroll
                 for (int w = 0; w < RB; ++w) {
                     const double wc = pc[w] - K * vc[w];
-                    if (r0 + u > k && c0 + w > k) A[u][w] -= vr[u] * wc + wr * vc[w];
+                    A[u][w] -= vr[u] * wc + wr * vc[w];
                 }
             }
         }
