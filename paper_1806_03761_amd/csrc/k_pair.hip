@@ -524,9 +524,205 @@ hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The two-row step on the matrix cores: the same four contractions as k_pair_step,
+// as 16x16x4 float32 MFMA tiles.  A 16x16x4 MFMA accumulates its four products into
+// each output in k order with one rounding per product, like a chain of fma, so a
+// 16-long sum split over four MFMAs keeps the ascending order of the vector form when
+// MFMA s takes k = 4s .. 4s+3, i.e. lane (i, g) supplies k = 4s + g as element s of its
+// operand.  Sums longer than 16 chain the MFMAs block by block, and padding adds exact
+// zeros, so every output is the vector form's value bit for bit.
+//
+// Work split (one sample per workgroup, four waves): a free bond is taken in chunks of
+// four (c' forward, l backward: free through all four contractions), and inside a
+// chunk wave w owns a second free index for the first three contractions (l in
+// [4w, 4w+4) forward, c' = w mod 4 backward), so those three run wave-locally through
+// the wave's own LDS tiles with no workgroup barrier.  Only the last contraction, which
+// sums over that index, reads the whole third temporary (two barriers per chunk).  The
+// first contraction's operand rows and the last one's B operand sit in registers for
+// the whole kernel, loaded straight from the float64 inputs.
+//
+// Tile rows are chosen so each MFMA result (lane (li, g), register r = row 4g + r,
+// column li) lands as four consecutive k entries of the next contraction: one 16-byte
+// LDS store per lane.  LDS positions are XOR-swizzled (t12_at, t3_at) so that these
+// stores and the 16-byte operand reads hit 16 distinct bank quads per 16 lanes.
+// ---------------------------------------------------------------------------
+typedef float mfma4_t __attribute__((ext_vector_type(4)));
+static constexpr int kPairMfmaLds = 4 * 2048 + 4096;   // floats: per-wave T1, T2; shared T3
+
+__device__ __forceinline__ mfma4_t mfma_k16(const float4& av, const float4& bv, mfma4_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
+    return acc;
+}
+
+// row R (of 64) of a 16-wide temporary, k quad q (k % 4 = q, k / 4 = offset in the quad)
+__device__ __forceinline__ int t12_at(int R, int q) { return R * 16 + 4 * (q ^ ((R >> 4) & 3)); }
+// row R of the 64-wide third temporary, k block kb, quad q
+__device__ __forceinline__ int t3_at(int R, int kb, int q) {
+    return R * 64 + 16 * (kb ^ (R & 3)) + 4 * (q ^ (((R >> 4) ^ (R >> 2)) & 3));
+}
+__device__ __forceinline__ void st4(float* p, const mfma4_t& v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+// LDS written by other lanes of this wave becomes readable: no reordering across this
+// point, and the wave's LDS stores complete first
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// B operand from a site table row (16 k entries in natural order): k = 4 s + g
+__device__ __forceinline__ float4 site_b(const float* row, int g) {
+    return make_float4(row[g], row[4 + g], row[8 + g], row[12 + g]);
+}
+__device__ __forceinline__ float ldz(bool ok, const double* p) { return ok ? (float)*p : 0.f; }
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
+    extern __shared__ __align__(16) float sm[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (b >= a.batch) return;
+    const int w = tid >> 6, li = tid & 15, g = (tid >> 4) & 3;
+    float* T1 = sm + w * 2048;   // this wave's first temporary, 64 rows x 16
+    float* T2 = T1 + 1024;       // this wave's second temporary, 64 rows x 16
+    float* T3 = sm + 8192;       // third temporary, 64 rows x 64, shared
+    const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
+    const int Du = a.Du, Dq = a.Dq, h = a.h, h1 = a.h1;
+    const double* X = a.X + (long long)b * a.xs;
+    const double* U = a.U + (long long)b * a.us;
+    const double* L = a.L + (long long)b * a.ls;
+    // site tables: FWD reads the second leg order ([right][down][left][up]), BWD the natural one
+    const float* S1 = a.site1 + (long long)((a.sel1[(long long)b * a.sel_bs] ^ a.flip1) & 1) * 512 + (FWD ? 256 : 0);
+    const float* S2 = a.site2 + (long long)((a.sel2[(long long)b * a.sel_bs] ^ a.flip2) & 1) * 512 + (FWD ? 256 : 0);
+
+    // ---- operands held in registers (element s of lane (li, g) is k = 4 s + g) ----
+    float4 xa[4];   // first contraction, A rows of tile tt
+    float4 wb[4];   // last contraction, B operand of k block kb
+    float4 ub[4];   // first contraction, B operand of chunk ch
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float v[4], x[4], y[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + g;
+            if (FWD) {
+                // P[c = k][b = li & 3][b' = t][l = 4w + li / 4]
+                const int bb = li & 3, l = 4 * w + (li >> 2);
+                v[s] = ldz(k < cu && bb < h && t < h && l < cl, X + (long long)k * h * h * cl + ((long long)bb * h + t) * cl + l);
+                // L[l = 4t + s][q = g][l' = li]
+                x[s] = ldz(4 * t + s < cl && g < Dq && li < cl1, L + ((long long)(4 * t + s) * Dq + g) * cl1 + li);
+                // U[c = k][u = li & 3][c' = 4t + li / 4]
+                const int u = li & 3, cp = 4 * t + (li >> 2);
+                y[s] = ldz(k < cu && u < Du && cp < cu1, U + ((long long)k * Du + u) * cu1 + cp);
+            } else {
+                // Q[c' = 4t + w][a = li / 4][a' = li & 3][l' = k]
+                const int cp = 4 * t + w, aa = li >> 2, ap = li & 3;
+                v[s] = ldz(cp < cu1 && aa < h1 && ap < h1 && k < cl1, X + (((long long)cp * h1 + aa) * h1 + ap) * cl1 + k);
+                // U[c = li][u = t][c' = k]
+                x[s] = ldz(li < cu && t < Du && k < cu1, U + ((long long)li * Du + t) * cu1 + k);
+                // L[l = 4t + li / 4][q = li & 3][l' = k]
+                const int l = 4 * t + (li >> 2), q = li & 3;
+                y[s] = ldz(l < cl && q < Dq && k < cl1, L + ((long long)l * Dq + q) * cl1 + k);
+            }
+        }
+        xa[t] = make_float4(v[0], v[1], v[2], v[3]);
+        wb[t] = make_float4(x[0], x[1], x[2], x[3]);
+        ub[t] = make_float4(y[0], y[1], y[2], y[3]);
+    }
+    const float4 s2b = site_b((FWD ? S1 : S2) + li * 16, g);
+    const float4 s3b = site_b((FWD ? S2 : S1) + li * 16, g);
+
+    const mfma4_t zero = {0.f, 0.f, 0.f, 0.f};
+    mfma4_t out[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t] = zero;
+    const int nch = ((FWD ? cu1 : cl) + 3) >> 2;
+    const int rread = 16 * (li & 3) + (li >> 2);   // operand row of a 16-wide temporary, tile 0
+    for (int ch = 0; ch < nch; ++ch) {
+        const float4 ubc = ch == 0 ? ub[0] : ch == 1 ? ub[1] : ch == 2 ? ub[2] : ub[3];
+        // first contraction.  FWD: T1[(b',l,cc)][(b,u)] = sum_c P[c][b][b'][l] U[c][u][c'],
+        // tile t = b', result row (b, l) = (r, 4w + g), column (cc, u).
+        // BWD: T1[(a,c',l)][(a',q)] = sum_l' Q[c'][a][a'][l'] L[l][q][l'], tile t: c' = 4t + w,
+        // result row (a', a) = (r, g), column (ll, q).
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const mfma4_t acc = mfma_k16(xa[t], ubc, zero);
+            const int R = FWD ? 16 * t + 4 * g + (li >> 2) : 16 * g + 4 * t + (li >> 2);
+            st4(T1 + t12_at(R, li & 3), acc);
+        }
+        wave_lds_sync();
+        // second contraction, tile t (FWD: l = 4w + t, BWD: c' = 4t + w).
+        // FWD: T2[(l,cc,a)][(b',m)] = sum_{(b,u)} T1 S1[b][u][a][m]; result row (b', cc) = (r, g).
+        // BWD: T2[(c',l,b')][(a,m)] = sum_{(a',q)} T1 S2[b'][m][a'][q]; result row (a, ll) = (r, g).
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4 av = ld4(T1 + t12_at(rread + 4 * t, g));
+            const mfma4_t acc = mfma_k16(av, s2b, zero);
+            st4(T2 + t12_at(16 * t + 4 * g + (li >> 2), li & 3), acc);
+        }
+        wave_lds_sync();
+        __syncthreads();   // every wave is done reading the previous chunk's third temporary
+        // third contraction, tile t (FWD: cc = t, BWD: ll = t).
+        // FWD: T3[(cc,a,a')][(l,q)] = sum_{(b',m)} T2 S2[b'][m][a'][q]; result row (l, a) = (4w + r, g).
+        // BWD: T3[(b,b',l)][(u,c')] = sum_{(a,m)} T2 S1[b][u][a][m]; result row (c', b') = (4r + w, g).
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4 av = ld4(T2 + t12_at(rread + 4 * t, g));
+            const mfma4_t acc = mfma_k16(av, s3b, zero);
+            if (FWD) st4(T3 + t3_at(16 * t + 4 * g + (li >> 2), w, li & 3), acc);
+            else st4(T3 + t3_at(16 * (li >> 2) + 4 * g + t, li & 3, w), acc);
+        }
+        __syncthreads();
+        // last contraction, rows 16 w .. 16 w + 15 of T3, k blocks in order.
+        // FWD: Pout[(cc,a,a')][l'] = sum_{(l,q)} T3 L[l][q][l'];  BWD: Qout[(b,b',l)][c] = sum_{(u,c')} T3 U[c][u][c']
+        mfma4_t acc = zero;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma_k16(ld4(T3 + t3_at(16 * w + li, kb, g)), wb[kb], acc);
+        out[ch] = acc;
+    }
+    // ---- optional max-abs rescale, then the store ----
+    double* Y = a.Y + (long long)b * a.ys;
+    double scale = 1.0;
+    if (a.lout) {
+        double mx = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) mx = fmax(mx, fabs((double)out[t][r]));
+        __shared__ double red[4];
+        scale = step_rescale(mx, a.lin, a.lout, b, red);
+    }
+    // chunk t, output row 16 w + 4 g + r, column li
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (FWD) {   // row (cc, a, a') = (w, g, r), column l' = li
+                const int cp = 4 * t + w;
+                if (t < nch && cp < cu1 && g < h1 && r < h1 && li < cl1)
+                    Y[(((long long)cp * h1 + g) * h1 + r) * cl1 + li] = (double)out[t][r] * scale;
+            } else {     // row (b, b', ll) = (w, g, r), column c = li
+                const int l = 4 * t + r;
+                if (t < nch && w < h && g < h && l < cl && li < cu)
+                    Y[(long long)li * h * h * cl + ((long long)w * h + g) * cl + l] = (double)out[t][r] * scale;
+            }
+        }
+}
+
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (!pair_step_fits(a)) return hipErrorInvalidValue;
+    if (a.mfma) {
+        const size_t mb = kPairMfmaLds * sizeof(float);
+        if (mb + 64 > get_lds_cap()) return hipErrorInvalidValue;
+        if (fwd) hipLaunchKernelGGL(k_pair_mfma<true>, dim3(a.batch), dim3(256), mb, st, a);
+        else hipLaunchKernelGGL(k_pair_mfma<false>, dim3(a.batch), dim3(256), mb, st, a);
+        return hipGetLastError();
+    }
     const size_t bytes = kPairLds * sizeof(float);
     if (fwd) hipLaunchKernelGGL(k_pair_step<true>, dim3(a.batch), dim3(256), bytes, st, a);
     else hipLaunchKernelGGL(k_pair_step<false>, dim3(a.batch), dim3(256), bytes, st, a);

@@ -67,6 +67,7 @@ struct PairArgs {
     double* Y; long long ys;             // outgoing partial
     const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
+    int mfma;                            // 1: the matrix-core form (float32 MFMA)
 };
 bool pair_step_fits(const PairArgs& a);
 // fused single-row sandwich step (float32, legs <= 4, boundary bonds <= 16)

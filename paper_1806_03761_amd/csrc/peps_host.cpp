@@ -114,6 +114,10 @@ public:
         // fused single- and two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the GEMM form)
         const char* fz = getenv("PEPS_FUSE");
         fuse_pairs = ar_sw == Arith::F32 && D <= 4 && !(fz && strcmp(fz, "0") == 0);
+        // the two-row step on the matrix cores (PEPS_PAIR=valu keeps the vector form,
+        // which matches the GEMM path bit for bit)
+        const char* pz = getenv("PEPS_PAIR");
+        pair_mfma = !(pz && strcmp(pz, "valu") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -595,6 +599,7 @@ public:
         a.flip1 = f1; a.flip2 = f2;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
         a.lin = lin; a.lout = lout;
+        a.mfma = pair_mfma ? 1 : 0;
         step_rescaled = lout != nullptr;
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
@@ -873,6 +878,7 @@ public:
     bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
     bool fuse_pairs = false;
     bool step_rescaled = false;   // the last sandwich step also applied the max-abs rescale
+    bool pair_mfma = true;
 };
 
 size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create

@@ -373,23 +373,33 @@ def test_autotune_keeps_results():
         p.tune_load(path)
 
 
-def test_fused_pair_step_matches_gemm_path():
-    """The fused two-row sandwich step accumulates every product in the order of its
-    four unfused GEMMs (float32 operands, fma, k ascending), so amplitudes, local
-    energies and log-derivatives equal those of the GEMM path exactly."""
+def _eval_env(p, Ad, Sd, lat, env):
     import os
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+def test_fused_pair_step_matches_gemm_path():
+    """The fused sandwich steps accumulate every product in the order of the unfused
+    GEMMs (float32 operands, fma, k ascending), so amplitudes, local energies and
+    log-derivatives equal those of the GEMM path exactly: the vector form of the
+    two-row step directly, the matrix-core form because each 16x16x4 MFMA sums its four
+    products in k order with one rounding per product and the operands are laid out so
+    that consecutive MFMAs take consecutive k."""
     p = _peps()
     lat, A, S, _ = make_workload("8x8_D4_Dc16", 37)
     Ad, Sd = _dev(A, S)
-    fused = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
-    old = os.environ.get("PEPS_FUSE")
-    os.environ["PEPS_FUSE"] = "0"
-    try:
-        plain = _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
-    finally:
-        if old is None:
-            del os.environ["PEPS_FUSE"]
-        else:
-            os.environ["PEPS_FUSE"] = old
-    for x, y in zip(fused, plain):
-        assert np.array_equal(x, y)
+    plain = _eval_env(p, Ad, Sd, lat, {"PEPS_FUSE": "0"})
+    for env in ({"PEPS_PAIR": "valu"}, {}):
+        fused = _eval_env(p, Ad, Sd, lat, env)
+        for name, x, y in zip(("log-amp", "sign", "E_loc", "grad", "flags"), fused, plain):
+            d = np.abs(np.asarray(x, np.float64) - np.asarray(y, np.float64))
+            assert np.array_equal(x, y), (env, name, int((d > 0).sum()), d.size, float(d.max()))
