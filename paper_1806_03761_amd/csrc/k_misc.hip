@@ -309,49 +309,84 @@ hipError_t launch_grad_store(const double* Dall, const int8_t* S, int N, int D4,
 }
 
 // out[m][s][e] (+)= sum over b in order of w_b [S_b[m] = s] Delta_b[m][e]; flagged samples skipped.
-__global__ void k_grad_reduce(const double* Dall, const int8_t* S, int N, int D4,
-                              const int8_t* flags, const double* w, int wmode, int accumulate,
-                              double* out, int batch) {
+// Batch sums of Eq. (5), in two passes so the whole grid reads Delta once: pass one,
+// block row p adds samples [p per, (p+1) per) in order, thread (m, e) keeping both the
+// weighted and the plain sum for each spin value of S_b[m]; pass two adds the partitions
+// in order.  Fixed partitions and orders make the result deterministic.
+__global__ void k_grad_partial(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
+                               const double* w, int batch, int per, double* ws1, double* ws0) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 2LL * N * D4) return;
-    const int m = (int)(e / (2 * D4));
-    const int rem = (int)(e % (2 * D4));
-    const int slice = rem / D4, k = rem % D4;
-    double acc = 0.0;
-    for (int b = 0; b < batch; ++b) {
+    const long long nd = (long long)N * D4;
+    if (e >= nd) return;
+    const int m = (int)(e / D4), k = (int)(e % D4);
+    double a1[2] = {0.0, 0.0}, a0[2] = {0.0, 0.0};
+    const int b0 = blockIdx.y * per, b1 = min(batch, b0 + per);
+    for (int b = b0; b < b1; ++b) {
         if (flags[b] != 0) continue;
-        if ((S[(long long)b * N + m] & 1) != slice) continue;
-        const double wb = (wmode == 2) ? 1.0 : w[b];
-        acc += wb * Dall[((long long)b * N + m) * D4 + k];
+        const int s = S[(long long)b * N + m] & 1;
+        const double d = Dall[((long long)b * N + m) * D4 + k];
+        const double wb = w ? w[b] : 1.0;
+        if (s) { a1[1] += wb * d; a0[1] += d; }
+        else { a1[0] += wb * d; a0[0] += d; }
     }
-    out[e] = accumulate ? out[e] + acc : acc;
+    const long long o = (long long)blockIdx.y * 2 * nd + (long long)m * 2 * D4 + k;
+    ws1[o] = a1[0]; ws1[o + D4] = a1[1];
+    if (ws0) { ws0[o] = a0[0]; ws0[o + D4] = a0[1]; }
 }
+__global__ void k_grad_parts_sum(const double* ws, int parts, long long n, int accumulate, double* out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int p = 0; p < parts; ++p) acc += ws[(long long)p * n + i];
+    out[i] = accumulate ? out[i] + acc : acc;
+}
+int grad_parts(int batch) { return batch / 64 < 1 ? 1 : (batch / 64 > kGradParts ? kGradParts : batch / 64); }
 hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
-                              const double* w, int wmode, int accumulate, double* out, int batch,
-                              hipStream_t st) {
+                              const double* w, int accumulate, double* out1, double* out0, double* ws,
+                              int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
-    const long long n = 2LL * N * D4;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, Dall, S, N,
-                       D4, flags, w, wmode, accumulate, out, batch);
+    const int parts = grad_parts(batch), per = (batch + parts - 1) / parts;
+    const long long nd = (long long)N * D4, n = 2 * nd;
+    double* ws1 = ws;
+    double* ws0 = out0 ? ws + (long long)parts * n : nullptr;
+    hipLaunchKernelGGL(k_grad_partial, dim3((unsigned)((nd + 255) / 256), parts), dim3(256), 0, st, Dall, S, N,
+                       D4, flags, w, batch, per, ws1, ws0);
+    hipLaunchKernelGGL(k_grad_parts_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ws1, parts, n,
+                       accumulate, out1);
+    if (out0)
+        hipLaunchKernelGGL(k_grad_parts_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ws0, parts,
+                           n, accumulate, out0);
     return hipGetLastError();
 }
 
-// acc[0] += sum of e_loc over flag-0 samples (in order), acc[1] += their count.
+// acc[0] (+)= sum of e_loc over flag-0 samples, acc[1] (+)= their count: 256 threads each
+// sum a contiguous run in order, thread 0 adds the runs in order.
 __global__ void k_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double ps[256], pc[256];
+    const int t = threadIdx.x, per = (batch + 255) / 256;
     double s = 0.0, c = 0.0;
-    for (int b = 0; b < batch; ++b)
+    for (int b = t * per; b < batch && b < (t + 1) * per; ++b)
         if (flags[b] == 0) {
             s += e_loc[b];
             c += 1.0;
         }
+    ps[t] = s;
+    pc[t] = c;
+    __syncthreads();
+    if (t != 0) return;
+    s = 0.0;
+    c = 0.0;
+    for (int i = 0; i < 256; ++i) {
+        s += ps[i];
+        c += pc[i];
+    }
     acc[0] = accumulate ? acc[0] + s : s;
     acc[1] = accumulate ? acc[1] + c : c;
 }
 hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_sums, dim3(1), dim3(64), 0, st, e_loc, flags, batch, acc, accumulate);
+    hipLaunchKernelGGL(k_energy_sums, dim3(1), dim3(256), 0, st, e_loc, flags, batch, acc, accumulate);
     return hipGetLastError();
 }
 

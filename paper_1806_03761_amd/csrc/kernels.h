@@ -115,11 +115,14 @@ hipError_t launch_grad_site(double* Dsite, long long bs, const double* A, const 
 // per-sample output out[b][m][s][D^4] (both slices written) from Delta[b][m][D^4]
 hipError_t launch_grad_store(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
                              double* out, int batch, hipStream_t st);
-// out[m][s][e] (+)= sum_b w_b [S_b[m] = s] Delta_b[m][e]; wmode 0/1: w[b], 2: ones.
-// Flagged samples are skipped.
+// out1[m][s][e] (+)= sum_b w_b [S_b[m] = s] Delta_b[m][e] (w null: ones) and, when out0 is
+// not null, out0 the same sum with unit weights.  Flagged samples are skipped.  ws holds
+// 2 * grad_parts(batch) * 2 N D4 doubles.
+static constexpr int kGradParts = 64;
+int grad_parts(int batch);
 hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
-                              const double* w, int wmode, int accumulate, double* out, int batch,
-                              hipStream_t st);
+                              const double* w, int accumulate, double* out1, double* out0, double* ws,
+                              int batch, hipStream_t st);
 hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate, hipStream_t st);
 hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,

@@ -287,6 +287,8 @@ public:
         o_acc = L.alloc(0, 8);
         o_G1 = want_g ? L.alloc(0, 2LL * N * D4) : 0;
         o_G0 = want_g ? L.alloc(0, 2LL * N * D4) : 0;
+        // partial sums of the batch reduction: 2 x grad_parts(Bc) partitions of 2 N D^4
+        o_gws = want_g ? L.alloc((4LL * N * D4 + kGradParts - 1) / kGradParts + 1, 4LL * N * D4) : 0;
     }
 
     static size_t lds_cap_bytes();
@@ -835,13 +837,11 @@ public:
             if (grad_mode == 1) {
                 KL(launch_grad_store(buf(o_delta), S, N, (int)D4, flags(), out, Bn, st));
             } else if (grad_mode == 2) {
-                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), weights, 0, !first_chunk, out,
-                                      Bn, st));
+                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), weights, !first_chunk, out,
+                                      nullptr, buf(o_gws), Bn, st));
             } else if (grad_mode == 3) {
-                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), eptr, 1, !first_chunk,
-                                      buf(o_G1), Bn, st));
-                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), nullptr, 2, !first_chunk,
-                                      buf(o_G0), Bn, st));
+                KL(launch_grad_reduce(buf(o_delta), S, N, (int)D4, flags(), eptr, !first_chunk, buf(o_G1),
+                                      buf(o_G0), buf(o_gws), Bn, st));
                 KL(launch_energy_sums(eptr, flags(), Bn, buf(o_acc), !first_chunk, st));
             }
         }
@@ -872,7 +872,7 @@ public:
     std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2;
     size_t o_site32 = 0;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
-        o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0;
+        o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0, o_gws;
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
     size_t o_eig = 0;
     bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
