@@ -55,6 +55,15 @@ __device__ inline long long gather_off(const Gather& g, int b) {
 // One DPP lane permutation of a double (both 32-bit halves moved alike).  Controls used:
 // 0xB1 swaps lanes 2i <-> 2i+1, 0x4E swaps pairs within a quad, 0x141 mirrors each half
 // row of 8 lanes, 0x140 mirrors each row of 16 lanes.
+// p[off] when ok, else zero, read without a branch: the load always goes to p[ok ? off : 0]
+// (p[0] must be readable), so a run of these issues back to back and waits once, where a
+// guarded load compiles to a branch that waits for its own result before the next one.
+template <class T>
+__device__ __forceinline__ T ld_or0(bool ok, const T* p, long long off) {
+    const T v = p[ok ? off : 0];
+    return ok ? v : T(0);
+}
+
 template <int CTRL>
 __device__ inline double dpp_perm(double x) {
     const long long b = __double_as_longlong(x);

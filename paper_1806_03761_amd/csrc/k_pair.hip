@@ -51,10 +51,9 @@ __global__ void k_site_tables(const double* A, float* T, int Lx, int Ly, int D) 
         const double* a = A + ((long long)s * 2 + sp) * D4;
         float* t = T + ((long long)s * 2 + sp) * 512;
         // natural order: (x0, x1, x2, x3) = (left, up, right, down)
-        t[tid] = (x0 < left && x1 < up && x2 < right && x3 < down) ? (float)a[x0 * D3 + x1 * D2 + x2 * D + x3] : 0.f;
+        t[tid] = (float)ld_or0(x0 < left && x1 < up && x2 < right && x3 < down, a, x0 * D3 + x1 * D2 + x2 * D + x3);
         // second order: (x0, x1, x2, x3) = (right, down, left, up)
-        t[256 + tid] = (x2 < left && x3 < up && x0 < right && x1 < down)
-                           ? (float)a[x2 * D3 + x3 * D2 + x0 * D + x1] : 0.f;
+        t[256 + tid] = (float)ld_or0(x2 < left && x3 < up && x0 < right && x1 < down, a, x2 * D3 + x3 * D2 + x0 * D + x1);
     }
 }
 
@@ -105,21 +104,19 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
         int c, u, cp;
         if (FWD) { c = e >> 6; cp = (e >> 2) & 15; u = e & 3; }     // Ue[c][c'][u]
         else { u = e >> 8; cp = (e >> 4) & 15; c = e & 15; }        // Ue[u][c'][c]
-        Ue[e] = (c < cu && u < Du && cp < cu1) ? (float)U[((long long)c * Du + u) * cu1 + cp] : 0.f;
+        Ue[e] = (float)ld_or0(c < cu && u < Du && cp < cu1, U, ((long long)c * Du + u) * cu1 + cp);
         int l, q, lp;
         if (FWD) { l = e >> 6; q = (e >> 4) & 3; lp = e & 15; }     // Le[l][q][l']
         else { lp = e >> 6; l = (e >> 2) & 15; q = e & 3; }         // Le[l'][l][q]
-        Le[e] = (l < cl && q < Dq && lp < cl1) ? (float)L[((long long)l * Dq + q) * cl1 + lp] : 0.f;
+        Le[e] = (float)ld_or0(l < cl && q < Dq && lp < cl1, L, ((long long)l * Dq + q) * cl1 + lp);
     }
     for (int e = tid; e < 4096; e += 256) {
         if (FWD) {   // Big[c][l][b][b'] = P[c][b][b'][l]
             const int c = e >> 8, l = (e >> 4) & 15, bb = (e >> 2) & 3, bp = e & 3;
-            Big[e] = (c < cu && l < cl && bb < h && bp < h)
-                         ? (float)X[(long long)c * h * h * cl + ((long long)bb * h + bp) * cl + l] : 0.f;
+            Big[e] = (float)ld_or0(c < cu && l < cl && bb < h && bp < h, X, (long long)c * h * h * cl + ((long long)bb * h + bp) * cl + l);
         } else {     // Big[l'][c'][a][a'] = Q[c'][a][a'][l']
             const int lp = e >> 8, cp = (e >> 4) & 15, aa = (e >> 2) & 3, ap = e & 3;
-            Big[e] = (lp < cl1 && cp < cu1 && aa < h1 && ap < h1)
-                         ? (float)X[(((long long)cp * h1 + aa) * h1 + ap) * cl1 + lp] : 0.f;
+            Big[e] = (float)ld_or0(lp < cl1 && cp < cu1 && aa < h1 && ap < h1, X, (((long long)cp * h1 + aa) * h1 + ap) * cl1 + lp);
         }
     }
     __syncthreads();
@@ -377,28 +374,28 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
         if (FWD) {
             {   // Xs[c][l][b] = P[c][b][l]
                 const int c = e >> 6, l = (e >> 2) & 15, bb = e & 3;
-                Xs[e] = (c < cu && l < cl && bb < h) ? (float)X[((long long)c * h + bb) * cl + l] : 0.f;
+                Xs[e] = (float)ld_or0(c < cu && l < cl && bb < h, X, ((long long)c * h + bb) * cl + l);
             }
             {   // Ue[c][c'][u]
                 const int c = e >> 6, cp = (e >> 2) & 15, u = e & 3;
-                Ue[e] = (c < cu && cp < cu1 && u < Du) ? (float)U[((long long)c * Du + u) * cu1 + cp] : 0.f;
+                Ue[e] = (float)ld_or0(c < cu && cp < cu1 && u < Du, U, ((long long)c * Du + u) * cu1 + cp);
             }
             {   // Le[l][d][l']
                 const int l = e >> 6, d = (e >> 4) & 3, lp = e & 15;
-                Le[e] = (l < cl && d < Dd && lp < cl1) ? (float)L[((long long)l * Dd + d) * cl1 + lp] : 0.f;
+                Le[e] = (float)ld_or0(l < cl && d < Dd && lp < cl1, L, ((long long)l * Dd + d) * cl1 + lp);
             }
         } else {
             {   // Xs[l'][c'][a] = Q[c'][a][l']
                 const int lp = e >> 6, cp = (e >> 2) & 15, aa = e & 3;
-                Xs[e] = (lp < cl1 && cp < cu1 && aa < h1) ? (float)X[((long long)cp * h1 + aa) * cl1 + lp] : 0.f;
+                Xs[e] = (float)ld_or0(lp < cl1 && cp < cu1 && aa < h1, X, ((long long)cp * h1 + aa) * cl1 + lp);
             }
             {   // Ue[u][c'][c]
                 const int u = e >> 8, cp = (e >> 4) & 15, c = e & 15;
-                Ue[e] = (c < cu && cp < cu1 && u < Du) ? (float)U[((long long)c * Du + u) * cu1 + cp] : 0.f;
+                Ue[e] = (float)ld_or0(c < cu && cp < cu1 && u < Du, U, ((long long)c * Du + u) * cu1 + cp);
             }
             {   // Le[l'][l][d]
                 const int lp = e >> 6, l = (e >> 2) & 15, d = e & 3;
-                Le[e] = (l < cl && d < Dd && lp < cl1) ? (float)L[((long long)l * Dd + d) * cl1 + lp] : 0.f;
+                Le[e] = (float)ld_or0(l < cl && d < Dd && lp < cl1, L, ((long long)l * Dd + d) * cl1 + lp);
             }
         }
     }
@@ -579,7 +576,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ float4 site_b(const float* row, int g) {
     return make_float4(row[g], row[4 + g], row[8 + g], row[12 + g]);
 }
-__device__ __forceinline__ float ldz(bool ok, const double* p) { return ok ? (float)*p : 0.f; }
 
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
@@ -603,35 +599,76 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
     float4 xa[4];   // first contraction, A rows of tile tt
     float4 wb[4];   // last contraction, B operand of k block kb
     float4 ub[4];   // first contraction, B operand of chunk ch
+    // offsets (element t * 4 + s of each group) with out-of-range entries sent to 0, then all
+    // loads issued before any conversion so they overlap
+    int ox[16], ow[16], ou[16];
+    unsigned mx = 0, mw = 0, mu = 0;   // bit t * 4 + s: entry in range
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        float v[4], x[4], y[4];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int k = 4 * s + g;
+            const int k = 4 * s + g, e = t * 4 + s;
+            bool okx, okw, oku;
+            int fx, fw, fu;
             if (FWD) {
                 // P[c = k][b = li & 3][b' = t][l = 4w + li / 4]
                 const int bb = li & 3, l = 4 * w + (li >> 2);
-                v[s] = ldz(k < cu && bb < h && t < h && l < cl, X + (long long)k * h * h * cl + ((long long)bb * h + t) * cl + l);
+                okx = k < cu && bb < h && t < h && l < cl;
+                fx = (k * h * h + bb * h + t) * cl + l;
                 // L[l = 4t + s][q = g][l' = li]
-                x[s] = ldz(4 * t + s < cl && g < Dq && li < cl1, L + ((long long)(4 * t + s) * Dq + g) * cl1 + li);
+                okw = 4 * t + s < cl && g < Dq && li < cl1;
+                fw = ((4 * t + s) * Dq + g) * cl1 + li;
                 // U[c = k][u = li & 3][c' = 4t + li / 4]
                 const int u = li & 3, cp = 4 * t + (li >> 2);
-                y[s] = ldz(k < cu && u < Du && cp < cu1, U + ((long long)k * Du + u) * cu1 + cp);
+                oku = k < cu && u < Du && cp < cu1;
+                fu = (k * Du + u) * cu1 + cp;
             } else {
                 // Q[c' = 4t + w][a = li / 4][a' = li & 3][l' = k]
                 const int cp = 4 * t + w, aa = li >> 2, ap = li & 3;
-                v[s] = ldz(cp < cu1 && aa < h1 && ap < h1 && k < cl1, X + (((long long)cp * h1 + aa) * h1 + ap) * cl1 + k);
+                okx = cp < cu1 && aa < h1 && ap < h1 && k < cl1;
+                fx = ((cp * h1 + aa) * h1 + ap) * cl1 + k;
                 // U[c = li][u = t][c' = k]
-                x[s] = ldz(li < cu && t < Du && k < cu1, U + ((long long)li * Du + t) * cu1 + k);
+                okw = li < cu && t < Du && k < cu1;
+                fw = (li * Du + t) * cu1 + k;
                 // L[l = 4t + li / 4][q = li & 3][l' = k]
                 const int l = 4 * t + (li >> 2), q = li & 3;
-                y[s] = ldz(l < cl && q < Dq && k < cl1, L + ((long long)l * Dq + q) * cl1 + k);
+                oku = l < cl && q < Dq && k < cl1;
+                fu = (l * Dq + q) * cl1 + k;
             }
+            ox[e] = okx ? fx : 0; ow[e] = okw ? fw : 0; ou[e] = oku ? fu : 0;
+            mx |= (unsigned)okx << e; mw |= (unsigned)okw << e; mu |= (unsigned)oku << e;
         }
-        xa[t] = make_float4(v[0], v[1], v[2], v[3]);
-        wb[t] = make_float4(x[0], x[1], x[2], x[3]);
-        ub[t] = make_float4(y[0], y[1], y[2], y[3]);
+    const double* Wsrc = FWD ? L : U;
+    const double* Usrc = FWD ? U : L;
+    {
+        double rx[16], rw[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rx[e] = X[ox[e]];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rw[e] = Wsrc[ow[e]];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float v[4], x[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                v[s] = (mx >> (t * 4 + s)) & 1 ? (float)rx[t * 4 + s] : 0.f;
+                x[s] = (mw >> (t * 4 + s)) & 1 ? (float)rw[t * 4 + s] : 0.f;
+            }
+            xa[t] = make_float4(v[0], v[1], v[2], v[3]);
+            wb[t] = make_float4(x[0], x[1], x[2], x[3]);
+        }
+    }
+    {
+        double ru[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) ru[e] = Usrc[ou[e]];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float y[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) y[s] = (mu >> (t * 4 + s)) & 1 ? (float)ru[t * 4 + s] : 0.f;
+            ub[t] = make_float4(y[0], y[1], y[2], y[3]);
+        }
     }
     const float4 s2b = site_b((FWD ? S1 : S2) + li * 16, g);
     const float4 s3b = site_b((FWD ? S2 : S1) + li * 16, g);
