@@ -29,6 +29,47 @@ __device__ inline typename ArithT<AR>::In to_in(double x) {
 }
 
 // WG of 256 threads as a 16x16 grid; each thread owns a (TM/16) x (TN/16) micro-tile.
+// Cooperative load of a TK x TW tile (rows of TW + 1 in LDS): entry (kk, ww) = src[off_w[ww] + off_k[kk]] (zero where
+// either offset is negative), threads striding over the TK * TW entries.  Every load
+// reads a valid address (entry 0 of the operand for padding) and all are issued before
+// the first conversion, so they overlap instead of each waiting on its own.
+template <int TK, int TW, Arith AR>
+__device__ __forceinline__ void tile_load(typename ArithT<AR>::In* dst, const long long* off_w,
+                                          const long long* off_k, int f32, const double* srcd,
+                                          const float* srcf, int tid) {
+    using In = typename ArithT<AR>::In;
+    constexpr int NE = TK * TW, NI = (NE + 255) / 256;
+    long long o[NI];
+    bool ok[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + 256 * i;
+        const bool in = NE % 256 == 0 || e < NE;
+        const long long ow = in ? off_w[e % TW] : -1, ok_ = in ? off_k[e / TW] : -1;
+        ok[i] = ow >= 0 && ok_ >= 0;
+        o[i] = ok[i] ? ow + ok_ : 0;
+    }
+    In v[NI];
+    if (f32) {
+        float x[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) x[i] = srcf[o[i]];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = ok[i] ? to_in<AR>((double)x[i]) : In(0);
+    } else {
+        double x[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) x[i] = srcd[o[i]];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = ok[i] ? to_in<AR>(x[i]) : In(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + 256 * i;
+        if (NE % 256 == 0 || e < NE) dst[(e / TW) * (TW + 1) + e % TW] = v[i];   // rows padded by one
+    }
+}
+
 template <int TM, int TN, int TK, Arith AR>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles_n) {
     using In = typename ArithT<AR>::In;
@@ -86,17 +127,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles
         }
         __syncthreads();
         // A tile: TK x TM, consecutive threads walk m (operand layouts vary, so no
-        // single order is coalesced for all of them)
-        for (int e = tid; e < TK * TM; e += 256) {
-            int kk = e / TM, mm = e % TM;
-            long long om = aoff_m[mm], ok = aoff_k[kk];
-            As[kk][mm] = (om >= 0 && ok >= 0) ? to_in<AR>(g.a_f32 ? (double)Af[om + ok] : Ab[om + ok]) : In(0);
-        }
-        for (int e = tid; e < TK * TN; e += 256) {
-            int kk = e / TN, nn = e % TN;
-            long long on = boff_n[nn], ok = boff_k[kk];
-            Bs[kk][nn] = (on >= 0 && ok >= 0) ? to_in<AR>(g.b_f32 ? (double)Bf[on + ok] : Bb[on + ok]) : In(0);
-        }
+        // single order is coalesced for all of them); B tile likewise.  All loads of a
+        // tile are issued before any is used.
+        tile_load<TK, TM, AR>(&As[0][0], aoff_m, aoff_k, g.a_f32, Ab, Af, tid);
+        tile_load<TK, TN, AR>(&Bs[0][0], boff_n, boff_k, g.b_f32, Bb, Bf, tid);
         __syncthreads();
 #pragma unroll 4
         for (int kk = 0; kk < TK; ++kk) {
@@ -153,14 +187,35 @@ __global__ __launch_bounds__(256) void k_gemm_rows(GemmArgs g, int blocks_m) {
     const long long a0 = (long long)b * g.a_bs + gather_off(g.ga, b);
     const long long b0 = (long long)b * g.b_bs + gather_off(g.gb, b);
     const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
-    for (int e = tid; e < g.K * NC; e += 256) {
-        const int k = e / NC, n = e % NC;
-        In v = In(0);
-        if (n < g.N) {
-            const long long o = b0 + idx_off(g.bk, k) + idx_off(g.bn, n);
-            v = to_in<AR>(g.b_f32 ? (double)reinterpret_cast<const float*>(g.B)[o] : g.B[o]);
+    // B staged in rounds of 8 loads per thread, each round's loads issued together
+    for (int e0 = 0; e0 < g.K * NC; e0 += 8 * 256) {
+        long long o[8];
+        bool ok[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + tid + 256 * i, k = e / NC, n = e % NC;
+            ok[i] = e < g.K * NC && n < g.N;
+            o[i] = b0 + (ok[i] ? idx_off(g.bk, k) + idx_off(g.bn, n) : 0);
         }
-        Bs[k][n] = v;
+        In v[8];
+        if (g.b_f32) {
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = reinterpret_cast<const float*>(g.B)[o[i]];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = ok[i] ? to_in<AR>((double)x[i]) : In(0);
+        } else {
+            double x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = g.B[o[i]];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = ok[i] ? to_in<AR>(x[i]) : In(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + tid + 256 * i;
+            if (e < g.K * NC) Bs[e / NC][e % NC] = v[i];
+        }
     }
     for (int k = tid; k < g.K; k += 256) koff[k] = idx_off(g.ak, k);
     for (int n = tid; n < NC; n += 256) coff_n[n] = n < g.N ? idx_off(g.cn, n) : 0;
