@@ -59,8 +59,8 @@ def cpu_baseline(name: str, per_core: int = 8):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "714fed1354dcbf1a",
-           "bytes_per_launch": {"svd": 524684024, "qr": 460542419, "gemm": 143302544, "fused": 102284016}}
+TRAFFIC = {"sources": "fa3e2638a23ad39d",
+           "bytes_per_launch": {"svd": 524639350, "qr": 460547339, "gemm": 143312674, "fused": 102279435}}
 
 
 def _sources_hash() -> str:
@@ -179,7 +179,7 @@ def main():
     con_peak = 78.6 if args.prec == "f64" else 157.3
     peak = 78.6 if dom in ("svd", "qr") else con_peak
     names = {"svd": "truncation step (k_eig_applyq + k_eig_tridiag + k_eig_tri + k_eig_fin)",
-             "qr": "k_qr_cols", "gemm": "k_gemm / k_gemm_rows", "fused": "k_pair_step / k_row_step"}
+             "qr": "k_qr_cols", "gemm": "k_gemm / k_gemm_rows", "fused": "k_pair_mfma / k_row_step"}
     traffic = None
     if TRAFFIC["sources"] == _sources_hash() and args.prec == "f32" and B == 4096:
         traffic = TRAFFIC["bytes_per_launch"].get(dom)
