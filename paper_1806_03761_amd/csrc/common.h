@@ -52,9 +52,6 @@ __device__ inline long long gather_off(const Gather& g, int b) {
     return (long long)((g.sel[(long long)b * g.sel_bs] ^ g.flip) & 1) * g.slice;
 }
 
-// One DPP lane permutation of a double (both 32-bit halves moved alike).  Controls used:
-// 0xB1 swaps lanes 2i <-> 2i+1, 0x4E swaps pairs within a quad, 0x141 mirrors each half
-// row of 8 lanes, 0x140 mirrors each row of 16 lanes.
 // p[off] when ok, else zero, read without a branch: the load always goes to p[ok ? off : 0]
 // (p[0] must be readable), so a run of these issues back to back and waits once, where a
 // guarded load compiles to a branch that waits for its own result before the next one.
@@ -64,6 +61,9 @@ __device__ __forceinline__ T ld_or0(bool ok, const T* p, long long off) {
     return ok ? v : T(0);
 }
 
+// One DPP lane permutation of a double (both 32-bit halves moved alike).  Controls used:
+// 0xB1 swaps lanes 2i <-> 2i+1, 0x4E swaps pairs within a quad, 0x141 mirrors each half
+// row of 8 lanes, 0x140 mirrors each row of 16 lanes.
 template <int CTRL>
 __device__ inline double dpp_perm(double x) {
     const long long b = __double_as_longlong(x);
@@ -72,16 +72,26 @@ __device__ inline double dpp_perm(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Lane l ^ 16 inside each group of 32 lanes (ds_swizzle in bit mode: and-mask 0x1F,
+// xor-mask 0x10), without the address round trip of ds_bpermute.
+__device__ inline double swz_xor16(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over aligned groups of `width` lanes (a power of two up to 64); every lane of a
 // group gets the bitwise-same total.  Inside a row of 16 lanes the partner values come
-// from DPP permutations (a few cycles each); across rows through ds_bpermute.  All lanes
-// of a group must be active.
+// from DPP permutations (a few cycles each); between the two rows of a 32-lane group
+// from ds_swizzle, between the two halves of the wave from ds_bpermute.  All lanes of a
+// group must be active.
 __device__ inline double lane_group_sum(double v, int width) {
     if (width >= 2) v += dpp_perm<0xB1>(v);
     if (width >= 4) v += dpp_perm<0x4E>(v);
     if (width >= 8) v += dpp_perm<0x141>(v);
     if (width >= 16) v += dpp_perm<0x140>(v);
-    if (width >= 32) v += __shfl_xor(v, 16, 64);
+    if (width >= 32) v += swz_xor16(v);
     if (width >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
