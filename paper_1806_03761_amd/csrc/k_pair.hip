@@ -535,7 +535,10 @@ hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
 // chunk wave w owns a second free index for the first three contractions (l in
 // [4w, 4w+4) forward, c' = w mod 4 backward), so those three run wave-locally through
 // the wave's own LDS tiles with no workgroup barrier.  Only the last contraction, which
-// sums over that index, reads the whole third temporary (two barriers per chunk).  The
+// sums over that index, reads the whole third temporary (one barrier per chunk: the
+// third temporary is double-buffered, and each wave's first and second temporaries
+// share one tile, every operand of the second contraction read before its results
+// overwrite them).  The
 // first contraction's operand rows and the last one's B operand sit in registers for
 // the whole kernel, loaded straight from the float64 inputs.
 //
@@ -545,7 +548,7 @@ hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
 // stores and the 16-byte operand reads hit 16 distinct bank quads per 16 lanes.
 // ---------------------------------------------------------------------------
 typedef float mfma4_t __attribute__((ext_vector_type(4)));
-static constexpr int kPairMfmaLds = 4 * 2048 + 4096;   // floats: per-wave T1, T2; shared T3
+static constexpr int kPairMfmaLds = 4 * 1024 + 2 * 4096;   // floats: per-wave T1/T2 tile; T3 x 2
 
 __device__ __forceinline__ mfma4_t mfma_k16(const float4& av, const float4& bv, mfma4_t acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
@@ -583,9 +586,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
     const int w = tid >> 6, li = tid & 15, g = (tid >> 4) & 3;
-    float* T1 = sm + w * 2048;   // this wave's first temporary, 64 rows x 16
-    float* T2 = T1 + 1024;       // this wave's second temporary, 64 rows x 16
-    float* T3 = sm + 8192;       // third temporary, 64 rows x 64, shared
+    float* T12 = sm + w * 1024;   // this wave's first, then second temporary, 64 rows x 16
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
     const int Du = a.Du, Dq = a.Dq, h = a.h, h1 = a.h1;
     const double* X = a.X + (long long)b * a.xs;
@@ -680,7 +681,9 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
     const int nch = ((FWD ? cu1 : cl) + 3) >> 2;
     const int rread = 16 * (li & 3) + (li >> 2);   // operand row of a 16-wide temporary, tile 0
     for (int ch = 0; ch < nch; ++ch) {
+        float* T3 = sm + 4096 + 4096 * (ch & 1);   // third temporary, 64 rows x 64, shared
         const float4 ubc = ch == 0 ? ub[0] : ch == 1 ? ub[1] : ch == 2 ? ub[2] : ub[3];
+        wave_lds_sync();   // the previous chunk's reads of T12 are done
         // first contraction.  FWD: T1[(b',l,cc)][(b,u)] = sum_c P[c][b][b'][l] U[c][u][c'],
         // tile t = b', result row (b, l) = (r, 4w + g), column (cc, u).
         // BWD: T1[(a,c',l)][(a',q)] = sum_l' Q[c'][a][a'][l'] L[l][q][l'], tile t: c' = 4t + w,
@@ -689,30 +692,34 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
         for (int t = 0; t < 4; ++t) {
             const mfma4_t acc = mfma_k16(xa[t], ubc, zero);
             const int R = FWD ? 16 * t + 4 * g + (li >> 2) : 16 * g + 4 * t + (li >> 2);
-            st4(T1 + t12_at(R, li & 3), acc);
+            st4(T12 + t12_at(R, li & 3), acc);
         }
         wave_lds_sync();
         // second contraction, tile t (FWD: l = 4w + t, BWD: c' = 4t + w).
         // FWD: T2[(l,cc,a)][(b',m)] = sum_{(b,u)} T1 S1[b][u][a][m]; result row (b', cc) = (r, g).
         // BWD: T2[(c',l,b')][(a,m)] = sum_{(a',q)} T1 S2[b'][m][a'][q]; result row (a, ll) = (r, g).
+        float4 av2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av2[t] = ld4(T12 + t12_at(rread + 4 * t, g));
+        wave_lds_sync();   // all of T1 read before T2 overwrites it
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float4 av = ld4(T1 + t12_at(rread + 4 * t, g));
-            const mfma4_t acc = mfma_k16(av, s2b, zero);
-            st4(T2 + t12_at(16 * t + 4 * g + (li >> 2), li & 3), acc);
+            const mfma4_t acc = mfma_k16(av2[t], s2b, zero);
+            st4(T12 + t12_at(16 * t + 4 * g + (li >> 2), li & 3), acc);
         }
         wave_lds_sync();
-        __syncthreads();   // every wave is done reading the previous chunk's third temporary
         // third contraction, tile t (FWD: cc = t, BWD: ll = t).
         // FWD: T3[(cc,a,a')][(l,q)] = sum_{(b',m)} T2 S2[b'][m][a'][q]; result row (l, a) = (4w + r, g).
         // BWD: T3[(b,b',l)][(u,c')] = sum_{(a,m)} T2 S1[b][u][a][m]; result row (c', b') = (4r + w, g).
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float4 av = ld4(T2 + t12_at(rread + 4 * t, g));
+            const float4 av = ld4(T12 + t12_at(rread + 4 * t, g));
             const mfma4_t acc = mfma_k16(av, s3b, zero);
             if (FWD) st4(T3 + t3_at(16 * t + 4 * g + (li >> 2), w, li & 3), acc);
             else st4(T3 + t3_at(16 * (li >> 2) + 4 * g + t, li & 3, w), acc);
         }
+        // T3 complete; its other buffer was last read before every wave passed the
+        // previous chunk's barrier, so the next chunk may refill it
         __syncthreads();
         // last contraction, rows 16 w .. 16 w + 15 of T3, k blocks in order.
         // FWD: Pout[(cc,a,a')][l'] = sum_{(l,q)} T3 L[l][q][l'];  BWD: Qout[(b,b',l)][c] = sum_{(u,c')} T3 U[c][u][c']
