@@ -61,6 +61,25 @@ __device__ __forceinline__ T ld_or0(bool ok, const T* p, long long off) {
     return ok ? v : T(0);
 }
 
+// dst[i] = src[i] for i in [0, n), by threads tid, tid + nth, ...: each thread issues its
+// loads in groups of 8 before storing them, instead of a load, wait and store per
+// element (a strided loop of unknown trip count is not unrolled by the compiler).
+__device__ inline void copy_strided(double* dst, const double* src, long long n, int tid, int nth) {
+    for (long long b0 = 0; b0 < n; b0 += 8LL * nth) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long long i = b0 + tid + (long long)u * nth;
+            v[u] = src[i < n ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long long i = b0 + tid + (long long)u * nth;
+            if (i < n) dst[i] = v[u];
+        }
+    }
+}
+
 // One DPP lane permutation of a double (both 32-bit halves moved alike).  Controls used:
 // 0xB1 swaps lanes 2i <-> 2i+1, 0x4E swaps pairs within a quad, 0x141 mirrors each half
 // row of 8 lanes, 0x140 mirrors each row of 16 lanes.

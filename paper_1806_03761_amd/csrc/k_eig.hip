@@ -311,9 +311,21 @@ __global__ __launch_bounds__(NT) void k_eig_applyq(EigArgs a, int kc) {
     for (int k1 = r - 1; k1 >= 0; k1 -= kc) {
         const int k0 = k1 - kc + 1 > 0 ? k1 - kc + 1 : 0, nk = k1 - k0 + 1;
         __syncthreads();
-        for (int e = tid; e < nk * LDV; e += NT) {
-            const int kk = e / LDV, i = e % LDV, k = k0 + kk;
-            vsh[e] = (i < k || i >= mz) ? 0.0 : (i == k ? 1.0 : V[(long long)k * mz + i]);
+        // reflectors k0..k1 zero-padded with the unit entry written out; loads in groups
+        for (int e0 = 0; e0 < nk * LDV; e0 += 8 * NT) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + tid + u * NT, kk = e / LDV, i = e % LDV, k = k0 + kk;
+                const bool in = e < nk * LDV;
+                const double raw = ld_or0(in && i > k && i < mz, V, (long long)k * mz + i);
+                v[u] = (in && i == k) ? 1.0 : raw;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + tid + u * NT;
+                if (e < nk * LDV) vsh[e] = v[u];
+            }
         }
         if (tid < nk) s_tq[tid] = tq[k0 + tid];
         __syncthreads();
@@ -432,7 +444,7 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
         // Z = Q [G; 0] was formed by k_eig_applyq in global scratch
         if constexpr (kLds) {
             const double* zg = a.scratch + (long long)b * a.ss + L.oZ;
-            for (long long e2 = tid; e2 < (long long)ldz * tin; e2 += NT) Z[e2] = zg[e2];
+            copy_strided(Z, zg, (long long)ldz * tin, tid, NT);
         }
     } else {
         for (int e2 = tid; e2 < mz * tin; e2 += NT) {
@@ -452,10 +464,7 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
         for (int k1 = r - 1; k1 >= 0; k1 -= kQc) {
             const int k0 = k1 - kQc + 1 > 0 ? k1 - kQc + 1 : 0;
             __syncthreads();
-            for (int e2 = tid; e2 < (k1 - k0 + 1) * mz; e2 += NT) {
-                const int kk = e2 / mz, i = e2 % mz;
-                vs[kk * mz + i] = V[(long long)(k0 + kk) * mz + i];
-            }
+            copy_strided(vs, V + (long long)k0 * mz, (long long)(k1 - k0 + 1) * mz, tid, NT);
             if (tid <= k1 - k0) s_tq[tid] = tq[k0 + tid];
             __syncthreads();
             for (int c0 = 0; c0 < tin; c0 += ngroups) {
@@ -639,12 +648,9 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
     for (int e2 = threadIdx.x; e2 < mats_per_block * n; e2 += blockDim.x) {
         const int m2 = e2 / n, i = e2 % n;
         const int b2 = blockIdx.x * mats_per_block + m2;
-        double dv = 0.0, ev = 0.0;
-        if (b2 < a.batch) {
-            const double* g2 = a.scratch + (long long)b2 * a.ss;
-            dv = g2[L.oD + i];
-            ev = (i + 1 < n) ? g2[L.oE + i] : 0.0;
-        }
+        const double* g2 = a.scratch + (long long)(b2 < a.batch ? b2 : 0) * a.ss;
+        const double dv = ld_or0(b2 < a.batch, g2, L.oD + i);
+        const double ev = ld_or0(b2 < a.batch && i + 1 < n, g2, L.oE + i);
         tri_lds[(3 * m2) * n + i] = dv;
         tri_lds[(3 * m2 + 1) * n + i] = ev;
         tri_lds[(3 * m2 + 2) * n + i] = ev * ev;
@@ -830,20 +836,29 @@ __device__ __forceinline__ void fin_vectors(double* X, const double* Am, const d
             }
         }
     }
-    // reflector k: unit entry at row k+1, entries beyond it in row k of Am
-    for (int k = ns - 3; k >= 0; --k) {
-        const double tq = tau[k];
-        if (tq == 0.0) continue;
+    // reflector k: unit entry at row k+1, entries beyond it in row k of Am.  Its entries
+    // are read without branches (row k's entry 0 stands in for the rows outside it), and
+    // those of reflector k - 1 are already in flight while reflector k is applied.
+    double vn[RPT], tn = 0.0;
+    const auto load_v = [&](int k, double (&v)[RPT], double& t) {
         const double* vk = Am + (long long)k * lda;
-        double v[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int i = zq_row<TPC>(q, l);
-            double vi = 0.0;
-            if (i == k + 1) vi = 1.0;
-            else if (i > k + 1 && i < ns) vi = vk[i];
-            v[q] = vi;
+            const bool in = i > k + 1 && i < ns;
+            const double raw = vk[in ? i : 0];
+            v[q] = i == k + 1 ? 1.0 : (in ? raw : 0.0);
         }
+        t = tau[k];
+    };
+    if (ns >= 3) load_v(ns - 3, vn, tn);
+    for (int k = ns - 3; k >= 0; --k) {
+        double v[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) v[q] = vn[q];
+        const double tq = tn;
+        if (k > 0) load_v(k - 1, vn, tn);
+        if (tq == 0.0) continue;
 #pragma unroll
         for (int s = 0; s < CPG; ++s) {
             if (g + s * NG >= tk) continue;
@@ -886,11 +901,11 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
         tau = Am + (long long)lda * ns;
         Z = tau + ns;
         lam = Z + (long long)ldz * tin;
-        for (long long i = tid; i < (long long)ldx * tk; i += NT) X[i] = gs[L.oX + i];
-        for (long long i = tid; i < (long long)lda * ns; i += NT) Am[i] = gs[L.oA + i];
-        for (int i = tid; i < ns; i += NT) tau[i] = gs[L.oT + i];
-        for (long long i = tid; i < (long long)ldz * tin; i += NT) Z[i] = gs[L.oZ + i];
-        for (int i = tid; i < tk; i += NT) lam[i] = gs[L.oL + i];
+        copy_strided(X, gs + L.oX, (long long)ldx * tk, tid, NT);
+        copy_strided(Am, gs + L.oA, (long long)lda * ns, tid, NT);
+        copy_strided(tau, gs + L.oT, ns, tid, NT);
+        copy_strided(Z, gs + L.oZ, (long long)ldz * tin, tid, NT);
+        copy_strided(lam, gs + L.oL, tk, tid, NT);
         __syncthreads();
     } else {
         X = gs + L.oX; Am = gs + L.oA; tau = gs + L.oT; Z = gs + L.oZ; lam = gs + L.oL;
