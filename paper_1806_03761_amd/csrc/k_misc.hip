@@ -113,8 +113,20 @@ __global__ __launch_bounds__(NT) void k_ratio(const double* F, long long fs, con
     const int b = blockIdx.x;
     const double* Fb = F + (long long)b * fs;
     const double* Gb = G + (long long)b * gs;
+    // each thread's terms in ascending i, their loads issued 8 strides at a time
     double d = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) d += Fb[i] * Gb[i];
+    for (int i0 = 0; i0 < n; i0 += 8 * NT) {
+        double f[8], g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + threadIdx.x + u * NT;
+            f[u] = Fb[i < n ? i : 0];
+            g[u] = Gb[i < n ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + threadIdx.x + u * NT < n) d += f[u] * g[u];
+    }
     d = bsum(d, red);
     if (threadIdx.x == 0) {
         double r;
