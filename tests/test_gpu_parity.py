@@ -396,10 +396,32 @@ def test_fused_pair_step_matches_gemm_path():
     that consecutive MFMAs take consecutive k."""
     p = _peps()
     lat, A, S, _ = make_workload("8x8_D4_Dc16", 37)
+    _fused_forms_equal_plain(p, lat, A, S)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 2, 4), (5, 4, 3, 9), (3, 6, 4, 11)])
+def test_fused_steps_ragged_shapes(shape):
+    """The same bitwise agreement where legs (D = 2, 3) and boundary bonds (Dc = 9, 11)
+    are below the fused kernels' padded sizes, so bond chunks end part-full, on
+    non-square lattices."""
+    Lx, Ly, D, Dc = shape
+    lat = Lattice(Lx, Ly, D, Dc)
+    A, S = make_random(lat, 21, 5 + D)
+    _fused_forms_equal_plain(_peps(), lat, A, S)
+
+
+def _fused_forms_equal_plain(p, lat, A, S):
     Ad, Sd = _dev(A, S)
-    plain = _eval_env(p, Ad, Sd, lat, {"PEPS_FUSE": "0"})
-    for env in ({"PEPS_PAIR": "valu"}, {}):
-        fused = _eval_env(p, Ad, Sd, lat, env)
-        for name, x, y in zip(("log-amp", "sign", "E_loc", "grad", "flags"), fused, plain):
-            d = np.abs(np.asarray(x, np.float64) - np.asarray(y, np.float64))
-            assert np.array_equal(x, y), (env, name, int((d > 0).sum()), d.size, float(d.max()))
+    p.profile_enable(("fused",))   # counts fused-step launches, so a fallback cannot pass
+    try:
+        plain = _eval_env(p, Ad, Sd, lat, {"PEPS_FUSE": "0"})
+        assert p.profile_read("fused")[1] == 0
+        for env in ({"PEPS_PAIR": "valu"}, {}):
+            n0 = p.profile_read("fused")[1]
+            fused = _eval_env(p, Ad, Sd, lat, env)
+            assert p.profile_read("fused")[1] > n0, ("fused steps did not run", env)
+            for name, x, y in zip(("log-amp", "sign", "E_loc", "grad", "flags"), fused, plain):
+                d = np.abs(np.asarray(x, np.float64) - np.asarray(y, np.float64))
+                assert np.array_equal(x, y), (env, name, int((d > 0).sum()), d.size, float(d.max()))
+    finally:
+        p.profile_enable(())
