@@ -726,19 +726,31 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
     const double ptol = fmax(2.220446049250313e-16 * tnorm, 1e-300);
     for (int i = 0; i < n; ++i)
         x[i * xs] = (double)(hash_u32((unsigned)(l * 7919 + i * 104729 + 17)) & 0xffffff) / 16777216.0 - 0.5;
+    // (each recurrence carries its previous term in a register, so the LDS traffic of
+    // x and piv stays off the dependency chain)
     for (int it = 0; it < 3; ++it) {
         double q = d[0] - lam;
         if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-        piv[0] = 1.0 / q;
+        double pp = 1.0 / q;
+        piv[0] = pp;
         for (int i = 1; i < n; ++i) {
-            q = d[i] - lam - e2[i - 1] * piv[(i - 1) * xs];
+            q = d[i] - lam - e2[i - 1] * pp;
             if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-            piv[i * xs] = 1.0 / q;
+            pp = 1.0 / q;
+            piv[i * xs] = pp;
         }
         // L y = b (in place), then L^T x = D^-1 y; piv holds the reciprocal pivots
-        for (int i = 1; i < n; ++i) x[i * xs] -= (e[i - 1] * piv[(i - 1) * xs]) * x[(i - 1) * xs];
-        x[(n - 1) * xs] *= piv[(n - 1) * xs];
-        for (int i = n - 2; i >= 0; --i) x[i * xs] = (x[i * xs] - e[i] * x[(i + 1) * xs]) * piv[i * xs];
+        double y = x[0];
+        for (int i = 1; i < n; ++i) {
+            y = x[i * xs] - (e[i - 1] * piv[(i - 1) * xs]) * y;
+            x[i * xs] = y;
+        }
+        double xn = x[(n - 1) * xs] * piv[(n - 1) * xs];
+        x[(n - 1) * xs] = xn;
+        for (int i = n - 2; i >= 0; --i) {
+            xn = (x[i * xs] - e[i] * xn) * piv[i * xs];
+            x[i * xs] = xn;
+        }
         double mx = 0.0;
         for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i * xs]));
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
