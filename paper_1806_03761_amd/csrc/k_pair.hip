@@ -100,7 +100,9 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     const float* S2 = a.site2 + (long long)((a.sel2[(long long)b * a.sel_bs] ^ a.flip2) & 1) * 512 + (FWD ? 0 : 256);
 
     // ---- staging (float32, zero padded) ----
-    for (int e = tid; e < 1024; e += 256) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {   // constant trip count: all loads issued together
+        const int e = tid + 256 * it;
         int c, u, cp;
         if (FWD) { c = e >> 6; cp = (e >> 2) & 15; u = e & 3; }     // Ue[c][c'][u]
         else { u = e >> 8; cp = (e >> 4) & 15; c = e & 15; }        // Ue[u][c'][c]
@@ -110,7 +112,9 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
         else { lp = e >> 6; l = (e >> 2) & 15; q = e & 3; }         // Le[l'][l][q]
         Le[e] = (float)ld_or0(l < cl && q < Dq && lp < cl1, L, ((long long)l * Dq + q) * cl1 + lp);
     }
-    for (int e = tid; e < 4096; e += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + 256 * it;
         if (FWD) {   // Big[c][l][b][b'] = P[c][b][b'][l]
             const int c = e >> 8, l = (e >> 4) & 15, bb = (e >> 2) & 3, bp = e & 3;
             Big[e] = (float)ld_or0(c < cu && l < cl && bb < h && bp < h, X, (long long)c * h * h * cl + ((long long)bb * h + bp) * cl + l);
@@ -370,7 +374,9 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
     const double* U = a.U + (long long)b * a.us;
     const double* L = a.L + (long long)b * a.ls;
     const float* S = a.site + (long long)((a.sel[(long long)b * a.sel_bs] ^ a.flip) & 1) * 512 + (FWD ? 0 : 256);
-    for (int e = tid; e < 1024; e += 256) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {   // constant trip count: all loads issued together
+        const int e = tid + 256 * it;
         if (FWD) {
             {   // Xs[c][l][b] = P[c][b][l]
                 const int c = e >> 6, l = (e >> 2) & 15, bb = e & 3;
