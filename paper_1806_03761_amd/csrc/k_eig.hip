@@ -249,7 +249,8 @@ __device__ inline void gram_4x4(const double* Z, int ldz, double* Am, int lda, c
             oi[u] = bx(min(bi * 4 + u, ns - 1));
             oj[u] = bx(min(bj * 4 + u, ns - 1));
         }
-        for (int y = 0; y < ny; ++y) {
+#pragma unroll 4
+        for (int y = 0; y < ny; ++y) {   // unrolled: four rows' LDS reads in flight
             const double* zy = Z + by(y);
             double a4[4], b4[4];
 #pragma unroll
@@ -987,6 +988,7 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
             double acc = 0.0;
             for (int dd = 0; dd < p; ++dd) {
                 const double* zrow = Z + ar * p + dd;
+#pragma unroll 4
                 for (int t = 0; t < tin; ++t) acc += zrow[(long long)t * ldz] * vk[dd * tin + t];
             }
             Go[e2] = acc;
@@ -1011,6 +1013,7 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
                     const int dd = c / tin, t = c % tin;
                     const double* zt = Z + (long long)t * ldz + dd;
                     double acc = 0.0;
+#pragma unroll 4
                     for (int ar = 0; ar < mp; ++ar) acc += zt[ar * p] * uk[ar];
                     U[(long long)rr * np + c] = acc;
                     nr += acc * acc;
