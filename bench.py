@@ -59,8 +59,8 @@ def cpu_baseline(name: str, per_core: int = 8):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "fa3e2638a23ad39d",
-           "bytes_per_launch": {"svd": 524639350, "qr": 460547339, "gemm": 143312674, "fused": 102279435}}
+TRAFFIC = {"sources": "b5859ca08afe6fee",
+           "bytes_per_launch": {"svd": 524885095, "qr": 460562737, "gemm": 143312846, "fused": 102269001}}
 
 
 def _sources_hash() -> str:
