@@ -37,9 +37,10 @@ def _oracle_worker(args):
     return hi - lo
 
 
-def cpu_baseline(name: str, per_core: int = 8):
-    """Time the FP64 oracle (amplitude + local energy + log-derivatives, one sample per
-    process) on the host cores, over a bounded sample of the workload."""
+def cpu_baseline(name: str, per_core: int = 96):
+    """Time the FP64 oracle (amplitude + local energy + log-derivatives, one sample at a
+    time per process) on the host cores, over a bounded sample of the workload (96 per
+    process: about 15 s of wall time on 16 cores)."""
     import multiprocessing as mp
     cores = max(1, min(16, os.cpu_count() or 1))
     n = per_core * cores
