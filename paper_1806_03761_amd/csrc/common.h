@@ -86,8 +86,10 @@ __device__ inline void copy_strided(double* dst, const double* src, long long n,
 template <int CTRL>
 __device__ inline double dpp_perm(double x) {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    // every control used here gives each lane a valid source lane, so no "old" value is
+    // ever kept: the plain DPP move needs no copy of the destination first
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
