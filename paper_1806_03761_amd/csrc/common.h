@@ -93,27 +93,36 @@ __device__ inline double dpp_perm(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Lane l ^ 16 inside each group of 32 lanes (ds_swizzle in bit mode: and-mask 0x1F,
-// xor-mask 0x10), without the address round trip of ds_bpermute.
-__device__ inline double swz_xor16(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+// v plus the value of lane l ^ 16 (l ^ 32): v_permlane16_swap (32_swap) with both operands
+// v hands every lane its own row's (half's) value and the partner row's (half's) value at
+// the same position, a plain VALU exchange.  Their sum is the same in every lane of the
+// pair, and equal to v + v[l ^ 16] since the addition commutes.
+__device__ inline double add_xor16(double v) {
+    const long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) +
+           __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+__device__ inline double add_xor32(double v) {
+    const long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) +
+           __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
 }
 
 // Sum over aligned groups of `width` lanes (a power of two up to 64); every lane of a
 // group gets the bitwise-same total.  Inside a row of 16 lanes the partner values come
-// from DPP permutations (a few cycles each); between the two rows of a 32-lane group
-// from ds_swizzle, between the two halves of the wave from ds_bpermute.  All lanes of a
-// group must be active.
+// from DPP permutations, across rows and wave halves from the permlane swaps: all VALU,
+// no LDS round trip.  All lanes of a group must be active.
 __device__ inline double lane_group_sum(double v, int width) {
     if (width >= 2) v += dpp_perm<0xB1>(v);
     if (width >= 4) v += dpp_perm<0x4E>(v);
     if (width >= 8) v += dpp_perm<0x141>(v);
     if (width >= 16) v += dpp_perm<0x140>(v);
-    if (width >= 32) v += swz_xor16(v);
-    if (width >= 64) v += __shfl_xor(v, 32, 64);
+    if (width >= 32) v = add_xor16(v);
+    if (width >= 64) v = add_xor32(v);
     return v;
 }
 

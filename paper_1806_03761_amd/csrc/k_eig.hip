@@ -177,8 +177,8 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
             double pv = 0.0;
 #pragma unroll
             for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
-            pv += swz_xor16(pv);
-            pv += __shfl_xor(pv, 32, 64);
+            pv = add_xor16(pv);
+            pv = add_xor32(pv);
             if (lane == 0) s_red[wave] = pv;
             if (tj == 0)
 #pragma unroll
