@@ -747,20 +747,34 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
         scale = step_rescale(mx, a.lin, a.lout, b, red);
     }
     // chunk t, output row 16 w + 4 g + r, column li
+    if (FWD) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (FWD) {   // row (cc, a, a') = (w, g, r), column l' = li
+            for (int r = 0; r < 4; ++r) {   // row (cc, a, a') = (w, g, r), column l' = li
                 const int cp = 4 * t + w;
                 if (t < nch && cp < cu1 && g < h1 && r < h1 && li < cl1)
                     Y[(((long long)cp * h1 + g) * h1 + r) * cl1 + li] = (double)out[t][r] * scale;
-            } else {     // row (b, b', ll) = (w, g, r), column c = li
-                const int l = 4 * t + r;
-                if (t < nch && w < h && g < h && l < cl && li < cu)
-                    Y[(long long)li * h * h * cl + ((long long)w * h + g) * cl + l] = (double)out[t][r] * scale;
             }
+    } else {
+        // row (b, b', l) = (w, g, 4t + r), column c = li: the lane index would be the slowest
+        // output index, so the block goes through LDS (padded [c][b][b'][l], c stride 257
+        // doubles: the 16 lanes of a store hit distinct banks) and leaves in output order
+        __syncthreads();   // every wave is done with the tiles
+        double* Ys = reinterpret_cast<double*>(sm);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (t < nch) Ys[li * 257 + (w * 4 + g) * 16 + 4 * t + r] = (double)out[t][r] * scale;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = tid + 256 * it, c = e >> 8, bb = (e >> 6) & 3, bp = (e >> 4) & 3, l = e & 15;
+            if (c < cu && bb < h && bp < h && l < cl)
+                Y[(((long long)c * h + bb) * h + bp) * cl + l] = Ys[c * 257 + (bb * 4 + bp) * 16 + l];
         }
+    }
 }
 
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st) {
