@@ -487,10 +487,18 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
             for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[y]));
             scale = step_rescale(mx, a.lin, a.lout, b, red);
         }
-        if (c2 < cu1 && aa < h1)
+        // through LDS (padded [c'][a][l'] in the incoming-partial and environment tiles,
+        // free now) so the global stores go out in output order
+        __syncthreads();
+        double* Ys = reinterpret_cast<double*>(sm);
 #pragma unroll
-            for (int y = 0; y < kPD; ++y)
-                if (lg * kPD + y < cl1) Y[((long long)c2 * h1 + aa) * cl1 + lg * kPD + y] = (double)acc[y] * scale;
+        for (int y = 0; y < kPD; ++y) Ys[(c2 * kPD + aa) * kPX + lg * kPD + y] = (double)acc[y] * scale;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int e = tid + 256 * it, c = e >> 6, x = (e >> 4) & 3, lp = e & 15;
+            if (c < cu1 && x < h1 && lp < cl1) Y[((long long)c * h1 + x) * cl1 + lp] = Ys[e];
+        }
     } else {
         // thread (l, b, c group): Qout[c][b][l] = sum_{u,c'} U[c][u][c'] T2[b][u][l][c']
         const int l2 = tid >> 4, bb = (tid >> 2) & 3, cg = tid & 3;
@@ -511,10 +519,17 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
             for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[y]));
             scale = step_rescale(mx, a.lin, a.lout, b, red);
         }
-        if (bb < h && l2 < cl)
+        // through LDS (padded [c][b][l]) so the global stores go out in output order
+        __syncthreads();
+        double* Ys = reinterpret_cast<double*>(sm);
 #pragma unroll
-            for (int y = 0; y < kPD; ++y)
-                if (cg * kPD + y < cu) Y[((long long)(cg * kPD + y) * h + bb) * cl + l2] = (double)acc[y] * scale;
+        for (int y = 0; y < kPD; ++y) Ys[((cg * kPD + y) * kPD + bb) * kPX + l2] = (double)acc[y] * scale;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int e = tid + 256 * it, c = e >> 6, x = (e >> 4) & 3, l = e & 15;
+            if (c < cu && x < h && l < cl) Y[((long long)c * h + x) * cl + l] = Ys[e];
+        }
     }
 }
 
