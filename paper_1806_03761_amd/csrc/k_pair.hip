@@ -569,7 +569,11 @@ hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
 // stores and the 16-byte operand reads hit 16 distinct bank quads per 16 lanes.
 // ---------------------------------------------------------------------------
 typedef float mfma4_t __attribute__((ext_vector_type(4)));
-static constexpr int kPairMfmaLds = 4 * 1024 + 2 * 4096;   // floats: per-wave T1/T2 tile; T3 x 2
+// LDS (floats): per-wave T1/T2 tiles, then T3 -- single-buffered forward (32 KB: four
+// workgroups per CU at the 128 registers the forward form fits in), double-buffered
+// backward (48 KB, one barrier per chunk; it also holds the staged output block)
+template <bool FWD>
+constexpr int pair_mfma_lds() { return 4 * 1024 + (FWD ? 1 : 2) * 4096; }
 
 __device__ __forceinline__ mfma4_t mfma_k16(const float4& av, const float4& bv, mfma4_t acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
@@ -602,7 +606,7 @@ __device__ __forceinline__ float4 site_b(const float* row, int g) {
 }
 
 template <bool FWD>
-__global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
+__global__ __launch_bounds__(256, FWD ? 4 : 3) void k_pair_mfma(PairArgs a) {
     extern __shared__ __align__(16) float sm[];
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
     const int nch = ((FWD ? cu1 : cl) + 3) >> 2;
     const int rread = 16 * (li & 3) + (li >> 2);   // operand row of a 16-wide temporary, tile 0
     for (int ch = 0; ch < nch; ++ch) {
-        float* T3 = sm + 4096 + 4096 * (ch & 1);   // third temporary, 64 rows x 64, shared
+        float* T3 = sm + 4096 + (FWD ? 0 : 4096 * (ch & 1));   // third temporary, 64 x 64, shared
         const float4 ubc = ch == 0 ? ub[0] : ch == 1 ? ub[1] : ch == 2 ? ub[2] : ub[3];
         wave_lds_sync();   // the previous chunk's reads of T12 are done
         // first contraction.  FWD: T1[(b',l,cc)][(b,u)] = sum_c P[c][b][b'][l] U[c][u][c'],
@@ -729,6 +733,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
             st4(T12 + t12_at(16 * t + 4 * g + (li >> 2), li & 3), acc);
         }
         wave_lds_sync();
+        if (FWD) __syncthreads();   // single buffer: the previous chunk's reads of T3 are done
         // third contraction, tile t (FWD: cc = t, BWD: ll = t).
         // FWD: T3[(cc,a,a')][(l,q)] = sum_{(b',m)} T2 S2[b'][m][a'][q]; result row (l, a) = (4w + r, g).
         // BWD: T3[(b,b',l)][(u,c')] = sum_{(a,m)} T2 S1[b][u][a][m]; result row (c', b') = (4r + w, g).
@@ -739,7 +744,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairArgs a) {
             if (FWD) st4(T3 + t3_at(16 * t + 4 * g + (li >> 2), w, li & 3), acc);
             else st4(T3 + t3_at(16 * (li >> 2) + 4 * g + t, li & 3, w), acc);
         }
-        // T3 complete; its other buffer was last read before every wave passed the
+        // T3 complete; backward, its other buffer was last read before every wave passed the
         // previous chunk's barrier, so the next chunk may refill it
         __syncthreads();
         // last contraction, rows 16 w .. 16 w + 15 of T3, k blocks in order.
@@ -796,7 +801,7 @@ hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (!pair_step_fits(a)) return hipErrorInvalidValue;
     if (a.mfma) {
-        const size_t mb = kPairMfmaLds * sizeof(float);
+        const size_t mb = (fwd ? pair_mfma_lds<true>() : pair_mfma_lds<false>()) * sizeof(float);
         if (mb + 64 > get_lds_cap()) return hipErrorInvalidValue;
         if (fwd) hipLaunchKernelGGL(k_pair_mfma<true>, dim3(a.batch), dim3(256), mb, st, a);
         else hipLaunchKernelGGL(k_pair_mfma<false>, dim3(a.batch), dim3(256), mb, st, a);
