@@ -627,8 +627,9 @@ __device__ inline unsigned hash_u32(unsigned x) {
 }
 
 // 1/q by the hardware reciprocal estimate refined with one Newton-Raphson step
-// (r <- r + r (1 - q r)), which roughly doubles the estimate's correct bits.  Used only
-// in the Sturm recurrence, whose sign count is backward stable to such rounding.
+// (r <- r + r (1 - q r)), which roughly doubles the estimate's correct bits.  Used in the
+// Sturm recurrence, whose sign count is backward stable to such rounding, and for the
+// pivots of inverse iteration (bounded away from zero there), which corrects itself.
 __device__ inline double sturm_rcp(double q) {
     const double r = __builtin_amdgcn_rcp(q);
     return fma(fma(-q, r, 1.0), r, r);
@@ -727,41 +728,41 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
     const double ptol = fmax(2.220446049250313e-16 * tnorm, 1e-300);
     for (int i = 0; i < n; ++i)
         x[i * xs] = (double)(hash_u32((unsigned)(l * 7919 + i * 104729 + 17)) & 0xffffff) / 16777216.0 - 0.5;
-    // (each recurrence carries its previous term in a register, so the LDS traffic of
-    // x and piv stays off the dependency chain)
+    // Per sweep: one pass factors and solves L y = b together (both run upwards), one
+    // solves L^T x = D^-1 y and finds max |x_i|, one forms the norm of x / max, one scales.
+    // Each recurrence carries its previous term in a register (LDS stays off the
+    // dependency chain); the reciprocal pivots come from the hardware estimate plus one
+    // Newton step, the pivots being bounded away from zero by ptol.
     for (int it = 0; it < 3; ++it) {
         double q = d[0] - lam;
         if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-        double pp = 1.0 / q;
+        double pp = sturm_rcp(q);
         piv[0] = pp;
-        for (int i = 1; i < n; ++i) {
-            q = d[i] - lam - e2[i - 1] * pp;
-            if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
-            pp = 1.0 / q;
-            piv[i * xs] = pp;
-        }
-        // L y = b (in place), then L^T x = D^-1 y; piv holds the reciprocal pivots
         double y = x[0];
         for (int i = 1; i < n; ++i) {
-            y = x[i * xs] - (e[i - 1] * piv[(i - 1) * xs]) * y;
+            y = x[i * xs] - (e[i - 1] * pp) * y;   // pp = 1 / pivot i-1
             x[i * xs] = y;
+            q = d[i] - lam - e2[i - 1] * pp;
+            if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
+            pp = sturm_rcp(q);
+            piv[i * xs] = pp;
         }
-        double xn = x[(n - 1) * xs] * piv[(n - 1) * xs];
+        double xn = x[(n - 1) * xs] * pp;
         x[(n - 1) * xs] = xn;
+        double mx = fabs(xn);
         for (int i = n - 2; i >= 0; --i) {
             xn = (x[i * xs] - e[i] * xn) * piv[i * xs];
             x[i * xs] = xn;
+            mx = fmax(mx, fabs(xn));
         }
-        double mx = 0.0;
-        for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i * xs]));
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
         double nrm = 0.0;
         for (int i = 0; i < n; ++i) {
-            x[i * xs] *= inv;
-            nrm += x[i * xs] * x[i * xs];
+            const double t = x[i * xs] * inv;
+            nrm += t * t;
         }
         const double sn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
-        for (int i = 0; i < n; ++i) x[i * xs] *= sn;
+        for (int i = 0; i < n; ++i) x[i * xs] = (x[i * xs] * inv) * sn;
     }
     // eigenvalue from the Rayleigh quotient of the converged unit vector
     double rq = d[0] * x[0] * x[0];
