@@ -8,7 +8,10 @@ What it computes, per spin configuration S (paper Sec. II-A):
   * W(S), the single-layer contraction of Eq. (1) at fixed S, approximated by
     the row-by-row boundary-MPS contraction with bond truncation Dc of Fig. 1(c);
   * the local energy E(S) of Eq. (4) for the J1-J2 Hamiltonian of Sec. III-A;
-  * the log-derivatives Delta = B/W of Eqs. (6)-(7).
+  * the log-derivatives Delta = B/W of Eqs. (6)-(7);
+  * one Metropolis step of the sampling loop of Sec. II-B (steps 1-3): a symmetric
+    exchange proposal on a J1 or J2 bond, W(S') by the same contraction, acceptance
+    for the weights W(S)^2 of Eq. (3), with the uniform random numbers passed in.
 Everything is IEEE float64.  numpy's QR and SVD (LAPACK) are used as library
 steps; contractions are written as einsum calls, one per tensor pair.
 
@@ -27,7 +30,11 @@ Readings of points the paper leaves open (each one is listed in the design notes
     same sandwich at the unflipped S;
   * Delta_m is the frozen-environment derivative of ln|W_i| (row i holds site m);
   * s = 0 is spin up (S^z = +1/2), sigma = 1 - 2s; S_i.S_j = sigma_i sigma_j / 4
-    plus 1/2 for the exchange of an anti-parallel pair (no sign rotation).
+    plus 1/2 for the exchange of an anti-parallel pair (no sign rotation);
+  * the Metropolis proposal (the paper names none): exchange the spins of a bond drawn
+    uniformly from every J1 and J2 bond (it conserves S^z and undoes itself); a bond of
+    equal spins is no move; W(S') comes from a full contraction of S', as in the
+    paper's step 2.
 
 Parity pins live in the test suite: dense transfer-matrix contraction (exact
 regime), dense sequential Schmidt projection (truncated regime), brute force
@@ -406,3 +413,47 @@ def full_path_one(A, lat, S):
     e = local_energy_one(A, lat, S, envs)
     d = log_derivative_one(A, lat, S, envs).reshape(lat.N, 2, -1)
     return la, sg, e, d, fl
+
+
+# --------------------------------------------------------------------------
+# Metropolis sampling (Sec. II-B, steps 1-3 of the sampling loop; weights W(S)^2 of
+# the energy estimator, Eq. (3))
+# --------------------------------------------------------------------------
+def proposal_bonds(lat):
+    """The exchange moves a Metropolis step draws from, in a fixed order: horizontal
+    pairs (i,j)-(i,j+1) row by row, then vertical (i,j)-(i+1,j), then the diagonals
+    (i,j)-(i+1,j+1), then the anti-diagonals (i,j+1)-(i+1,j): every J1 and J2 bond once."""
+    Lx, Ly = lat.Lx, lat.Ly
+    out = [(i * Lx + j, i * Lx + j + 1) for i in range(Ly) for j in range(Lx - 1)]
+    out += [(i * Lx + j, (i + 1) * Lx + j) for i in range(Ly - 1) for j in range(Lx)]
+    out += [(i * Lx + j, (i + 1) * Lx + j + 1) for i in range(Ly - 1) for j in range(Lx - 1)]
+    out += [(i * Lx + j + 1, (i + 1) * Lx + j) for i in range(Ly - 1) for j in range(Lx - 1)]
+    return out
+
+
+def metropolis_step(A, lat, S, u, log_abs, sign):
+    """One Metropolis step of every chain.  Chain b proposes the exchange of the two
+    spins of bond k = min(floor(u[b,0] nb), nb - 1) of proposal_bonds (a symmetric
+    proposal: the same bond undoes it; a pair of equal spins is no move), contracts
+    W(S') like log_amplitude, and moves to S' when u[b,1] < W(S')^2 / W(S)^2 (the
+    Metropolis rule for weights W^2) and S' has flag 0.
+    log_abs, sign: ln|W(S)| and sign of the current configurations.
+    Returns (S, log_abs, sign, accepted), new arrays."""
+    bonds = proposal_bonds(lat)
+    nb = len(bonds)
+    S = np.array(S, dtype=np.int8, copy=True)
+    la = np.array(log_abs, dtype=np.float64, copy=True)
+    sg = np.array(sign, dtype=np.int8, copy=True)
+    acc = np.zeros(S.shape[0], dtype=np.int8)
+    for b in range(S.shape[0]):
+        m, n = bonds[min(int(u[b, 0] * nb), nb - 1)]
+        if S[b, m] == S[b, n]:
+            continue
+        Sp = S[b].copy()
+        Sp[m], Sp[n] = S[b, n], S[b, m]
+        lap, sgp, flp = log_amplitude_one(A, lat, Sp)
+        if flp != FLAG_OK:
+            continue
+        if u[b, 1] < math.exp(min(2.0 * (lap - la[b]), 700.0)):
+            S[b], la[b], sg[b], acc[b] = Sp, lap, sgp, 1
+    return S, la, sg, acc

@@ -349,3 +349,88 @@ def test_envs_agree_in_exact_regime():
     for i in range(lat.Ly):
         s, l = O.row_sandwich(U[i], O.row_tensors(A, lat, S[0], i), L[i])
         assert s == sg and _rel(l + logU[i] + logL[i], la) < 1e-12
+
+
+# --- Metropolis sampling (Sec. II-B, steps 1-3 of the sampling loop) -----------------
+def _sz0_configs(N):
+    S = P.configs_from_index(N)
+    return S[S.sum(1) == N // 2]
+
+
+def _amp_index(S):
+    N = S.shape[-1]
+    return (S.astype(np.int64) << (N - 1 - np.arange(N))).sum(-1)
+
+
+def test_metropolis_proposal_bonds_cover_j1_j2():
+    """The proposal list holds every J1 and J2 pair exactly once, grouped horizontal,
+    vertical, diagonal, anti-diagonal."""
+    for Lx, Ly in [(4, 2), (3, 5), (4, 4)]:
+        lat = Lattice(Lx, Ly, 2, 4)
+        bonds = O.proposal_bonds(lat)
+        nn, nnn = P.lattice_bonds(Lx, Ly)
+        assert sorted(bonds) == sorted(nn + nnn) and len(set(bonds)) == len(bonds)
+        kinds = []
+        for m, n in bonds:
+            dr = n // Lx - m // Lx
+            dc = n % Lx - m % Lx
+            kinds.append({(0, 1): 0, (1, 0): 1, (1, 1): 2, (1, -1): 3}[(dr, dc)])
+        assert kinds == sorted(kinds)
+
+
+def test_metropolis_decisions_against_exact_weights():
+    """Exact regime (4x2, D=2, Dc=4): for every proposal bond, the step exchanges the pair
+    exactly when u1 < W(S')^2 / W(S)^2 with W from the dense contraction, and carries
+    ln|W(S')| and its sign."""
+    lat = Lattice(4, 2, 2, 4)
+    A, _ = make_random(lat, 0, 41)
+    psi = P.full_wavefunction(A, lat)
+    bonds = O.proposal_bonds(lat)
+    nb = len(bonds)
+    rng = np.random.default_rng(5)
+    for S0 in _sz0_configs(lat.N)[rng.choice(70, 6, replace=False)]:
+        w = psi[_amp_index(S0)]
+        la0, sg0 = np.array([math.log(abs(w))]), np.array([int(np.sign(w))], np.int8)
+        for k, (m, n) in enumerate(bonds):
+            Sp = S0.copy()
+            Sp[m], Sp[n] = S0[n], S0[m]
+            t = (psi[_amp_index(Sp)] / w) ** 2
+            for frac in (0.5, 0.999, 1.001, 2.0):
+                u1 = min(frac * t, 0.999999)
+                u = np.array([[(k + 0.5) / nb, u1]])
+                S1, la1, sg1, acc = O.metropolis_step(A, lat, S0[None], u, la0, sg0)
+                want = S0[m] != S0[n] and u1 < t
+                assert bool(acc[0]) == want, (k, frac, t)
+                if want:
+                    assert np.array_equal(S1[0], Sp)
+                    assert abs(la1[0] - math.log(abs(psi[_amp_index(Sp)]))) < 1e-12
+                    assert sg1[0] == np.sign(psi[_amp_index(Sp)])
+                else:
+                    assert np.array_equal(S1[0], S0) and la1[0] == la0[0]
+
+
+def test_metropolis_rule_keeps_w2_stationary():
+    """The transition matrix of the step (uniform bond, exchange accepted with
+    probability min(1, W(S')^2/W(S)^2)) leaves pi(S) = W(S)^2 / Z invariant on the S^z = 0
+    sector of a 4x2 lattice, and does not leave |W| / Z' invariant."""
+    lat = Lattice(4, 2, 2, 4)
+    A, _ = make_random(lat, 0, 43)
+    psi = P.full_wavefunction(A, lat)
+    cfg = _sz0_configs(lat.N)
+    idx = {int(i): r for r, i in enumerate(_amp_index(cfg))}
+    w = psi[_amp_index(cfg)]
+    bonds = O.proposal_bonds(lat)
+    T = np.zeros((len(cfg), len(cfg)))
+    for r, S0 in enumerate(cfg):
+        for m, n in bonds:
+            if S0[m] == S0[n]:
+                continue
+            Sp = S0.copy()
+            Sp[m], Sp[n] = S0[n], S0[m]
+            c = idx[int(_amp_index(Sp))]
+            T[r, c] += min(1.0, (w[c] / w[r]) ** 2) / len(bonds)
+        T[r, r] = 1.0 - T[r].sum()
+    pi = w ** 2 / (w ** 2).sum()
+    assert np.abs(pi @ T - pi).max() < 1e-14
+    pa = np.abs(w) / np.abs(w).sum()
+    assert np.abs(pa @ T - pa).max() > 1e-4
