@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-mcmc", action="store_true", help="skip the Metropolis sampling leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (3 times): the reference "
@@ -189,6 +190,25 @@ def main():
                        "traffic": traffic, "avg_launch_us": timed["avg_us"],
                        "launches": timed["launches"]}
     res["kernels_warmup"] = kern
+    if not args.no_mcmc:
+        # Metropolis sampling on the same 4096 chains: one step = proposal, contraction of
+        # W(S') (amplitude only) and the accept/reject of every chain
+        Sm = Sd.clone()
+        la_m, sg_m, _ = peps.log_amplitude(Ad, Sm, lat, args.prec)
+        g = torch.Generator(device=dev)
+        g.manual_seed(7)
+        U = torch.rand((args.steps + 1, B, 2), dtype=torch.float64, device=dev, generator=g)
+        peps.metropolis_step(Ad, Sm, lat, U[0], la_m, sg_m, args.prec)
+        acc = torch.zeros(B, dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            acc += peps.metropolis_step(Ad, Sm, lat, U[k + 1], la_m, sg_m, args.prec)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        res["mcmc"] = {"value": B * args.steps / dtm, "unit": "chain-steps/s",
+                       "ms_per_step": dtm * 1e3 / args.steps, "chains": B,
+                       "acceptance": acc.sum().item() / (B * args.steps)}
     if not args.no_plain:
         # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
         nplain = 8

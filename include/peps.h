@@ -123,6 +123,26 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           const double* weights, double* log_abs, int8_t* sign,
                           double* e_loc, double* out, int8_t* flags);
 
+/* One Metropolis step of every chain: the sampling loop of Sec. II-B (steps 1-3: a
+ * proposed configuration, its weight by contraction, accept or reject) for weights
+ * W(S)^2, the importance sampling of the energy estimator Eq. (3).
+ * Chain b draws bond k = min(floor(u[b][0] * nb), nb - 1) of the nb J1 and J2 bonds,
+ * ordered: horizontal (i,j)-(i,j+1) row by row, vertical (i,j)-(i+1,j), diagonal
+ * (i,j)-(i+1,j+1), anti-diagonal (i,j+1)-(i+1,j).  If its two spins differ, S' is S with
+ * them exchanged (S^z is kept; the same bond undoes it), ln|W(S')| is contracted as in
+ * peps_log_amplitude, and S' replaces S when it has flag 0 and
+ * u[b][1] < exp(2 (ln|W(S')| - log_abs[b])).
+ * S: device int8 [batch][Ly*Lx], the chains, updated in place.
+ * log_abs, sign: device [batch], ln|W(S)| and sign of the chains on entry (as from
+ *   peps_log_amplitude), updated with the moves.
+ * u: device float64 [batch][2], uniform in [0, 1), drawn by the caller.
+ * accepted: device int8 [batch] or NULL; 1 where the chain moved, else 0.
+ * Work is enqueued on the context's stream; the context keeps a proposal buffer of
+ * about batch * (N + 11) bytes between calls. */
+peps_status peps_metropolis_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                                 const double* A, int8_t* S, int64_t batch, const double* u,
+                                 double* log_abs, int8_t* sign, int8_t* accepted);
+
 /* One job of a heterogeneous batch (peps_eval_jobs): a lattice with its own tensors,
  * configurations and outputs, with the meanings of peps_evaluate.  A NULL e_loc skips
  * the local energy (unless grad_mode is 3). */

@@ -402,6 +402,75 @@ hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batc
     return hipGetLastError();
 }
 
+// Metropolis step (Sec. II-B, steps 1-3 of the sampling loop), per sample (one thread):
+// bond k = min(floor(u0 nb), nb - 1) of the J1 and J2 bonds in the order horizontal,
+// vertical, diagonal (i,j)-(i+1,j+1), anti-diagonal (i,j+1)-(i+1,j).
+__device__ inline void mc_bond(int k, int Lx, int Ly, int* m, int* n) {
+    const int nh = Ly * (Lx - 1), nv = (Ly - 1) * Lx, nd = (Ly - 1) * (Lx - 1);
+    if (k < nh) {
+        const int i = k / (Lx - 1), j = k % (Lx - 1);
+        *m = i * Lx + j; *n = *m + 1;
+    } else if (k < nh + nv) {
+        k -= nh;
+        *m = k; *n = k + Lx;
+    } else if (k < nh + nv + nd) {
+        k -= nh + nv;
+        const int i = k / (Lx - 1), j = k % (Lx - 1);
+        *m = i * Lx + j; *n = (i + 1) * Lx + j + 1;
+    } else {
+        k -= nh + nv + nd;
+        const int i = k / (Lx - 1), j = k % (Lx - 1);
+        *m = i * Lx + j + 1; *n = (i + 1) * Lx + j;
+    }
+}
+
+// proposal S' = S with the spins of the drawn bond exchanged; moved = they differ
+__global__ void k_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
+                             int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const int N = Lx * Ly, nb = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
+    const int8_t* s = S + (long long)b * N;
+    int8_t* sp = Sp + (long long)b * N;
+    for (int i = 0; i < N; ++i) sp[i] = s[i];
+    const double kf = floor(u[2LL * b] * nb);
+    const int k = kf < (double)(nb - 1) ? (int)kf : nb - 1;
+    int m, n;
+    mc_bond(k, Lx, Ly, &m, &n);
+    moved[b] = s[m] != s[n];
+    sp[m] = s[n];
+    sp[n] = s[m];
+}
+hipError_t launch_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
+                             int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mc_propose, dim3((batch + 127) / 128), dim3(128), 0, st, S, Sp, moved, u, Lx, Ly, batch);
+    return hipGetLastError();
+}
+
+// accept when u1 < W(S')^2 / W(S)^2 = exp(2 (ln|W(S')| - ln|W(S)|)) and S' has flag 0
+__global__ void k_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+                            const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
+                            int8_t* sign, int8_t* accepted, int N, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const bool acc = moved[b] && flp[b] == 0 && u[2LL * b + 1] < exp(2.0 * (lap[b] - log_abs[b]));
+    if (acc) {
+        for (int i = 0; i < N; ++i) S[(long long)b * N + i] = Sp[(long long)b * N + i];
+        log_abs[b] = lap[b];
+        sign[b] = sgp[b];
+    }
+    if (accepted) accepted[b] = acc ? 1 : 0;
+}
+hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+                            const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
+                            int8_t* sign, int8_t* accepted, int N, int batch, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mc_accept, dim3((batch + 127) / 128), dim3(128), 0, st, S, Sp, moved, u, lap, sgp,
+                       flp, log_abs, sign, accepted, N, batch);
+    return hipGetLastError();
+}
+
 // Eq. (5): dE/dA = 2 <Delta E> - 2 <Delta><E> with <.> the mean over flag-0 samples.
 __global__ void k_energy_grad_combine(const double* G1, const double* G0, const double* acc,
                                       long long n, double* out) {

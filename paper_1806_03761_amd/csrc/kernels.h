@@ -123,6 +123,12 @@ int grad_parts(int batch);
 hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4, const int8_t* flags,
                               const double* w, int accumulate, double* out1, double* out0, double* ws,
                               int batch, hipStream_t st);
+// Metropolis step (see k_misc.hip): proposal and acceptance kernels, one thread per sample
+hipError_t launch_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
+                             int batch, hipStream_t st);
+hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+                            const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
+                            int8_t* sign, int8_t* accepted, int N, int batch, hipStream_t st);
 hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate, hipStream_t st);
 hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,

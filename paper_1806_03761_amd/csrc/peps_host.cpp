@@ -49,6 +49,8 @@ struct peps_ctx {
     size_t ws_bytes = 0;
     size_t ws_limit = 0;
     double* ones = nullptr;   // 4096 ones
+    char* mc = nullptr;       // Metropolis proposals (peps_metropolis_step)
+    size_t mc_bytes = 0;
     std::string err;
 };
 
@@ -953,6 +955,7 @@ peps_status peps_destroy(peps_ctx* c) {
     for (auto e2 : c->job_events) hipEventDestroy(e2);
     if (c->ws) hipFree(c->ws);
     if (c->ones) hipFree(c->ones);
+    if (c->mc) hipFree(c->mc);
     for (auto& r : c->prof) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -1337,6 +1340,52 @@ peps_status peps_log_derivative(peps_ctx* c, const peps_lattice* lat, peps_preci
     if (!out) return fail(c, PEPS_ERR_INVALID_ARG, "out is NULL");
     return run_all(c, lat, prec, A, S, batch, false, weights ? 2 : 1, weights, log_abs, sign, nullptr,
                    out, flags);
+}
+
+peps_status peps_metropolis_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
+                                 const double* A, int8_t* S, int64_t batch, const double* u,
+                                 double* log_abs, int8_t* sign, int8_t* accepted) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!lat) return fail(c, PEPS_ERR_INVALID_ARG, "lattice is NULL");
+    peps_status st = check_lat(c, lat);
+    if (st != PEPS_OK) return st;
+    if (batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
+    if (batch == 0) return PEPS_OK;
+    if (batch > (1LL << 30)) return fail(c, PEPS_ERR_INVALID_ARG, "batch too large");
+    if (!A || !S || !u || !log_abs || !sign) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
+    const int N = lat->Lx * lat->Ly;
+    // proposals S' [batch][N], ln|W(S')| [batch], sign, flag, moved [batch]
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t oSp = 0, oLa = up((size_t)batch * N), oSg = oLa + up((size_t)batch * 8);
+    const size_t oFl = oSg + up((size_t)batch), oMv = oFl + up((size_t)batch), need = oMv + up((size_t)batch);
+    if (need > c->mc_bytes) {
+        if (c->mc) {
+            if (c->stream) hipStreamSynchronize(c->stream);
+            else hipDeviceSynchronize();
+            hipFree(c->mc);
+            c->mc = nullptr;
+            c->mc_bytes = 0;
+        }
+        if (hipMalloc(&c->mc, need) != hipSuccess) {
+            c->mc = nullptr;
+            return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", need);
+        }
+        c->mc_bytes = need;
+    }
+    int8_t* Sp = reinterpret_cast<int8_t*>(c->mc + oSp);
+    double* lap = reinterpret_cast<double*>(c->mc + oLa);
+    int8_t* sgp = reinterpret_cast<int8_t*>(c->mc + oSg);
+    int8_t* flp = reinterpret_cast<int8_t*>(c->mc + oFl);
+    int8_t* moved = reinterpret_cast<int8_t*>(c->mc + oMv);
+    hipError_t e = launch_mc_propose(S, Sp, moved, u, lat->Lx, lat->Ly, (int)batch, c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    st = run_all(c, lat, prec, A, Sp, batch, false, 0, nullptr, lap, sgp, nullptr, nullptr, flp);
+    if (st != PEPS_OK) return st;
+    e = launch_mc_accept(S, Sp, moved, u, lap, sgp, flp, log_abs, sign, accepted, N, (int)batch, c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    return PEPS_OK;
 }
 
 peps_status peps_evaluate(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,

@@ -66,6 +66,8 @@ _SIGS = {
     "peps_tune_load": [_P, ctypes.c_char_p],
     "peps_evaluate": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                       ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+    "peps_metropolis_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                             _P, _P, _P, _P],
 }
 
 
@@ -272,6 +274,25 @@ def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out
                            _ptr(weights), _ptr(la), _ptr(sg), _ptr(e), _ptr(out), _ptr(fl))
     _check(lib, ctx, st, "peps_evaluate")
     return la, sg, e, out, fl
+
+
+def metropolis_step(A, S, lat, u, log_abs, sign, prec: str = "f64", accepted=None):
+    """One Metropolis step of every chain (peps_metropolis_step): S, log_abs and sign are
+    updated in place; u is float64 [batch][2] of uniforms on the device.  Returns the int8
+    accepted flags."""
+    lib, ctx, A, S2 = _prep(A, S, lat)
+    if S2.data_ptr() != S.data_ptr():
+        raise PepsError("S must be contiguous: it is updated in place")
+    B = S.shape[0]
+    for t, dt, shape in ((u, torch.float64, (B, 2)), (log_abs, torch.float64, (B,)), (sign, torch.int8, (B,))):
+        if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous() or t.device != S.device:
+            raise PepsError(f"expected a contiguous {dt} tensor of shape {shape} on {S.device}")
+    if accepted is None:
+        accepted = torch.empty(B, dtype=torch.int8, device=A.device)
+    st = lib.peps_metropolis_step(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, _ptr(u),
+                                  _ptr(log_abs), _ptr(sign), _ptr(accepted))
+    _check(lib, ctx, st, "peps_metropolis_step")
+    return accepted
 
 
 def job_outputs(A, S, lat, grad_mode=3, want_eloc=True):
