@@ -11,7 +11,10 @@ What it computes, per spin configuration S (paper Sec. II-A):
   * the log-derivatives Delta = B/W of Eqs. (6)-(7);
   * one Metropolis step of the sampling loop of Sec. II-B (steps 1-3): a symmetric
     exchange proposal on a J1 or J2 bond, W(S') by the same contraction, acceptance
-    for the weights W(S)^2 of Eq. (3), with the uniform random numbers passed in.
+    for the weights W(S)^2 of Eq. (3), with the uniform random numbers passed in;
+  * the sampled energy (Eq. (3)) and gradient (Eq. (5)), the gradient-optimisation
+    update of the tensors, and one iteration of the optimisation loop (Sec. II-B,
+    Step B: sample, estimate, update), with the random step factors passed in.
 Everything is IEEE float64.  numpy's QR and SVD (LAPACK) are used as library
 steps; contractions are written as einsum calls, one per tensor pair.
 
@@ -457,3 +460,54 @@ def metropolis_step(A, lat, S, u, log_abs, sign):
         if u[b, 1] < math.exp(min(2.0 * (lap - la[b]), 700.0)):
             S[b], la[b], sg[b], acc[b] = Sp, lap, sgp, 1
     return S, la, sg, acc
+
+
+# --------------------------------------------------------------------------
+# Monte Carlo estimators and the gradient-optimisation step (Sec. II-A: the sampled
+# energy of Eq. (3), its gradient Eq. (5), the GO update of the tensors; Sec. II-B:
+# one iteration of the GO main loop, Step B)
+# --------------------------------------------------------------------------
+def energy_gradient(A, lat, S, weights=None):
+    """Monte Carlo energy and energy gradient over the samples with flag 0.
+    <x> is the sample mean (weights None: every sample counts once; else the weighted
+    mean sum_b w_b x_b / sum_b w_b).  E = <E(S)> (the sampled form of Eq. (3)) and
+    dE/dA = 2 <Delta E> - 2 <Delta> <E> (Eq. (5)).
+    Returns (E, count, grad [N][2][D^4], e_loc, flags)."""
+    _, _, e, fl = local_energy(A, lat, S)
+    ok = fl == FLAG_OK
+    w = np.ones(S.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64)
+    w = np.where(ok, w, 0.0)
+    tot = w.sum()
+    count = int(ok.sum())
+    if count == 0 or tot == 0.0:
+        return math.nan, count, np.zeros((lat.N, 2, lat.D ** 4)), e, fl
+    Em = float((w[ok] * e[ok]).sum() / tot)
+    dE = np.zeros((lat.N, 2, lat.D ** 4))
+    dm = np.zeros_like(dE)
+    for b in np.nonzero(ok)[0]:
+        d = log_derivative_one(A, lat, S[b]).reshape(lat.N, 2, -1)
+        dE += (w[b] / tot) * e[b] * d
+        dm += (w[b] / tot) * d
+    return Em, count, 2.0 * dE - 2.0 * dm * Em, e, fl
+
+
+def go_update(A, grad, p, dt):
+    """Gradient-optimisation rule: every element moves against the sign of its energy
+    derivative by p * dt(n), p in (0, 1) drawn per element (passed in).  A zero (or NaN)
+    derivative leaves the element where it is.  Returns a new array."""
+    g = np.asarray(grad, dtype=np.float64).reshape(np.shape(A))
+    s = np.where(g > 0, 1.0, np.where(g < 0, -1.0, 0.0))
+    step = np.asarray(p, dtype=np.float64).reshape(np.shape(A)) * dt
+    return np.asarray(A, dtype=np.float64) - step * s
+
+
+def vmc_step(A, lat, S, u, p, dt):
+    """One iteration of the GO main loop: ln|W| of the chains S under A, len(u)
+    Metropolis steps of every chain (u[t] are the uniforms of step t), the energy and
+    gradient over the chains' configurations, then the GO update with the per-element
+    p and the step dt.  Returns (A_new, S, E, count, grad)."""
+    la, sg, _ = log_amplitude(A, lat, S)
+    for t in range(len(u)):
+        S, la, sg, _ = metropolis_step(A, lat, S, u[t], la, sg)
+    E, count, grad, _, _ = energy_gradient(A, lat, S)
+    return go_update(A, grad, p, dt), S, E, count, grad

@@ -434,3 +434,82 @@ def test_metropolis_rule_keeps_w2_stationary():
     assert np.abs(pi @ T - pi).max() < 1e-14
     pa = np.abs(w) / np.abs(w).sum()
     assert np.abs(pa @ T - pa).max() > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Monte Carlo estimators (Eqs. (3), (5)), the GO update and one optimisation step
+# --------------------------------------------------------------------------
+def _sector_setup(seed):
+    lat = Lattice(4, 2, 2, 4)
+    A, S = make_random(lat, 128, seed)
+    cfg = _sz0_configs(lat.N)
+    idx = _amp_index(cfg)
+    Hs = P.heisenberg_j1j2(lat.Lx, lat.Ly, lat.J1, lat.J2)[idx][:, idx]
+
+    def energy(A_):
+        psi = P.full_wavefunction(A_, lat)[idx]
+        return float(psi @ (Hs @ psi) / (psi @ psi))
+    return lat, A, S, cfg, idx, energy
+
+
+def test_energy_gradient_with_exact_weights_is_the_exact_gradient():
+    """Exact regime (4x2, D=2, Dc=4): the estimators of Eqs. (3) and (5), averaged over
+    all 70 S^z = 0 configurations with weights W(S)^2 (dense contraction), equal the
+    Rayleigh quotient of H on that sector and its derivative by central differences
+    with respect to every tensor element (dead boundary entries included: zero)."""
+    lat, A, _, cfg, idx, energy = _sector_setup(45)
+    w = P.full_wavefunction(A, lat)[idx] ** 2
+    E, cnt, g, _, fl = O.energy_gradient(A, lat, cfg, weights=w)
+    assert cnt == 70 and np.all(fl == 0)
+    assert abs(E - energy(A)) <= 1e-12 * max(1.0, abs(E))
+    h = 1e-6
+    fd = np.zeros(A.size)
+    flat = A.reshape(-1)
+    for k in range(A.size):
+        Ap = flat.copy()
+        Ap[k] += h
+        Am = flat.copy()
+        Am[k] -= h
+        fd[k] = (energy(Ap.reshape(A.shape)) - energy(Am.reshape(A.shape))) / (2 * h)
+    g = g.reshape(-1)
+    assert np.linalg.norm(g - fd) <= 1e-7 * np.linalg.norm(fd)
+    assert np.all(g[fd == 0.0] == 0.0) and np.count_nonzero(fd) > 0
+
+
+def test_go_update_descends_to_first_order():
+    """The GO step A - p dt sign(dE/dA) with the exact gradient changes the exact energy
+    by -dt sum p |dE/dA| to first order: the error of that prediction shrinks four-fold
+    when dt halves, and the energy goes down.  Entries with zero derivative stay."""
+    lat, A, _, cfg, idx, energy = _sector_setup(45)
+    w = P.full_wavefunction(A, lat)[idx] ** 2
+    _, _, g, _, _ = O.energy_gradient(A, lat, cfg, weights=w)
+    g = g.reshape(A.shape)
+    p = np.random.default_rng(9).uniform(0.0, 1.0, A.shape)
+    rate = -(p * np.abs(g)).sum()
+    E0 = energy(A)
+    res = []
+    for dt in (1e-4, 5e-5):
+        A1 = O.go_update(A, g, p, dt)
+        dE = energy(A1) - E0
+        assert dE < 0
+        res.append(abs(dE - dt * rate))
+        assert res[-1] < 0.05 * abs(dt * rate)
+        assert np.array_equal(A1[g == 0], A[g == 0])
+    assert res[1] < 0.3 * res[0]
+
+
+def test_vmc_steps_lower_the_exact_energy():
+    """Three optimisation steps (8 Metropolis steps of 128 chains, the sampled gradient,
+    GO with dt = 0.02) from a random 4x2 state lower the exact sector energy at every
+    step; the chains stay in the S^z = 0 sector."""
+    lat, A, S, cfg, idx, energy = _sector_setup(45)
+    rng = np.random.default_rng(2)
+    E = [energy(A)]
+    for _ in range(3):
+        u = rng.random((8, S.shape[0], 2))
+        p = rng.random(A.shape)
+        A, S, Em, cnt, g = O.vmc_step(A, lat, S, u, p, 0.02)
+        assert cnt == S.shape[0] and np.all(S.sum(1) == lat.N // 2)
+        E.append(energy(A))
+    assert all(b < a for a, b in zip(E, E[1:])), E
+    assert E[-1] < E[0] - 0.5
