@@ -209,6 +209,21 @@ def main():
         res["mcmc"] = {"value": B * args.steps / dtm, "unit": "chain-steps/s",
                        "ms_per_step": dtm * 1e3 / args.steps, "chains": B,
                        "acceptance": acc.sum().item() / (B * args.steps)}
+        # one optimisation-loop iteration: ln|W| of the chains, 4 Metropolis steps, the
+        # sampled energy and gradient over the chains, the GO update of the tensors
+        Av = Ad.clone()
+        n_mc, iters = 4, 2
+        Uv = torch.rand((iters + 1, n_mc, B, 2), dtype=torch.float64, device=dev, generator=g)
+        Pv = torch.rand((iters + 1,) + tuple(Ad.shape), dtype=torch.float64, device=dev, generator=g)
+        peps.vmc_step(Av, Sm, lat, Uv[0], Pv[0], 1e-3, args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(iters):
+            Ev, _ = peps.vmc_step(Av, Sm, lat, Uv[k + 1], Pv[k + 1], 1e-3, args.prec)
+        torch.cuda.synchronize()
+        dtv = time.perf_counter() - t0
+        res["vmc"] = {"ms_per_iteration": dtv * 1e3 / iters, "chains": B, "metropolis_steps": n_mc,
+                      "energy": Ev[0].item()}
     if not args.no_plain:
         # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
         nplain = 8

@@ -137,11 +137,41 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
  *   peps_log_amplitude), updated with the moves.
  * u: device float64 [batch][2], uniform in [0, 1), drawn by the caller.
  * accepted: device int8 [batch] or NULL; 1 where the chain moved, else 0.
- * Work is enqueued on the context's stream; the context keeps a proposal buffer of
- * about batch * (N + 11) bytes between calls. */
+ * Work is enqueued on the context's stream; the context keeps its sampling buffers
+ * (about batch * (N + 35) bytes) between calls. */
 peps_status peps_metropolis_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
                                  const double* A, int8_t* S, int64_t batch, const double* u,
                                  double* log_abs, int8_t* sign, int8_t* accepted);
+
+/* Gradient-optimisation update of the tensors (Sec. II-A): every element moves against
+ * the sign of its energy derivative, A[i] -= p[i] * dt * sign(grad[i]), with p[i] in
+ * (0, 1) drawn per element by the caller and dt the step length of this iteration.  A
+ * zero or NaN derivative leaves the element unchanged.
+ * A: device float64 [Ly*Lx][2][D^4] (the layout of every entry point), updated in place.
+ * grad, p: device float64, same layout.  dt must be finite.
+ * Enqueued on the context's stream; no allocation. */
+peps_status peps_go_update(peps_ctx* ctx, const peps_lattice* lat, double* A, const double* grad,
+                           const double* p, double dt);
+
+/* One iteration of the optimisation loop (Sec. II-B, Step B; Step B-a then B-b):
+ *   1. ln|W| of the chains S under A (as peps_log_amplitude);
+ *   2. n_mc Metropolis steps of every chain (as peps_metropolis_step, step t taking the
+ *      uniforms u + 2*batch*t);
+ *   3. the sampled energy (Eq. (3)) and dE/dA (Eq. (5)) over the chains' configurations,
+ *      samples with a non-zero flag left out (as peps_evaluate with grad_mode 3);
+ *   4. the GO update of A with p and dt (as peps_go_update).
+ * A: device float64 [Ly*Lx][2][D^4], updated in place.  S: device int8 [batch][Ly*Lx],
+ * the chains, updated in place.  u: device float64 [n_mc][batch][2] uniforms in [0, 1)
+ * (may be NULL when n_mc is 0).  p: device float64 [Ly*Lx][2][D^4] in (0, 1).
+ * energy: device float64 [2] or NULL: {sampled E, number of samples with flag 0} (E is
+ * NaN when there is none).  grad: device float64 [Ly*Lx][2][D^4] or NULL: dE/dA before the
+ * update (the context keeps its own copy when NULL).
+ * batch must be at least 1.  Work is enqueued on the context's stream; the context keeps
+ * its sampling buffers (about batch * (N + 35) bytes, plus the gradient when grad is
+ * NULL) between calls. */
+peps_status peps_vmc_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec, double* A,
+                          int8_t* S, int64_t batch, int32_t n_mc, const double* u, const double* p,
+                          double dt, double* energy, double* grad);
 
 /* One job of a heterogeneous batch (peps_eval_jobs): a lattice with its own tensors,
  * configurations and outputs, with the meanings of peps_evaluate.  A NULL e_loc skips

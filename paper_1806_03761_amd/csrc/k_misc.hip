@@ -471,6 +471,35 @@ hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, co
     return hipGetLastError();
 }
 
+// Sampled energy of Eq. (3) from the ordered sums of k_energy_sums: out = {mean, count}
+// (NaN mean when no sample has flag 0).
+__global__ void k_energy_mean(const double* acc, double* out) {
+    if (threadIdx.x != 0) return;
+    out[0] = acc[1] == 0.0 ? __longlong_as_double(0x7ff8000000000000LL) : acc[0] / acc[1];
+    out[1] = acc[1];
+}
+hipError_t launch_energy_mean(const double* acc, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_mean, dim3(1), dim3(64), 0, st, acc, out);
+    return hipGetLastError();
+}
+
+// Gradient-optimisation update: A[i] moves against the sign of grad[i] by p[i] * dt; a
+// zero or NaN derivative leaves it.  The step p * dt is rounded on its own before the
+// addition (no fused multiply-add), so the result is the exactly rounded rule.
+__global__ void k_go_update(double* A, const double* grad, const double* p, double dt, long long n) {
+#pragma clang fp contract(off)
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double g = grad[i], step = p[i] * dt, a = A[i];
+    A[i] = g > 0.0 ? a - step : (g < 0.0 ? a + step : a);
+}
+hipError_t launch_go_update(double* A, const double* grad, const double* p, double dt, long long n,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_go_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, grad, p, dt, n);
+    return hipGetLastError();
+}
+
 // Eq. (5): dE/dA = 2 <Delta E> - 2 <Delta><E> with <.> the mean over flag-0 samples.
 __global__ void k_energy_grad_combine(const double* G1, const double* G0, const double* acc,
                                       long long n, double* out) {

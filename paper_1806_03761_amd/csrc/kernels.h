@@ -129,6 +129,9 @@ hipError_t launch_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const d
 hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
                             const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
                             int8_t* sign, int8_t* accepted, int N, int batch, hipStream_t st);
+hipError_t launch_energy_mean(const double* acc, double* out, hipStream_t st);
+hipError_t launch_go_update(double* A, const double* grad, const double* p, double dt, long long n,
+                            hipStream_t st);
 hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate, hipStream_t st);
 hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -1342,24 +1343,26 @@ peps_status peps_log_derivative(peps_ctx* c, const peps_lattice* lat, peps_preci
                    out, flags);
 }
 
-peps_status peps_metropolis_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
-                                 const double* A, int8_t* S, int64_t batch, const double* u,
-                                 double* log_abs, int8_t* sign, int8_t* accepted) {
-    if (!c) return PEPS_ERR_INVALID_ARG;
-    c->err.clear();
-    if (!lat) return fail(c, PEPS_ERR_INVALID_ARG, "lattice is NULL");
-    peps_status st = check_lat(c, lat);
-    if (st != PEPS_OK) return st;
-    if (batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
-    if (batch == 0) return PEPS_OK;
-    if (batch > (1LL << 30)) return fail(c, PEPS_ERR_INVALID_ARG, "batch too large");
-    if (!A || !S || !u || !log_abs || !sign) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
-    const int N = lat->Lx * lat->Ly;
-    // proposals S' [batch][N], ln|W(S')| [batch], sign, flag, moved [batch]
+}  // extern "C"
+
+// Buffers of the sampling and optimisation entry points, carved from one per-context
+// allocation that grows on demand: proposals S' [batch][N] with ln|W(S')|, sign, flag and
+// moved [batch]; the chains' ln|W|, sign, E(S), flags [batch]; the energy sums; the
+// gradient [N][2][D^4].
+struct McBuffers {
+    int8_t* Sp; double* lap; int8_t* sgp; int8_t* flp; int8_t* moved;
+    double* la; int8_t* sg; double* e; int8_t* fl; double* acc; double* grad;
+};
+
+static peps_status mc_buffers(peps_ctx* c, int64_t batch, int N, long long ngrad, McBuffers* m) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t oSp = 0, oLa = up((size_t)batch * N), oSg = oLa + up((size_t)batch * 8);
-    const size_t oFl = oSg + up((size_t)batch), oMv = oFl + up((size_t)batch), need = oMv + up((size_t)batch);
+    const size_t B = (size_t)batch;
+    size_t off[11], need = 0;
+    const size_t sz[11] = {B * N, B * 8, B, B, B, B * 8, B, B * 8, B, 16, (size_t)ngrad * 8};
+    for (int k = 0; k < 11; ++k) {
+        off[k] = need;
+        need += up(sz[k]);
+    }
     if (need > c->mc_bytes) {
         if (c->mc) {
             if (c->stream) hipStreamSynchronize(c->stream);
@@ -1374,16 +1377,105 @@ peps_status peps_metropolis_step(peps_ctx* c, const peps_lattice* lat, peps_prec
         }
         c->mc_bytes = need;
     }
-    int8_t* Sp = reinterpret_cast<int8_t*>(c->mc + oSp);
-    double* lap = reinterpret_cast<double*>(c->mc + oLa);
-    int8_t* sgp = reinterpret_cast<int8_t*>(c->mc + oSg);
-    int8_t* flp = reinterpret_cast<int8_t*>(c->mc + oFl);
-    int8_t* moved = reinterpret_cast<int8_t*>(c->mc + oMv);
-    hipError_t e = launch_mc_propose(S, Sp, moved, u, lat->Lx, lat->Ly, (int)batch, c->stream);
+    char* b = c->mc;
+    *m = McBuffers{reinterpret_cast<int8_t*>(b + off[0]), reinterpret_cast<double*>(b + off[1]),
+                   reinterpret_cast<int8_t*>(b + off[2]), reinterpret_cast<int8_t*>(b + off[3]),
+                   reinterpret_cast<int8_t*>(b + off[4]), reinterpret_cast<double*>(b + off[5]),
+                   reinterpret_cast<int8_t*>(b + off[6]), reinterpret_cast<double*>(b + off[7]),
+                   reinterpret_cast<int8_t*>(b + off[8]), reinterpret_cast<double*>(b + off[9]),
+                   reinterpret_cast<double*>(b + off[10])};
+    return PEPS_OK;
+}
+
+// One Metropolis step of every chain on validated arguments: propose, contract W(S'),
+// accept (Sec. II-B steps 1-3).
+static peps_status mc_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                           int8_t* S, int64_t batch, const double* u, double* log_abs, int8_t* sign,
+                           int8_t* accepted, const McBuffers& m) {
+    const int N = lat->Lx * lat->Ly;
+    hipError_t e = launch_mc_propose(S, m.Sp, m.moved, u, lat->Lx, lat->Ly, (int)batch, c->stream);
     if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
-    st = run_all(c, lat, prec, A, Sp, batch, false, 0, nullptr, lap, sgp, nullptr, nullptr, flp);
+    peps_status st = run_all(c, lat, prec, A, m.Sp, batch, false, 0, nullptr, m.lap, m.sgp, nullptr, nullptr,
+                             m.flp);
     if (st != PEPS_OK) return st;
-    e = launch_mc_accept(S, Sp, moved, u, lap, sgp, flp, log_abs, sign, accepted, N, (int)batch, c->stream);
+    e = launch_mc_accept(S, m.Sp, m.moved, u, m.lap, m.sgp, m.flp, log_abs, sign, accepted, N, (int)batch,
+                         c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    return PEPS_OK;
+}
+
+static peps_status check_batch_call(peps_ctx* c, const peps_lattice* lat, int64_t batch) {
+    peps_status st = check_lat(c, lat);
+    if (st != PEPS_OK) return st;
+    if (batch < 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch < 0");
+    if (batch > (1LL << 30)) return fail(c, PEPS_ERR_INVALID_ARG, "batch too large");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
+    return PEPS_OK;
+}
+
+extern "C" {
+
+peps_status peps_metropolis_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec,
+                                 const double* A, int8_t* S, int64_t batch, const double* u,
+                                 double* log_abs, int8_t* sign, int8_t* accepted) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_batch_call(c, lat, batch);
+    if (st != PEPS_OK || batch == 0) return st;
+    if (!A || !S || !u || !log_abs || !sign) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    McBuffers m;
+    st = mc_buffers(c, batch, lat->Lx * lat->Ly, 0, &m);
+    if (st != PEPS_OK) return st;
+    return mc_step(c, lat, prec, A, S, batch, u, log_abs, sign, accepted, m);
+}
+
+peps_status peps_go_update(peps_ctx* c, const peps_lattice* lat, double* A, const double* grad,
+                           const double* p, double dt) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_batch_call(c, lat, 0);
+    if (st != PEPS_OK) return st;
+    if (!A || !grad || !p) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    if (!std::isfinite(dt)) return fail(c, PEPS_ERR_INVALID_ARG, "dt is not finite");
+    const long long n = (long long)lat->Lx * lat->Ly * 2 * lat->D * lat->D * lat->D * lat->D;
+    hipError_t e = launch_go_update(A, grad, p, dt, n, c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    return PEPS_OK;
+}
+
+peps_status peps_vmc_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec, double* A, int8_t* S,
+                          int64_t batch, int32_t n_mc, const double* u, const double* p, double dt,
+                          double* energy, double* grad) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_batch_call(c, lat, batch);
+    if (st != PEPS_OK) return st;
+    if (batch == 0) return fail(c, PEPS_ERR_INVALID_ARG, "batch is 0: no samples to estimate from");
+    if (n_mc < 0) return fail(c, PEPS_ERR_INVALID_ARG, "n_mc < 0");
+    if (!A || !S || !p || (n_mc > 0 && !u)) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    if (!std::isfinite(dt)) return fail(c, PEPS_ERR_INVALID_ARG, "dt is not finite");
+    const int N = lat->Lx * lat->Ly;
+    const long long ng = (long long)N * 2 * lat->D * lat->D * lat->D * lat->D;
+    McBuffers m;
+    st = mc_buffers(c, batch, N, grad ? 0 : ng, &m);
+    if (st != PEPS_OK) return st;
+    double* g = grad ? grad : m.grad;
+    // ln|W| of the chains under the current tensors, then the Metropolis steps
+    st = run_all(c, lat, prec, A, S, batch, false, 0, nullptr, m.la, m.sg, nullptr, nullptr, m.fl);
+    if (st != PEPS_OK) return st;
+    for (int t = 0; t < n_mc; ++t) {
+        st = mc_step(c, lat, prec, A, S, batch, u + 2LL * batch * t, m.la, m.sg, nullptr, m);
+        if (st != PEPS_OK) return st;
+    }
+    // Eqs. (3) and (5) over the chains, then the GO update of A
+    st = run_all(c, lat, prec, A, S, batch, true, 3, nullptr, m.la, m.sg, m.e, g, m.fl);
+    if (st != PEPS_OK) return st;
+    hipError_t e = hipSuccess;
+    if (energy) {
+        e = launch_energy_sums(m.e, m.fl, (int)batch, m.acc, 0, c->stream);
+        if (e == hipSuccess) e = launch_energy_mean(m.acc, energy, c->stream);
+    }
+    if (e == hipSuccess) e = launch_go_update(A, g, p, dt, ng, c->stream);
     if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
     return PEPS_OK;
 }

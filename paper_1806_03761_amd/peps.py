@@ -68,6 +68,9 @@ _SIGS = {
                       ctypes.c_int32, _P, _P, _P, _P, _P, _P],
     "peps_metropolis_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                              _P, _P, _P, _P],
+    "peps_go_update": [_P, ctypes.POINTER(_Lattice), _P, _P, _P, ctypes.c_double],
+    "peps_vmc_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                      _P, _P, ctypes.c_double, _P, _P],
 }
 
 
@@ -293,6 +296,48 @@ def metropolis_step(A, S, lat, u, log_abs, sign, prec: str = "f64", accepted=Non
                                   _ptr(log_abs), _ptr(sign), _ptr(accepted))
     _check(lib, ctx, st, "peps_metropolis_step")
     return accepted
+
+
+def _param_like(t, A, what):
+    if t.dtype != torch.float64 or t.numel() != A.numel() or not t.is_contiguous() or t.device != A.device:
+        raise PepsError(f"{what} must be a contiguous float64 tensor with the elements of A, on {A.device}")
+
+
+def go_update(A, grad, p, lat, dt: float):
+    """GO update in place (peps_go_update): A -= p * dt * sign(grad), elementwise."""
+    lib, ctx = _context(A.device.index or 0)
+    for t, what in ((A, "A"), (grad, "grad"), (p, "p")):
+        _param_like(t, A, what)
+    N, D = lat.Lx * lat.Ly, lat.D
+    if tuple(A.shape) != (N, 2, D, D, D, D):
+        raise PepsError(f"A has shape {tuple(A.shape)}, expected {(N, 2, D, D, D, D)}")
+    st = lib.peps_go_update(ctx, ctypes.byref(_lat(lat)), _ptr(A), _ptr(grad), _ptr(p), float(dt))
+    _check(lib, ctx, st, "peps_go_update")
+    return A
+
+
+def vmc_step(A, S, lat, u, p, dt: float, prec: str = "f64", grad=None, return_grad: bool = True):
+    """One optimisation-loop iteration in place (peps_vmc_step): u is float64
+    [n_mc][batch][2] (n_mc may be 0), p shaped like A.  Returns (energy, grad) with
+    energy a float64 device tensor {E, count} and grad dE/dA before the update (None
+    with return_grad False: the library then keeps the gradient to itself)."""
+    lib, ctx, A2, S2 = _prep(A, S, lat)
+    if A2.data_ptr() != A.data_ptr() or S2.data_ptr() != S.data_ptr():
+        raise PepsError("A and S must be contiguous: they are updated in place")
+    B = S.shape[0]
+    if u.dtype != torch.float64 or u.dim() != 3 or tuple(u.shape[1:]) != (B, 2) or not u.is_contiguous() \
+            or u.device != A.device:
+        raise PepsError(f"u must be a contiguous float64 tensor of shape (n_mc, {B}, 2)")
+    _param_like(p, A, "p")
+    if grad is None and return_grad:
+        grad = torch.empty_like(A)
+    if grad is not None:
+        _param_like(grad, A, "grad")
+    energy = torch.empty(2, dtype=torch.float64, device=A.device)
+    st = lib.peps_vmc_step(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, u.shape[0],
+                           _ptr(u) if u.numel() else None, _ptr(p), float(dt), _ptr(energy), _ptr(grad))
+    _check(lib, ctx, st, "peps_vmc_step")
+    return energy, grad
 
 
 def job_outputs(A, S, lat, grad_mode=3, want_eloc=True):
