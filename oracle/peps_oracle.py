@@ -14,7 +14,10 @@ What it computes, per spin configuration S (paper Sec. II-A):
     for the weights W(S)^2 of Eq. (3), with the uniform random numbers passed in;
   * the sampled energy (Eq. (3)) and gradient (Eq. (5)), the gradient-optimisation
     update of the tensors, and one iteration of the optimisation loop (Sec. II-B,
-    Step B: sample, estimate, update), with the random step factors passed in.
+    Step B: sample, estimate, update), with the random step factors passed in;
+  * spin-spin correlations <S_m . S_m'> (local value sigma sigma / 4 plus half the
+    ratio W(S')/W(S) of the exchanged configuration, contracted in full) and the
+    structure factor m_s^2(k) over a block of sites (Sec. III-B).
 Everything is IEEE float64.  numpy's QR and SVD (LAPACK) are used as library
 steps; contractions are written as einsum calls, one per tensor pair.
 
@@ -511,3 +514,74 @@ def vmc_step(A, lat, S, u, p, dt):
         S, la, sg, _ = metropolis_step(A, lat, S, u[t], la, sg)
     E, count, grad, _, _ = energy_gradient(A, lat, S)
     return go_update(A, grad, p, dt), S, E, count, grad
+
+
+# --------------------------------------------------------------------------
+# Spin-spin correlations (Sec. III-B: <S_m . S_m'> and the structure factor m_s^2(k))
+# --------------------------------------------------------------------------
+def pair_correlation_one(A, lat, S, m, n, la=None, sg=None):
+    """Local value of S_m . S_n at configuration S: sigma_m sigma_n / 4, plus 1/2 W(S')/W(S)
+    when the two spins differ (S' = S with them exchanged), W(S') from a full contraction;
+    3/4 when m == n.  Returns (value, flag): the flag of S, or FLAG_NONFINITE when the
+    contraction of S' is not finite (a zero W(S') just gives a zero ratio)."""
+    if la is None:
+        la, sg, fl = log_amplitude_one(A, lat, S)
+        if fl != FLAG_OK:
+            return math.nan, fl
+    if m == n:
+        return 0.75, FLAG_OK
+    sm, sn = 1 - 2 * int(S[m]), 1 - 2 * int(S[n])
+    v = 0.25 * sm * sn
+    if S[m] != S[n]:
+        Sp = np.array(S, dtype=np.int8, copy=True)
+        Sp[m], Sp[n] = S[n], S[m]
+        lap, sgp, flp = log_amplitude_one(A, lat, Sp)
+        if flp == FLAG_ZERO_AMPLITUDE:
+            return v, FLAG_OK
+        if flp != FLAG_OK:
+            return math.nan, FLAG_NONFINITE
+        v += 0.5 * sgp * sg * math.exp(lap - la)
+    return v, FLAG_OK
+
+
+def pair_correlations(A, lat, S, pairs, weights=None):
+    """Monte Carlo mean of S_m . S_n for every (m, n) in pairs over the samples whose
+    configuration and exchanged configurations all contract (flag 0); weights as in
+    energy_gradient.  Returns (means [P], per-sample values [B][P], flags [B])."""
+    B, P = S.shape[0], len(pairs)
+    vals = np.full((B, P), np.nan)
+    fl = np.zeros(B, dtype=np.int8)
+    for b in range(B):
+        la, sg, f = log_amplitude_one(A, lat, S[b])
+        if f != FLAG_OK:
+            fl[b] = f
+            continue
+        for k, (m, n) in enumerate(pairs):
+            vals[b, k], f = pair_correlation_one(A, lat, S[b], m, n, la, sg)
+            if f != FLAG_OK:
+                fl[b] = f
+                break
+    ok = fl == FLAG_OK
+    w = np.ones(B) if weights is None else np.asarray(weights, dtype=np.float64)
+    w = np.where(ok, w, 0.0)
+    if w.sum() == 0.0:
+        return np.full(P, np.nan), vals, fl
+    means = (w[ok, None] * vals[ok]).sum(0) / w.sum()
+    return means, vals, fl
+
+
+def structure_factor(lat, sites, corr, ks):
+    """m_s^2(k) = (1 / Nb^2) sum_{m, m' in sites} <S_m . S_m'> exp(i k . (r_m - r_m'))
+    for each k = (kx, ky), with r_m = (column, row) of site m and Nb = len(sites).
+    corr: the full matrix <S_m . S_m'> over `sites` (diagonal 3/4).  Returns real parts."""
+    r = np.array([(s % lat.Lx, s // lat.Lx) for s in sites], dtype=np.float64)
+    out = []
+    for kx, ky in ks:
+        ph = np.exp(1j * (kx * r[:, 0] + ky * r[:, 1]))
+        out.append(float(np.real(ph @ corr @ np.conj(ph))) / len(sites) ** 2)
+    return np.array(out)
+
+
+def bulk_sites(lat, margin=2):
+    """Sites of the central (Lx - 2 margin) x (Ly - 2 margin) block, row-major."""
+    return [i * lat.Lx + j for i in range(margin, lat.Ly - margin) for j in range(margin, lat.Lx - margin)]

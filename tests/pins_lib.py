@@ -238,3 +238,21 @@ def gauge_dress(A, lat, rng, horizontal=True, vertical="orthogonal", cond=3.0):
                 A[m] = np.einsum("slurd,dx->slurx", A[m], G)
                 A[m + lat.Lx] = np.einsum("xu,slurd->slxrd", Gi, A[m + lat.Lx])
     return A
+
+
+def spin_pair_operator(N, m, n):
+    """Sparse S_m . S_n on {0,1}^N (basis index as above; s = 0 is S^z = +1/2): the
+    diagonal +-1/4 and the exchange of an anti-parallel pair with element 1/2."""
+    dim = 2 ** N
+    idx = np.arange(dim, dtype=np.int64)
+    if m == n:
+        return sp.identity(dim, format="csr") * 0.75
+    bm = (idx >> (N - 1 - m)) & 1
+    bn = (idx >> (N - 1 - n)) & 1
+    diag = 0.25 * np.where(bm == bn, 1.0, -1.0)
+    anti = np.nonzero(bm != bn)[0]
+    flipped = anti ^ ((1 << (N - 1 - m)) | (1 << (N - 1 - n)))
+    rows = np.concatenate([idx, flipped])
+    cols = np.concatenate([idx, anti])
+    vals = np.concatenate([diag, np.full(anti.size, 0.5)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(dim, dim))

@@ -513,3 +513,62 @@ def test_vmc_steps_lower_the_exact_energy():
         E.append(energy(A))
     assert all(b < a for a, b in zip(E, E[1:])), E
     assert E[-1] < E[0] - 0.5
+
+
+# --------------------------------------------------------------------------
+# Spin-spin correlations and the structure factor (Sec. III-B)
+# --------------------------------------------------------------------------
+def test_pair_correlations_with_exact_weights_equal_dense_expectation():
+    """Exact regime (4x2, D=2, Dc=4): the correlation estimator averaged over all 70
+    S^z = 0 configurations with weights W(S)^2 equals <psi|S_m . S_n|psi> / <psi|psi> with
+    the operator built on the full Hilbert space, for every pair (and m == n)."""
+    lat = Lattice(4, 2, 2, 4)
+    A, _ = make_random(lat, 0, 47)
+    psi = P.full_wavefunction(A, lat)
+    cfg = _sz0_configs(lat.N)
+    idx = _amp_index(cfg)
+    pairs = [(m, n) for m in range(lat.N) for n in range(m, lat.N)]
+    means, vals, fl = O.pair_correlations(A, lat, cfg, pairs, weights=psi[idx] ** 2)
+    assert np.all(fl == 0)
+    ps = np.zeros_like(psi)
+    ps[idx] = psi[idx]
+    for k, (m, n) in enumerate(pairs):
+        want = ps @ (P.spin_pair_operator(lat.N, m, n) @ ps) / (ps @ ps)
+        assert abs(means[k] - want) < 1e-12, (m, n, means[k], want)
+
+
+def test_structure_factor_closed_forms():
+    """Neel correlations (<S_m.S_n> = +-1/4 by sublattice, 3/4 on the diagonal) give
+    m^2(pi, pi) = 3/(4 Nb) + (Nb - 1)/(4 Nb) and m^2(0, 0) = 1/(2 Nb) (the staggered sum
+    cancels); ferromagnetic correlations (1/4 off the diagonal) the reverse; and over all
+    sites of a state, N^2 m^2(0) = <S_tot^2>."""
+    lat = Lattice(8, 8, 4, 16)
+    sites = O.bulk_sites(lat)
+    assert len(sites) == 16 and sites[0] == 2 * 8 + 2 and sites[-1] == 5 * 8 + 5
+    Nb = len(sites)
+    par = np.array([(s % 8 + s // 8) % 2 for s in sites])
+    neel = np.where(par[:, None] == par[None, :], 0.25, -0.25)
+    np.fill_diagonal(neel, 0.75)
+    ferro = np.full((Nb, Nb), 0.25)
+    np.fill_diagonal(ferro, 0.75)
+    m = O.structure_factor(lat, sites, neel, [(np.pi, np.pi), (0.0, 0.0)])
+    assert abs(m[0] - (0.75 / Nb + (Nb - 1) / (4 * Nb))) < 1e-14
+    assert abs(m[1] - 0.5 / Nb) < 1e-14
+    m = O.structure_factor(lat, sites, ferro, [(np.pi, np.pi), (0.0, 0.0)])
+    assert abs(m[0] - 0.5 / Nb) < 1e-14
+    assert abs(m[1] - (0.75 / Nb + (Nb - 1) / (4 * Nb))) < 1e-14
+    # total spin of an exact 4x2 state (dense) against the estimator's matrix
+    lat = Lattice(4, 2, 2, 4)
+    A, _ = make_random(lat, 0, 47)
+    psi = P.full_wavefunction(A, lat)
+    cfg = _sz0_configs(lat.N)
+    idx = _amp_index(cfg)
+    pairs = [(a, b) for a in range(lat.N) for b in range(lat.N)]
+    means, _, _ = O.pair_correlations(A, lat, cfg, pairs, weights=psi[idx] ** 2)
+    C = means.reshape(lat.N, lat.N)
+    ps = np.zeros_like(psi)
+    ps[idx] = psi[idx]
+    S2 = sum(P.spin_pair_operator(lat.N, a, b) for a in range(lat.N) for b in range(lat.N))
+    want = ps @ (S2 @ ps) / (ps @ ps)
+    m0 = O.structure_factor(lat, list(range(lat.N)), C, [(0.0, 0.0)])[0]
+    assert abs(lat.N ** 2 * m0 - want) < 1e-11
