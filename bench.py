@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mcmc", action="store_true", help="skip the Metropolis sampling leg")
+    ap.add_argument("--no-corr", action="store_true", help="skip the correlation-estimator leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (3 times): the reference "
@@ -224,6 +225,21 @@ def main():
         dtv = time.perf_counter() - t0
         res["vmc"] = {"ms_per_iteration": dtv * 1e3 / iters, "chains": B, "metropolis_steps": n_mc,
                       "energy": Ev[0].item()}
+    if not args.no_corr:
+        # correlation estimator on the first 1024 samples: <S_i . S_j> over the central
+        # 4x4 block (136 pairs i <= j, the anti-parallel ones contracted in full) and
+        # m^2 at (pi, pi)
+        nb = min(B, 1024)
+        sites = [i * lat.Lx + j for i in range(2, lat.Ly - 2) for j in range(2, lat.Lx - 2)]
+        peps.correlation_matrix(Ad, Sd[:nb], lat, sites, args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, _ = peps.correlation_matrix(Ad, Sd[:nb], lat, sites, args.prec)
+        m2 = peps.structure_factor(C, lat, sites, [(3.141592653589793, 3.141592653589793)])
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t0
+        res["corr"] = {"ms": dtc * 1e3, "samples": nb, "pairs": len(sites) * (len(sites) + 1) // 2,
+                       "samples_per_s": nb / dtc, "m2_pi_pi": m2[0].item()}
     if not args.no_plain:
         # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
         nplain = 8

@@ -173,6 +173,35 @@ peps_status peps_vmc_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           int8_t* S, int64_t batch, int32_t n_mc, const double* u, const double* p,
                           double dt, double* energy, double* grad);
 
+/* Spin-spin correlations <S_m . S_n> by Monte Carlo (Sec. III-B): for every sample and
+ * pair, the local value sigma_m sigma_n / 4 plus, where the two spins differ, half the
+ * ratio W(S')/W(S) of the configuration with them exchanged (both contracted in full, as
+ * in peps_log_amplitude); 3/4 when m == n.  A zero W(S') gives a zero ratio; a sample
+ * whose W(S), or any of whose W(S'), has another non-zero flag is left out (flag 3 for
+ * an exchanged configuration that is not finite).
+ * pairs: device int32 [npairs][2] site indices in [0, Ly*Lx) (checked; read back to the
+ *   host, which synchronises the context's stream).
+ * means: device float64 [npairs] or NULL: mean over the samples with flag 0 (NaN when
+ *   there is none).  per_sample: device float64 [batch][npairs] or NULL (NaN where the
+ *   sample is left out).  flags: device int8 [batch] or NULL.
+ * batch * npairs must be at most 2^30.  The context keeps a buffer of about
+ * batch * npairs * (N + 22) bytes between calls. */
+peps_status peps_pair_correlations(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                                   const double* A, const int8_t* S, int64_t batch, int32_t npairs,
+                                   const int32_t* pairs, double* means, double* per_sample,
+                                   int8_t* flags);
+
+/* Structure factor of Sec. III-B over a block of nsites sites:
+ * out[q] = (1/nsites^2) sum_{i,j} corr[i][j] cos(k_q . (r_i - r_j)), r = (column, row) of
+ * the site, which is the real part of the Fourier sum for a real correlation matrix
+ * (M^2 = out at k = (pi, pi) with the central (L-4) x (L-4) block).
+ * sites: device int32 [nsites] (checked; read back to the host).  corr: device float64
+ * [nsites][nsites], <S_i . S_j> of those sites.  k: device float64 [nk][2].  out: device
+ * float64 [nk]. */
+peps_status peps_structure_factor(peps_ctx* ctx, const peps_lattice* lat, int32_t nsites,
+                                  const int32_t* sites, const double* corr, int32_t nk,
+                                  const double* k, double* out);
+
 /* One job of a heterogeneous batch (peps_eval_jobs): a lattice with its own tensors,
  * configurations and outputs, with the meanings of peps_evaluate.  A NULL e_loc skips
  * the local energy (unless grad_mode is 3). */

@@ -132,6 +132,15 @@ hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, co
 hipError_t launch_energy_mean(const double* acc, double* out, hipStream_t st);
 hipError_t launch_go_update(double* A, const double* grad, const double* p, double dt, long long n,
                             hipStream_t st);
+hipError_t launch_corr_pack(const int8_t* S, const int* pairs, int P, int N, int batch, int8_t* Sx, int* slot,
+                            int* count, hipStream_t st);
+hipError_t launch_corr_values(const int8_t* S, const int* pairs, int P, int N, int batch, const double* la,
+                              const int8_t* sg, const int8_t* fl, const int* slot, const double* lax,
+                              const int8_t* sgx, const int8_t* flx, double* v, int8_t* flags, hipStream_t st);
+hipError_t launch_corr_means(const double* v, const int8_t* flags, int P, int batch, double* means,
+                             hipStream_t st);
+hipError_t launch_structure_factor(int Lx, int nb, const int* sites, const double* C, int nk, const double* kv,
+                                   double* out, hipStream_t st);
 hipError_t launch_energy_sums(const double* e_loc, const int8_t* flags, int batch, double* acc,
                               int accumulate, hipStream_t st);
 hipError_t launch_energy_grad_combine(const double* G1, const double* G0, const double* acc,

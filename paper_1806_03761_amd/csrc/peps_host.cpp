@@ -50,8 +50,10 @@ struct peps_ctx {
     size_t ws_bytes = 0;
     size_t ws_limit = 0;
     double* ones = nullptr;   // 4096 ones
-    char* mc = nullptr;       // Metropolis proposals (peps_metropolis_step)
+    char* mc = nullptr;       // sampling buffers (peps_metropolis_step, peps_vmc_step)
     size_t mc_bytes = 0;
+    char* corr = nullptr;     // exchanged configurations and their amplitudes (peps_pair_correlations)
+    size_t corr_bytes = 0;
     std::string err;
 };
 
@@ -957,6 +959,7 @@ peps_status peps_destroy(peps_ctx* c) {
     if (c->ws) hipFree(c->ws);
     if (c->ones) hipFree(c->ones);
     if (c->mc) hipFree(c->mc);
+    if (c->corr) hipFree(c->corr);
     for (auto& r : c->prof) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -1354,6 +1357,24 @@ struct McBuffers {
     double* la; int8_t* sg; double* e; int8_t* fl; double* acc; double* grad;
 };
 
+// Grows a per-context device buffer to at least `need` bytes (contents not kept).
+static peps_status grow_buffer(peps_ctx* c, char** buf, size_t* bytes, size_t need) {
+    if (need <= *bytes) return PEPS_OK;
+    if (*buf) {
+        if (c->stream) hipStreamSynchronize(c->stream);
+        else hipDeviceSynchronize();
+        hipFree(*buf);
+        *buf = nullptr;
+        *bytes = 0;
+    }
+    if (hipMalloc(buf, need) != hipSuccess) {
+        *buf = nullptr;
+        return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", need);
+    }
+    *bytes = need;
+    return PEPS_OK;
+}
+
 static peps_status mc_buffers(peps_ctx* c, int64_t batch, int N, long long ngrad, McBuffers* m) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t B = (size_t)batch;
@@ -1363,20 +1384,8 @@ static peps_status mc_buffers(peps_ctx* c, int64_t batch, int N, long long ngrad
         off[k] = need;
         need += up(sz[k]);
     }
-    if (need > c->mc_bytes) {
-        if (c->mc) {
-            if (c->stream) hipStreamSynchronize(c->stream);
-            else hipDeviceSynchronize();
-            hipFree(c->mc);
-            c->mc = nullptr;
-            c->mc_bytes = 0;
-        }
-        if (hipMalloc(&c->mc, need) != hipSuccess) {
-            c->mc = nullptr;
-            return fail(c, PEPS_ERR_OOM, "hipMalloc of %zu bytes failed", need);
-        }
-        c->mc_bytes = need;
-    }
+    peps_status st = grow_buffer(c, &c->mc, &c->mc_bytes, need);
+    if (st != PEPS_OK) return st;
     char* b = c->mc;
     *m = McBuffers{reinterpret_cast<int8_t*>(b + off[0]), reinterpret_cast<double*>(b + off[1]),
                    reinterpret_cast<int8_t*>(b + off[2]), reinterpret_cast<int8_t*>(b + off[3]),
@@ -1476,6 +1485,85 @@ peps_status peps_vmc_step(peps_ctx* c, const peps_lattice* lat, peps_precision p
         if (e == hipSuccess) e = launch_energy_mean(m.acc, energy, c->stream);
     }
     if (e == hipSuccess) e = launch_go_update(A, g, p, dt, ng, c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    return PEPS_OK;
+}
+
+peps_status peps_pair_correlations(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                                   const int8_t* S, int64_t batch, int32_t npairs, const int32_t* pairs,
+                                   double* means, double* per_sample, int8_t* flags) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_batch_call(c, lat, batch);
+    if (st != PEPS_OK) return st;
+    if (npairs < 1) return fail(c, PEPS_ERR_INVALID_ARG, "npairs < 1");
+    if (!A || !S || !pairs) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    if (batch * (int64_t)npairs > (1LL << 30)) return fail(c, PEPS_ERR_INVALID_ARG, "batch * npairs too large");
+    const int N = lat->Lx * lat->Ly, P = npairs;
+    // the site indices are checked on the host before any kernel reads them
+    std::vector<int32_t> hp(2 * (size_t)P);
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipMemcpy(hp.data(), pairs, hp.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, PEPS_ERR_HIP, "cannot read the pair list");
+    for (int32_t x : hp)
+        if (x < 0 || x >= N) return fail(c, PEPS_ERR_INVALID_ARG, "pair site %d outside [0, %d)", x, N);
+    if (batch == 0) return PEPS_OK;
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t B = (size_t)batch, BP = B * P;
+    const size_t sz[10] = {BP * N, BP * 4, 256, BP * 8, BP, BP, B * 8, B, B, per_sample ? 0 : BP * 8};
+    size_t off[10], need = 0;
+    for (int k = 0; k < 10; ++k) {
+        off[k] = need;
+        need += up(sz[k]);
+    }
+    st = grow_buffer(c, &c->corr, &c->corr_bytes, need);
+    if (st != PEPS_OK) return st;
+    char* base = c->corr;
+    int8_t* Sx = reinterpret_cast<int8_t*>(base + off[0]);
+    int* slot = reinterpret_cast<int*>(base + off[1]);
+    int* count = reinterpret_cast<int*>(base + off[2]);
+    double* lax = reinterpret_cast<double*>(base + off[3]);
+    int8_t* sgx = reinterpret_cast<int8_t*>(base + off[4]);
+    int8_t* flx = reinterpret_cast<int8_t*>(base + off[5]);
+    double* la = reinterpret_cast<double*>(base + off[6]);
+    int8_t* sg = reinterpret_cast<int8_t*>(base + off[7]);
+    int8_t* fl = reinterpret_cast<int8_t*>(base + off[8]);
+    double* v = per_sample ? per_sample : reinterpret_cast<double*>(base + off[9]);
+    st = run_all(c, lat, prec, A, S, batch, false, 0, nullptr, la, sg, nullptr, nullptr, fl);
+    if (st != PEPS_OK) return st;
+    hipError_t e = hipMemsetAsync(count, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = launch_corr_pack(S, pairs, P, N, (int)batch, Sx, slot, count, c->stream);
+    int hcount = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hcount, count, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    if (hcount < 0 || (size_t)hcount > BP) return fail(c, PEPS_ERR_HIP, "exchanged-configuration count out of range");
+    if (hcount > 0) {
+        st = run_all(c, lat, prec, A, Sx, hcount, false, 0, nullptr, lax, sgx, nullptr, nullptr, flx);
+        if (st != PEPS_OK) return st;
+    }
+    int8_t* fo = flags ? flags : fl;
+    e = launch_corr_values(S, pairs, P, N, (int)batch, la, sg, fl, slot, lax, sgx, flx, v, fo, c->stream);
+    if (e == hipSuccess && means) e = launch_corr_means(v, fo, P, (int)batch, means, c->stream);
+    if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
+    return PEPS_OK;
+}
+
+peps_status peps_structure_factor(peps_ctx* c, const peps_lattice* lat, int32_t nsites, const int32_t* sites,
+                                  const double* corr, int32_t nk, const double* k, double* out) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->err.clear();
+    peps_status st = check_batch_call(c, lat, 0);
+    if (st != PEPS_OK) return st;
+    if (nsites < 1 || nk < 0) return fail(c, PEPS_ERR_INVALID_ARG, "nsites < 1 or nk < 0");
+    if (nk == 0) return PEPS_OK;
+    if (!sites || !corr || !k || !out) return fail(c, PEPS_ERR_INVALID_ARG, "NULL argument");
+    const int N = lat->Lx * lat->Ly;
+    std::vector<int32_t> hs((size_t)nsites);
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipMemcpy(hs.data(), sites, hs.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, PEPS_ERR_HIP, "cannot read the site list");
+    for (int32_t x : hs)
+        if (x < 0 || x >= N) return fail(c, PEPS_ERR_INVALID_ARG, "site %d outside [0, %d)", x, N);
+    hipError_t e = launch_structure_factor(lat->Lx, nsites, sites, corr, nk, k, out, c->stream);
     if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
     return PEPS_OK;
 }

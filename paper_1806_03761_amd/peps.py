@@ -69,6 +69,9 @@ _SIGS = {
     "peps_metropolis_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                              _P, _P, _P, _P],
     "peps_go_update": [_P, ctypes.POINTER(_Lattice), _P, _P, _P, ctypes.c_double],
+    "peps_pair_correlations": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                               ctypes.c_int32, _P, _P, _P, _P],
+    "peps_structure_factor": [_P, ctypes.POINTER(_Lattice), ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P],
     "peps_vmc_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64, ctypes.c_int32,
                       _P, _P, ctypes.c_double, _P, _P],
 }
@@ -338,6 +341,52 @@ def vmc_step(A, S, lat, u, p, dt: float, prec: str = "f64", grad=None, return_gr
                            _ptr(u) if u.numel() else None, _ptr(p), float(dt), _ptr(energy), _ptr(grad))
     _check(lib, ctx, st, "peps_vmc_step")
     return energy, grad
+
+
+def pair_correlations(A, S, lat, pairs, prec: str = "f64", per_sample: bool = False):
+    """<S_m . S_n> for every (m, n) of `pairs` (peps_pair_correlations).  Returns
+    (means [P], per-sample values [B][P] or None, flags [B]) as device tensors."""
+    lib, ctx, A, S = _prep(A, S, lat)
+    dev = A.device
+    pr = torch.as_tensor(pairs, dtype=torch.int32).reshape(-1, 2).contiguous().to(dev)
+    B, P = S.shape[0], pr.shape[0]
+    means = torch.empty(P, dtype=torch.float64, device=dev)
+    vals = torch.empty((B, P), dtype=torch.float64, device=dev) if per_sample else None
+    fl = torch.empty(B, dtype=torch.int8, device=dev)
+    st = lib.peps_pair_correlations(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, P, _ptr(pr),
+                                    _ptr(means), _ptr(vals), _ptr(fl))
+    _check(lib, ctx, st, "peps_pair_correlations")
+    return means, vals, fl
+
+
+def structure_factor(corr, lat, sites, ks):
+    """m_s^2(k) for each k of `ks` over `sites` from their correlation matrix
+    (peps_structure_factor); corr is a float64 device tensor [n][n]."""
+    lib, ctx = _context(corr.device.index or 0)
+    sd = torch.as_tensor(sites, dtype=torch.int32).contiguous().to(corr.device)
+    kd = torch.as_tensor(ks, dtype=torch.float64).reshape(-1, 2).contiguous().to(corr.device)
+    n = sd.numel()
+    if corr.dtype != torch.float64 or tuple(corr.shape) != (n, n) or not corr.is_contiguous():
+        raise PepsError(f"corr must be a contiguous float64 tensor of shape {(n, n)}")
+    out = torch.empty(kd.shape[0], dtype=torch.float64, device=corr.device)
+    st = lib.peps_structure_factor(ctx, ctypes.byref(_lat(lat)), n, _ptr(sd), _ptr(corr), kd.shape[0], _ptr(kd),
+                                   _ptr(out))
+    _check(lib, ctx, st, "peps_structure_factor")
+    return out
+
+
+def correlation_matrix(A, S, lat, sites, prec: str = "f64"):
+    """<S_i . S_j> over `sites`: pair_correlations on the unordered pairs i <= j, placed
+    symmetrically into an [n][n] device tensor."""
+    n = len(sites)
+    iu = [(a, b) for a in range(n) for b in range(a, n)]
+    means, _, fl = pair_correlations(A, S, lat, [(sites[a], sites[b]) for a, b in iu], prec)
+    ia = torch.tensor([a for a, _ in iu], device=means.device)
+    ib = torch.tensor([b for _, b in iu], device=means.device)
+    C = torch.empty((n, n), dtype=torch.float64, device=means.device)
+    C[ia, ib] = means
+    C[ib, ia] = means
+    return C, fl
 
 
 def job_outputs(A, S, lat, grad_mode=3, want_eloc=True):
