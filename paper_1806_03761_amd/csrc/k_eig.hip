@@ -160,44 +160,56 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
     for (int k = 0; k + 2 < ns; ++k) {
         const int par = k & 1;
         const double tk = s_tau2[par];
+        // rows 0..k are final: v is zero there, so a wave whose rows all lie in that range
+        // adds exact zeros to p and to v.p, and the trailing matrix never reads the entries
+        // it would update; such a wave only publishes its zeros (the test is wave-uniform)
+        const bool fin = (wave + 1) * 4 * RB <= k + 1;
         if (tk != 0.0) {
             const double* vb = vbuf + par * W;
             double vr[RB], vc[RB], pr[RB];
+            if (!fin) {
 #pragma unroll
-            for (int u = 0; u < RB; ++u) vr[u] = vb[r0 + u];
+                for (int u = 0; u < RB; ++u) vr[u] = vb[r0 + u];
 #pragma unroll
-            for (int w = 0; w < RB; ++w) vc[w] = vb[c0 + w];
+                for (int w = 0; w < RB; ++w) vc[w] = vb[c0 + w];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                double acc = 0.0;
+                for (int u = 0; u < RB; ++u) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int w = 0; w < RB; ++w) acc = fma(A[u][w], vc[w], acc);
-                pr[u] = tk * e_wave_sum(acc, 16);
+                    for (int w = 0; w < RB; ++w) acc = fma(A[u][w], vc[w], acc);
+                    pr[u] = tk * e_wave_sum(acc, 16);
+                }
+                double pv = 0.0;
+#pragma unroll
+                for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
+                pv = add_xor16(pv);
+                pv = add_xor32(pv);
+                if (lane == 0) s_red[wave] = pv;
+            } else {
+#pragma unroll
+                for (int u = 0; u < RB; ++u) pr[u] = 0.0;
+                if (lane == 0) s_red[wave] = 0.0;
             }
-            double pv = 0.0;
-#pragma unroll
-            for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
-            pv = add_xor16(pv);
-            pv = add_xor32(pv);
-            if (lane == 0) s_red[wave] = pv;
             if (tj == 0)
 #pragma unroll
                 for (int u = 0; u < RB; ++u) pb[r0 + u] = pr[u];
             __syncthreads();
-            double pc[RB];
+            if (!fin) {
+                double pc[RB];
 #pragma unroll
-            for (int w = 0; w < RB; ++w) pc[w] = pb[c0 + w];
-            double sp = 0.0;
+                for (int w = 0; w < RB; ++w) pc[w] = pb[c0 + w];
+                double sp = 0.0;
 #pragma unroll
-            for (int i = 0; i < NT / 64; ++i) sp += s_red[i];
-            const double K = 0.5 * tk * sp;
+                for (int i = 0; i < NT / 64; ++i) sp += s_red[i];
+                const double K = 0.5 * tk * sp;
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const double wr = pr[u] - K * vr[u];
+                for (int u = 0; u < RB; ++u) {
+                    const double wr = pr[u] - K * vr[u];
 #pragma unroll
-                for (int w = 0; w < RB; ++w) {
-                    const double wc = pc[w] - K * vc[w];
-                    A[u][w] -= vr[u] * wc + wr * vc[w];
+                    for (int w = 0; w < RB; ++w) {
+                        const double wc = pc[w] - K * vc[w];
+                        A[u][w] -= vr[u] * wc + wr * vc[w];
+                    }
                 }
             }
         }
