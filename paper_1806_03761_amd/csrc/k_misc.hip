@@ -424,49 +424,102 @@ __device__ inline void mc_bond(int k, int Lx, int Ly, int* m, int* n) {
     }
 }
 
-// proposal S' = S with the spins of the drawn bond exchanged; moved = they differ
-__global__ void k_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
-                             int batch) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const int N = Lx * Ly, nb = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
-    const int8_t* s = S + (long long)b * N;
-    int8_t* sp = Sp + (long long)b * N;
-    for (int i = 0; i < N; ++i) sp[i] = s[i];
+// The drawn bond of chain b (u[2b] picks it) and whether its two spins differ.
+__device__ inline void mc_draw(const double* u, int b, int Lx, int Ly, int* m, int* n) {
+    const int nb = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
     const double kf = floor(u[2LL * b] * nb);
     const int k = kf < (double)(nb - 1) ? (int)kf : nb - 1;
+    mc_bond(k, Lx, Ly, m, n);
+}
+
+__global__ void k_mc_mark(const int8_t* S, const double* u, int Lx, int Ly, int batch, int8_t* moved) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
     int m, n;
-    mc_bond(k, Lx, Ly, &m, &n);
+    mc_draw(u, b, Lx, Ly, &m, &n);
+    const int8_t* s = S + (long long)b * Lx * Ly;
     moved[b] = s[m] != s[n];
+}
+
+// pos[b] = number of moved chains before b, count = all of them: one block of 1024
+// threads, each summing a contiguous run of chains, then a scan of the run totals in LDS
+// (deterministic: the proposals are packed in chain order).
+__global__ __launch_bounds__(1024) void k_mc_scan(const int8_t* moved, int batch, int* pos, int* count) {
+    __shared__ int run[1024];
+    const int t = threadIdx.x, per = (batch + 1023) / 1024;
+    const long long lo = (long long)t * per, hi = lo + per < batch ? lo + per : batch;
+    int c = 0;
+    for (long long b = lo; b < hi; ++b) c += moved[b];
+    run[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {      // inclusive Hillis-Steele scan
+        const int v = t >= off ? run[t - off] : 0;
+        __syncthreads();
+        run[t] += v;
+        __syncthreads();
+    }
+    int p = run[t] - c;
+    for (long long b = lo; b < hi; ++b) {
+        pos[b] = p;
+        p += moved[b];
+    }
+    if (t == 1023) *count = run[1023];
+}
+
+// the proposal of every moved chain at its packed position: S with the bond's spins
+// exchanged (S^z is kept)
+__global__ void k_mc_build(const int8_t* S, const double* u, const int8_t* moved, const int* pos, int Lx, int Ly,
+                           int batch, int8_t* Sp) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch || !moved[b]) return;
+    const int N = Lx * Ly;
+    int m, n;
+    mc_draw(u, b, Lx, Ly, &m, &n);
+    const int8_t* s = S + (long long)b * N;
+    int8_t* sp = Sp + (long long)pos[b] * N;
+    for (int i = 0; i < N; ++i) sp[i] = s[i];
     sp[m] = s[n];
     sp[n] = s[m];
 }
-hipError_t launch_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
-                             int batch, hipStream_t st) {
+
+hipError_t launch_mc_propose(const int8_t* S, const double* u, int Lx, int Ly, int batch, int8_t* moved, int* pos,
+                             int* count, int8_t* Sp, int* hcount, hipStream_t st) {
+    *hcount = 0;
     if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mc_propose, dim3((batch + 127) / 128), dim3(128), 0, st, S, Sp, moved, u, Lx, Ly, batch);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_mc_mark, dim3((batch + 127) / 128), dim3(128), 0, st, S, u, Lx, Ly, batch, moved);
+    hipLaunchKernelGGL(k_mc_scan, dim3(1), dim3(1024), 0, st, moved, batch, pos, count);
+    hipLaunchKernelGGL(k_mc_build, dim3((batch + 127) / 128), dim3(128), 0, st, S, u, moved, pos, Lx, Ly, batch,
+                       Sp);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hcount, count, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
 }
 
-// accept when u1 < W(S')^2 / W(S)^2 = exp(2 (ln|W(S')| - ln|W(S)|)) and S' has flag 0
-__global__ void k_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+// accept when the chain moved, its proposal has flag 0 and
+// u1 < W(S')^2 / W(S)^2 = exp(2 (ln|W(S')| - ln|W(S)|)); proposal data at the packed position
+__global__ void k_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const int* pos, const double* u,
                             const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
                             int8_t* sign, int8_t* accepted, int N, int batch) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    const bool acc = moved[b] && flp[b] == 0 && u[2LL * b + 1] < exp(2.0 * (lap[b] - log_abs[b]));
-    if (acc) {
-        for (int i = 0; i < N; ++i) S[(long long)b * N + i] = Sp[(long long)b * N + i];
-        log_abs[b] = lap[b];
-        sign[b] = sgp[b];
+    bool acc = false;
+    if (moved[b]) {
+        const int k = pos[b];
+        acc = flp[k] == 0 && u[2LL * b + 1] < exp(2.0 * (lap[k] - log_abs[b]));
+        if (acc) {
+            for (int i = 0; i < N; ++i) S[(long long)b * N + i] = Sp[(long long)k * N + i];
+            log_abs[b] = lap[k];
+            sign[b] = sgp[k];
+        }
     }
     if (accepted) accepted[b] = acc ? 1 : 0;
 }
-hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const int* pos, const double* u,
                             const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
                             int8_t* sign, int8_t* accepted, int N, int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mc_accept, dim3((batch + 127) / 128), dim3(128), 0, st, S, Sp, moved, u, lap, sgp,
+    hipLaunchKernelGGL(k_mc_accept, dim3((batch + 127) / 128), dim3(128), 0, st, S, Sp, moved, pos, u, lap, sgp,
                        flp, log_abs, sign, accepted, N, batch);
     return hipGetLastError();
 }

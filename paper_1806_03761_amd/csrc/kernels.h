@@ -124,9 +124,11 @@ hipError_t launch_grad_reduce(const double* Dall, const int8_t* S, int N, int D4
                               const double* w, int accumulate, double* out1, double* out0, double* ws,
                               int batch, hipStream_t st);
 // Metropolis step (see k_misc.hip): proposal and acceptance kernels, one thread per sample
-hipError_t launch_mc_propose(const int8_t* S, int8_t* Sp, int8_t* moved, const double* u, int Lx, int Ly,
-                             int batch, hipStream_t st);
-hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const double* u,
+// Metropolis proposals of the moved chains packed in chain order (moved, pos per chain;
+// the number of moved chains is returned in *hcount, which synchronises the stream).
+hipError_t launch_mc_propose(const int8_t* S, const double* u, int Lx, int Ly, int batch, int8_t* moved, int* pos,
+                             int* count, int8_t* Sp, int* hcount, hipStream_t st);
+hipError_t launch_mc_accept(int8_t* S, const int8_t* Sp, const int8_t* moved, const int* pos, const double* u,
                             const double* lap, const int8_t* sgp, const int8_t* flp, double* log_abs,
                             int8_t* sign, int8_t* accepted, int N, int batch, hipStream_t st);
 hipError_t launch_energy_mean(const double* acc, double* out, hipStream_t st);

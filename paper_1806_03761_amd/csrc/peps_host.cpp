@@ -1349,12 +1349,12 @@ peps_status peps_log_derivative(peps_ctx* c, const peps_lattice* lat, peps_preci
 }  // extern "C"
 
 // Buffers of the sampling and optimisation entry points, carved from one per-context
-// allocation that grows on demand: proposals S' [batch][N] with ln|W(S')|, sign, flag and
-// moved [batch]; the chains' ln|W|, sign, E(S), flags [batch]; the energy sums; the
-// gradient [N][2][D^4].
+// allocation that grows on demand: the packed proposals S' [batch][N] with ln|W(S')|,
+// sign and flag; moved and packed position per chain; the chains' ln|W|, sign, E(S),
+// flags [batch]; the energy sums; the gradient [N][2][D^4]; the moved-chain count.
 struct McBuffers {
     int8_t* Sp; double* lap; int8_t* sgp; int8_t* flp; int8_t* moved;
-    double* la; int8_t* sg; double* e; int8_t* fl; double* acc; double* grad;
+    double* la; int8_t* sg; double* e; int8_t* fl; double* acc; double* grad; int* pos; int* count;
 };
 
 // Grows a per-context device buffer to at least `need` bytes (contents not kept).
@@ -1378,9 +1378,9 @@ static peps_status grow_buffer(peps_ctx* c, char** buf, size_t* bytes, size_t ne
 static peps_status mc_buffers(peps_ctx* c, int64_t batch, int N, long long ngrad, McBuffers* m) {
     auto up = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t B = (size_t)batch;
-    size_t off[11], need = 0;
-    const size_t sz[11] = {B * N, B * 8, B, B, B, B * 8, B, B * 8, B, 16, (size_t)ngrad * 8};
-    for (int k = 0; k < 11; ++k) {
+    size_t off[13], need = 0;
+    const size_t sz[13] = {B * N, B * 8, B, B, B, B * 8, B, B * 8, B, 16, (size_t)ngrad * 8, B * 4, 4};
+    for (int k = 0; k < 13; ++k) {
         off[k] = need;
         need += up(sz[k]);
     }
@@ -1392,22 +1392,31 @@ static peps_status mc_buffers(peps_ctx* c, int64_t batch, int N, long long ngrad
                    reinterpret_cast<int8_t*>(b + off[4]), reinterpret_cast<double*>(b + off[5]),
                    reinterpret_cast<int8_t*>(b + off[6]), reinterpret_cast<double*>(b + off[7]),
                    reinterpret_cast<int8_t*>(b + off[8]), reinterpret_cast<double*>(b + off[9]),
-                   reinterpret_cast<double*>(b + off[10])};
+                   reinterpret_cast<double*>(b + off[10]), reinterpret_cast<int*>(b + off[11]),
+                   reinterpret_cast<int*>(b + off[12])};
     return PEPS_OK;
 }
 
 // One Metropolis step of every chain on validated arguments: propose, contract W(S'),
-// accept (Sec. II-B steps 1-3).
+// accept (Sec. II-B steps 1-3).  Only the chains whose drawn bond holds two different
+// spins have a proposal to contract; those are packed in chain order first (each
+// sample's contraction is independent of the others in the batch, so packing changes no
+// result).
 static peps_status mc_step(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
                            int8_t* S, int64_t batch, const double* u, double* log_abs, int8_t* sign,
                            int8_t* accepted, const McBuffers& m) {
     const int N = lat->Lx * lat->Ly;
-    hipError_t e = launch_mc_propose(S, m.Sp, m.moved, u, lat->Lx, lat->Ly, (int)batch, c->stream);
+    int nmoved = 0;
+    hipError_t e = launch_mc_propose(S, u, lat->Lx, lat->Ly, (int)batch, m.moved, m.pos, m.count, m.Sp, &nmoved,
+                                     c->stream);
     if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
-    peps_status st = run_all(c, lat, prec, A, m.Sp, batch, false, 0, nullptr, m.lap, m.sgp, nullptr, nullptr,
-                             m.flp);
-    if (st != PEPS_OK) return st;
-    e = launch_mc_accept(S, m.Sp, m.moved, u, m.lap, m.sgp, m.flp, log_abs, sign, accepted, N, (int)batch,
+    if (nmoved < 0 || nmoved > batch) return fail(c, PEPS_ERR_HIP, "moved-chain count out of range");
+    if (nmoved > 0) {
+        peps_status st = run_all(c, lat, prec, A, m.Sp, nmoved, false, 0, nullptr, m.lap, m.sgp, nullptr, nullptr,
+                                 m.flp);
+        if (st != PEPS_OK) return st;
+    }
+    e = launch_mc_accept(S, m.Sp, m.moved, m.pos, u, m.lap, m.sgp, m.flp, log_abs, sign, accepted, N, (int)batch,
                          c->stream);
     if (e != hipSuccess) return fail(c, PEPS_ERR_HIP, "HIP error: %s", hipGetErrorString(e));
     return PEPS_OK;
