@@ -137,8 +137,10 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
  *   peps_log_amplitude), updated with the moves.
  * u: device float64 [batch][2], uniform in [0, 1), drawn by the caller.
  * accepted: device int8 [batch] or NULL; 1 where the chain moved, else 0.
- * Work is enqueued on the context's stream; the context keeps its sampling buffers
- * (about batch * (N + 35) bytes) between calls. */
+ * Only the chains whose bond holds two different spins are contracted; their number is
+ * read back to the host to size that contraction, so the call synchronises the
+ * context's stream once.  The context keeps its sampling buffers (about
+ * batch * (N + 35) bytes) between calls. */
 peps_status peps_metropolis_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
                                  const double* A, int8_t* S, int64_t batch, const double* u,
                                  double* log_abs, int8_t* sign, int8_t* accepted);
@@ -166,7 +168,8 @@ peps_status peps_go_update(peps_ctx* ctx, const peps_lattice* lat, double* A, co
  * energy: device float64 [2] or NULL: {sampled E, number of samples with flag 0} (E is
  * NaN when there is none).  grad: device float64 [Ly*Lx][2][D^4] or NULL: dE/dA before the
  * update (the context keeps its own copy when NULL).
- * batch must be at least 1.  Work is enqueued on the context's stream; the context keeps
+ * batch must be at least 1.  Work is enqueued on the context's stream, which each
+ * Metropolis step synchronises once (see peps_metropolis_step); the context keeps
  * its sampling buffers (about batch * (N + 35) bytes, plus the gradient when grad is
  * NULL) between calls. */
 peps_status peps_vmc_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec, double* A,
