@@ -98,15 +98,17 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
 // Entries beyond k+1 of v_k are stored in row k of Am for the back-transformation.
 // Two barriers per step; v and tau are double-buffered so the next pivot can run
 // while other waves still finish their update.
-template <int RB>
+// G x G threads (G = 16: four waves; G = 8: one wave holding 8x8 blocks, whose row
+// sums then take three lane stages instead of four and need no barrier between waves).
+template <int RB, int G = 16>
 __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double* tau, double* vbuf, int ns, int lda) {
-    constexpr int W = 16 * RB;
+    constexpr int W = G * RB, NW = G * G / 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int ti = wave * 4 + (lane >> 4), tj = lane & 15;
+    const int ti = tid / G, tj = tid % G;
     const int r0 = ti * RB, c0 = tj * RB;
     double* pb = vbuf + 2 * W;
     __shared__ double s_tau2[2];
-    __shared__ double s_red[NT / 64];
+    __shared__ double s_red[NW];
     double A[RB][RB];
 #pragma unroll
     for (int u = 0; u < RB; ++u)
@@ -115,15 +117,14 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
             A[u][w] = (r0 + u < ns && c0 + w < ns) ? Am[(long long)(c0 + w) * lda + r0 + u] : 0.0;
     __syncthreads();   // Am rows are overwritten by reflectors below
     auto pivot = [&](int kp) {
-        const int ku = kp - r0;
+        // the same for every active lane (the row group holding row kp)
+        const int ku = __builtin_amdgcn_readfirstlane(kp - r0);
         double rv[RB];
 #pragma unroll
-        for (int w = 0; w < RB; ++w) {
-            rv[w] = A[0][w];
+        for (int u = 0; u < RB; ++u)
+            if (u == ku)   // a uniform branch: one row of registers copied
 #pragma unroll
-            for (int u = 1; u < RB; ++u)
-                if (u == ku) rv[w] = A[u][w];
-        }
+                for (int w = 0; w < RB; ++w) rv[w] = A[u][w];
         double sq = 0.0, al = 0.0;
 #pragma unroll
         for (int w = 0; w < RB; ++w) {
@@ -131,8 +132,8 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
             if (j >= kp + 2) sq = fma(rv[w], rv[w], sq);
             if (j == kp + 1) al = rv[w];
         }
-        sq = e_wave_sum(sq, 16);
-        al = e_wave_sum(al, 16);
+        sq = e_wave_sum(sq, G);
+        al = e_wave_sum(al, G);
         double tk, be, sc;
         if (sq == 0.0) {
             tk = 0.0; be = al; sc = 0.0;
@@ -163,7 +164,7 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
         // rows 0..k are final: v is zero there, so a wave whose rows all lie in that range
         // adds exact zeros to p and to v.p, and the trailing matrix never reads the entries
         // it would update; such a wave only publishes its zeros (the test is wave-uniform)
-        const bool fin = (wave + 1) * 4 * RB <= k + 1;
+        const bool fin = (wave + 1) * (64 / G) * RB <= k + 1;
         if (tk != 0.0) {
             const double* vb = vbuf + par * W;
             double vr[RB], vc[RB], pr[RB];
@@ -177,11 +178,12 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
                     double acc = 0.0;
 #pragma unroll
                     for (int w = 0; w < RB; ++w) acc = fma(A[u][w], vc[w], acc);
-                    pr[u] = tk * e_wave_sum(acc, 16);
+                    pr[u] = tk * e_wave_sum(acc, G);
                 }
                 double pv = 0.0;
 #pragma unroll
                 for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
+                if (G == 8) pv += dpp_perm<0x140>(pv);   // the other row group of the 16 lanes
                 pv = add_xor16(pv);
                 pv = add_xor32(pv);
                 if (lane == 0) s_red[wave] = pv;
@@ -200,7 +202,7 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
                 for (int w = 0; w < RB; ++w) pc[w] = pb[c0 + w];
                 double sp = 0.0;
 #pragma unroll
-                for (int i = 0; i < NT / 64; ++i) sp += s_red[i];
+                for (int i = 0; i < NW; ++i) sp += s_red[i];
                 const double K = 0.5 * tk * sp;
 #pragma unroll
                 for (int u = 0; u < RB; ++u) {
@@ -392,13 +394,13 @@ __global__ __launch_bounds__(NT) void k_eig_applyq(EigArgs a, int kc) {
 }
 
 // Householder tridiagonalisation of the Gram matrix formed by k_eig_applyq (order
-// <= 16 RB), A in registers; reflectors, d, e and tau go straight to the scratch slots.
-template <int RB>
-__global__ __launch_bounds__(NT) void k_eig_tridiag(EigArgs a) {
-    __shared__ __align__(16) double vbuf[48 * RB];
+// <= G RB), A in registers; reflectors, d, e and tau go straight to the scratch slots.
+template <int RB, int G = 16>
+__global__ __launch_bounds__(G * G) void k_eig_tridiag(EigArgs a) {
+    __shared__ __align__(16) double vbuf[3 * G * RB];
     const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
     double* gs = a.scratch + (long long)blockIdx.x * a.ss;
-    tri_reg<RB>(gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, vbuf, L.ns, L.lda);
+    tri_reg<RB, G>(gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, vbuf, L.ns, L.lda);
 }
 
 // launch k_eig_applyq for the first lane-group width (16, 32, 64) whose register
@@ -1099,7 +1101,7 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     switch (a.gram_ready ? -rb : tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
         case -1: hipLaunchKernelGGL((k_eig_tridiag<1>), dim3(batch), dim3(NT), 0, st, a); break;
         case -2: hipLaunchKernelGGL((k_eig_tridiag<2>), dim3(batch), dim3(NT), 0, st, a); break;
-        case -4: hipLaunchKernelGGL((k_eig_tridiag<4>), dim3(batch), dim3(NT), 0, st, a); break;
+        case -4: hipLaunchKernelGGL((k_eig_tridiag<8, 8>), dim3(batch), dim3(64), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_eig_prep<false, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
         case 3: hipLaunchKernelGGL((k_eig_prep<true, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
         case 4: hipLaunchKernelGGL((k_eig_prep<false, 2>), dim3(batch), dim3(NT), bpl, st, a); break;
