@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "34c96d78b7bd952d",
-           "bytes_per_launch": {"svd": 524864157, "qr": 460517031, "gemm": 143312591, "fused": 102274913}}
+TRAFFIC = {"sources": "49e708c9e3b30e32",
+           "bytes_per_launch": {"svd": 600033636, "qr": 460519873, "gemm": 143312589, "fused": 102273226}}
 
 
 def _sources_hash() -> str:

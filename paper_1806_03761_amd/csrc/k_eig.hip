@@ -1099,8 +1099,8 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const bool in_lds_prep = bp <= cap;
     const size_t bpl = in_lds_prep ? bp : 0;
     switch (a.gram_ready ? -rb : tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
-        case -1: hipLaunchKernelGGL((k_eig_tridiag<1>), dim3(batch), dim3(NT), 0, st, a); break;
-        case -2: hipLaunchKernelGGL((k_eig_tridiag<2>), dim3(batch), dim3(NT), 0, st, a); break;
+        case -1: hipLaunchKernelGGL((k_eig_tridiag<2, 8>), dim3(batch), dim3(64), 0, st, a); break;
+        case -2: hipLaunchKernelGGL((k_eig_tridiag<4, 8>), dim3(batch), dim3(64), 0, st, a); break;
         case -4: hipLaunchKernelGGL((k_eig_tridiag<8, 8>), dim3(batch), dim3(64), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_eig_prep<false, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
         case 3: hipLaunchKernelGGL((k_eig_prep<true, 1>), dim3(batch), dim3(NT), bpl, st, a); break;
