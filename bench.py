@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "49e708c9e3b30e32",
-           "bytes_per_launch": {"svd": 600033636, "qr": 460519873, "gemm": 143312589, "fused": 102273226}}
+TRAFFIC = {"sources": "34ba7cc40675b0e1",
+           "bytes_per_launch": {"svd": 599024094, "qr": 460531398, "gemm": 143312891, "fused": 102274659}}
 
 
 def _sources_hash() -> str:

@@ -1115,7 +1115,10 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     if (e != hipSuccess) return e;
     if (L.tk > NT) return hipErrorInvalidValue;   // one lane per kept value, at most NT per matrix
     const int tkk = L.tk > 0 ? L.tk : 1;
-    const int S = 4 * tkk <= 64 ? 4 : (2 * tkk <= 64 ? 2 : 1);   // multisection sub-lanes
+    // multisection sub-lanes: two points per eigenvalue and step (measured against one, four
+    // and eight: the bisection is issue-bound, and fewer points cost fewer Sturm sweeps in
+    // all while keeping the chain of steps short)
+    const int S = 2 * tkk <= 64 ? 2 : 1;
     const int lpm = tkk * S;
     const int mpb = 64 / lpm > 0 ? 64 / lpm : 1;
     size_t tri_bytes = (size_t)3 * mpb * L.ns * sizeof(double);
