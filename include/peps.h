@@ -9,15 +9,22 @@
  *   - the local energy E(S) of Eq. (4) for the J1-J2 Heisenberg model of
  *     Sec. III-A (Eq. (9)), from cached upper and lower environments;
  *   - the log-derivatives Delta = B/W of Eqs. (6)-(7), per sample or contracted
- *     with per-sample weights (the Monte Carlo gradient of Eq. (5)).
+ *     with per-sample weights (the Monte Carlo gradient of Eq. (5));
+ *   - around that path: a Metropolis step of many Markov chains sampling W(S)^2
+ *     (Sec. II-B, steps 1-3), the gradient-optimisation update of the tensors and one
+ *     iteration of the optimisation loop (Sec. II-A, II-B), and the spin-spin
+ *     correlations and structure factor of Sec. III-B.
  *
  * Conventions shared by every entry point
  *   A      device, float64, [Ly*Lx][2][D][D][D][D] = [site][phys][l][u][r][d],
  *          C order, site m = i*Lx + j (row i from the top, column j from the
  *          left).  Legs that point out of the open lattice (l at j = 0, u at
  *          i = 0, r at j = Lx-1, d at i = Ly-1) are read at index 0 only; the
- *          other entries of those legs are never read.  Read-only.
+ *          other entries of those legs are never read.  Read-only, except for
+ *          peps_go_update and peps_vmc_step, which update it in place.
  *   S      device, int8, [batch][Ly*Lx], values {0, 1}; 0 = spin up (S^z=+1/2).
+ *          Read-only, except for the chains of peps_metropolis_step and
+ *          peps_vmc_step, which move in place.
  *   batch  number of configurations (>= 0; 0 is a no-op that returns PEPS_OK).
  *   flags  optional device int8 [batch] (may be NULL): 0 ok, 1 configuration
  *          value outside {0,1}, 2 zero amplitude, 3 non-finite result.
