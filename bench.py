@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "34ba7cc40675b0e1",
-           "bytes_per_launch": {"svd": 599024094, "qr": 460531398, "gemm": 143312891, "fused": 102274659}}
+TRAFFIC = {"sources": "df1523226ad8d258",
+           "bytes_per_launch": {"svd": 598978006, "qr": 460527012, "gemm": 143312724, "fused": 102273371}}
 
 
 def _sources_hash() -> str:

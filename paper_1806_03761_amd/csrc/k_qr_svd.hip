@@ -758,6 +758,10 @@ static size_t lds_cap() { return get_lds_cap(); }
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
+    // column groups of 16 lanes in 256-thread blocks up to 128 rows (four-stage lane sums),
+    // 32 lanes in 512-thread blocks above: the faster of the launch shapes measured at
+    // each height
+    if (m <= 128 && launch_qr_cols(X, xs, m, n, R, rs, tau, ts, batch, 16, 256, st)) return hipGetLastError();
     if (launch_qr_cols(X, xs, m, n, R, rs, tau, ts, batch, 32, 512, st)) return hipGetLastError();
     if (n <= 64) {
         if (launch_qr_reg_wg<256>(X, xs, m, n, R, rs, tau, ts, batch, st) ||
