@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "df1523226ad8d258",
-           "bytes_per_launch": {"svd": 598978006, "qr": 460527012, "gemm": 143312724, "fused": 102273371}}
+TRAFFIC = {"sources": "70d62337e23412f8",
+           "bytes_per_launch": {"svd": 603985494, "qr": 460517370, "gemm": 143312860, "fused": 102273865}}
 
 
 def _sources_hash() -> str:
