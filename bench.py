@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "70d62337e23412f8",
-           "bytes_per_launch": {"svd": 603985494, "qr": 460517370, "gemm": 143312860, "fused": 102273865}}
+TRAFFIC = {"sources": "f8c47db57b7140ec",
+           "bytes_per_launch": {"svd": 590595745, "qr": 460531694, "gemm": 143312830, "fused": 102274513}}
 
 
 def _sources_hash() -> str:

@@ -75,10 +75,11 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
     L.total = L.oM;
     // LDS needs of the two workgroup kernels
     L.lds_prep = (long long)L.ldz * tin + (long long)L.lda * L.ns + 3LL * L.ns + L.nv + 8;
-    // k_eig_fin stages X, the reflectors, tau and the eigenvalues; Z stays in global scratch
-    // (read only by the output products, from L2): about 43 KB of LDS per block instead of
-    // 76 KB at the bulk shape
-    L.lds_fin = (long long)L.ldx * L.tk + (long long)L.lda * L.ns + L.ns + L.tk + 8;
+    // k_eig_fin stages X, tau and the eigenvalues; the reflectors and Z stay in global
+    // scratch, where they are L2-resident (the reflectors are read by every vector group
+    // alike, Z only by the output products): about 9 KB of LDS per block instead of 76 KB
+    // at the bulk shape, so more blocks share a CU
+    L.lds_fin = (long long)L.ldx * L.tk + L.ns + L.tk + 8;
     return L;
 }
 
@@ -928,12 +929,11 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
     double *X, *Am, *tau, *Z, *lam;
     if constexpr (kLds) {
         X = lds;
-        Am = X + (long long)ldx * tk;
-        tau = Am + (long long)lda * ns;
+        Am = gs + L.oA;
+        tau = X + (long long)ldx * tk;
         Z = gs + L.oZ;
         lam = tau + ns;
         copy_strided(X, gs + L.oX, (long long)ldx * tk, tid, NT);
-        copy_strided(Am, gs + L.oA, (long long)lda * ns, tid, NT);
         copy_strided(tau, gs + L.oT, ns, tid, NT);
         copy_strided(lam, gs + L.oL, tk, tid, NT);
         __syncthreads();
