@@ -60,8 +60,8 @@ def cpu_baseline(name: str, per_core: int = 96):
 # (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
 # 256 MiB device copy (command and figures in profiles/); valid only for the kernel
 # sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "f8c47db57b7140ec",
-           "bytes_per_launch": {"svd": 590595745, "qr": 460531694, "gemm": 143312830, "fused": 102274513}}
+TRAFFIC = {"sources": "f8afcdcd88d66ed4",
+           "bytes_per_launch": {"svd": 640246418, "qr": 460538203, "gemm": 143312682, "fused": 102274218}}
 
 
 def _sources_hash() -> str:

@@ -727,18 +727,22 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
     }
     if (sub != 0 || l >= tk) return;
     const double lam = 0.5 * (lo + hi);
-    // the lane's iterate and pivots: in LDS after the d/e block when they fit, element i of
-    // every vector lane side by side (stride mats_per_block * tk); else in global scratch
+    // the lane's iterate: in LDS after the d/e block when it fits, element i of every
+    // vector lane side by side (stride mats_per_block * tk), its pivots then side by side in
+    // global scratch (stride tk: coalesced, and half the LDS, so more blocks share a CU);
+    // else both in global scratch, one row per lane
     const int vl = mi * tk + l, nvl = mats_per_block * tk;
     double* x;
     double* piv;
-    int xs;
+    int xs, ps;
     if (tri_lanes_in_lds) {
         xs = nvl;
         x = tri_lds + 3LL * mats_per_block * n + vl;
-        piv = x + (long long)n * nvl;
+        piv = gs + L.oP + l;
+        ps = tk;
     } else {
         xs = 1;
+        ps = 1;
         x = gs + L.oX + (long long)l * L.ldx;
         piv = gs + L.oP + (long long)l * L.ldx;
     }
@@ -763,13 +767,13 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
             q = d[i] - lam - e2[i - 1] * pp;
             if (fabs(q) < ptol) q = (q < 0.0) ? -ptol : ptol;
             pp = sturm_rcp(q);
-            piv[i * xs] = pp;
+            piv[i * ps] = pp;
         }
         double xn = x[(n - 1) * xs] * pp;
         x[(n - 1) * xs] = xn;
         double mx = fabs(xn);
         for (int i = n - 2; i >= 0; --i) {
-            xn = (x[i * xs] - e[i] * xn) * piv[i * xs];
+            xn = (x[i * xs] - e[i] * xn) * piv[i * ps];
             x[i * xs] = xn;
             mx = fmax(mx, fabs(xn));
         }
@@ -1124,7 +1128,7 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const int lpm = tkk * S;
     const int mpb = 64 / lpm > 0 ? 64 / lpm : 1;
     size_t tri_bytes = (size_t)3 * mpb * L.ns * sizeof(double);
-    const size_t lane_bytes = (size_t)mpb * tkk * 2 * L.ns * sizeof(double);
+    const size_t lane_bytes = (size_t)mpb * tkk * L.ns * sizeof(double);   // the iterates
     const int in_lds = tri_bytes + lane_bytes <= cap ? 1 : 0;
     if (in_lds) tri_bytes += lane_bytes;
     hipLaunchKernelGGL(k_eig_tri, dim3((unsigned)((batch + mpb - 1) / mpb)), dim3(mpb * lpm), tri_bytes, st,
