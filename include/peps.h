@@ -13,7 +13,7 @@
  *   - around that path: a Metropolis step of many Markov chains sampling W(S)^2
  *     (Sec. II-B, steps 1-3), the gradient-optimisation update of the tensors and one
  *     iteration of the optimisation loop (Sec. II-A, II-B), and the spin-spin
- *     correlations and structure factor of Sec. III-B.
+ *     correlations and structure factor of Sec. III-A.
  *
  * Conventions shared by every entry point
  *   A      device, float64, [Ly*Lx][2][D][D][D][D] = [site][phys][l][u][r][d],
@@ -183,7 +183,7 @@ peps_status peps_vmc_step(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           int8_t* S, int64_t batch, int32_t n_mc, const double* u, const double* p,
                           double dt, double* energy, double* grad);
 
-/* Spin-spin correlations <S_m . S_n> by Monte Carlo (Sec. III-B): for every sample and
+/* Spin-spin correlations <S_m . S_n> by Monte Carlo (Sec. III-A): for every sample and
  * pair, the local value sigma_m sigma_n / 4 plus, where the two spins differ, half the
  * ratio W(S')/W(S) of the configuration with them exchanged (both contracted in full, as
  * in peps_log_amplitude); 3/4 when m == n.  A zero W(S') gives a zero ratio; a sample
@@ -201,7 +201,7 @@ peps_status peps_pair_correlations(peps_ctx* ctx, const peps_lattice* lat, peps_
                                    const int32_t* pairs, double* means, double* per_sample,
                                    int8_t* flags);
 
-/* Structure factor of Sec. III-B over a block of nsites sites:
+/* Structure factor of Sec. III-A over a block of nsites sites:
  * out[q] = (1/nsites^2) sum_{i,j} corr[i][j] cos(k_q . (r_i - r_j)), r = (column, row) of
  * the site, which is the real part of the Fourier sum for a real correlation matrix
  * (M^2 = out at k = (pi, pi) with the central (L-4) x (L-4) block).

@@ -17,7 +17,7 @@ What it computes, per spin configuration S (paper Sec. II-A):
     Step B: sample, estimate, update), with the random step factors passed in;
   * spin-spin correlations <S_m . S_m'> (local value sigma sigma / 4 plus half the
     ratio W(S')/W(S) of the exchanged configuration, contracted in full) and the
-    structure factor m_s^2(k) over a block of sites (Sec. III-B).
+    structure factor m_s^2(k) over a block of sites (Sec. III-A).
 Everything is IEEE float64.  numpy's QR and SVD (LAPACK) are used as library
 steps; contractions are written as einsum calls, one per tensor pair.
 
@@ -517,7 +517,7 @@ def vmc_step(A, lat, S, u, p, dt):
 
 
 # --------------------------------------------------------------------------
-# Spin-spin correlations (Sec. III-B: <S_m . S_m'> and the structure factor m_s^2(k))
+# Spin-spin correlations (Sec. III-A: <S_m . S_m'> and the structure factor m_s^2(k))
 # --------------------------------------------------------------------------
 def pair_correlation_one(A, lat, S, m, n, la=None, sg=None):
     """Local value of S_m . S_n at configuration S: sigma_m sigma_n / 4, plus 1/2 W(S')/W(S)

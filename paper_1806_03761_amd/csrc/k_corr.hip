@@ -1,4 +1,4 @@
-// Spin-spin correlation estimator (Sec. III-B): local value of S_m . S_n at a sampled
+// Spin-spin correlation estimator (Sec. III-A): local value of S_m . S_n at a sampled
 // configuration, sigma_m sigma_n / 4 plus half the ratio W(S')/W(S) of the configuration
 // S' with the two spins exchanged (only where they differ), and the structure factor
 // m_s^2(k) of a block of sites.

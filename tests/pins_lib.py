@@ -6,6 +6,8 @@ formulation that reaches the same numbers by another route.
     (Eq. (1) at fixed S) with no MPS and no truncation;
   * dense_psi_truncated: the truncated boundary contraction done on the dense
     boundary vector, projecting every cut onto its leading Schmidt vectors;
+  * dense_env_down / dense_env_up / dense_local_energy: the truncated upper and lower
+    environments as dense vectors, and the local energy from dense sandwiches of them;
   * full_wavefunction: all 2^N amplitudes of a small PEPS at once;
   * heisenberg_j1j2: the sparse J1-J2 Hamiltonian (Sec. III-A) built from bit
     operations, for brute-force local energies and exact diagonalisation.
@@ -98,6 +100,81 @@ def dense_env_down(A, lat, S, i_stop):
         psi = psi / nu
         logscale += math.log(nu)
     return psi, logscale
+
+
+def _push_row_up(phi, A, lat, S, i):
+    """phi over the d-legs of row i (shape (Dd,)*Lx) -> vector over its u-legs: the row
+    is read with u and d exchanged, so the same left-to-right pass applies."""
+    Lx = lat.Lx
+    X = phi.reshape(1, -1, 1)
+    rem = [phi.shape[j] for j in range(Lx)]
+    done = []
+    for j in range(Lx):
+        T = _T(A, lat, i, j, int(S[i * Lx + j])).transpose(0, 3, 2, 1)   # [l, d, r, u]
+        Pd = X.shape[0]
+        R = int(np.prod(rem[j + 1:])) if j + 1 < Lx else 1
+        X4 = X.reshape(Pd, rem[j], R, X.shape[2])
+        Y = np.einsum("pdRh,hdru->puRr", X4, T)
+        done.append(T.shape[3])
+        X = Y.reshape(Pd * T.shape[3], R, T.shape[2])
+    return X.reshape(done)
+
+
+def dense_env_up(A, lat, S, i_stop):
+    """Dense truncated lower environment of row i_stop (state over its d-legs), with log:
+    rows Ly-1 .. i_stop+1 pushed upwards, each followed by the same cut projection as
+    the downward sweep (last cut first) and a normalisation."""
+    phi = np.ones([1] * lat.Lx)
+    logscale = 0.0
+    for i in range(lat.Ly - 1, i_stop, -1):
+        phi = _push_row_up(phi, A, lat, S, i)
+        phi = _project_cuts(phi, lat.Dc)
+        nu = np.linalg.norm(phi)
+        phi = phi / nu
+        logscale += math.log(nu)
+    return phi, logscale
+
+
+def dense_two_row_sandwich(Udense, A, lat, S, i, Ldense):
+    """<U| rows i, i+1 |L> with U over the u-legs of row i and L over the d-legs of row i+1."""
+    out = _push_row(_push_row(Udense, A, lat, S, i), A, lat, S, i + 1)
+    return float(np.sum(out * Ldense))
+
+
+def dense_local_energy(A, lat, S, ratio_source="sandwich"):
+    """E(S) of Eq. (4) with every exchange ratio from dense sandwiches of the dense
+    truncated environments: <U_i|row i|L_i> for a bond inside row i, <U_i|rows i,
+    i+1|L_{i+1}> for a bond between rows i and i+1 (numerator and denominator from the
+    same sandwich).  ratio_source="full" takes every ratio from the top-down truncated
+    contraction of the whole lattice instead (a different reading, used only to show
+    that the two readings differ when cuts are truncated)."""
+    Lx, Ly = lat.Lx, lat.Ly
+    S = np.asarray(S)
+    sig = 1 - 2 * S.astype(np.int64)
+    Ud = [dense_env_down(A, lat, S, i)[0] for i in range(Ly)]
+    Ld = [dense_env_up(A, lat, S, i)[0] for i in range(Ly)]
+    nn, nnn = lattice_bonds(Lx, Ly)
+    E = 0.0
+    for bonds, J in ((nn, lat.J1), (nnn, lat.J2)):
+        for m, n in bonds:
+            E += J * sig[m] * sig[n] / 4.0
+            if S[m] == S[n]:
+                continue
+            Sp = S.copy()
+            Sp[m], Sp[n] = S[n], S[m]
+            i = min(m, n) // Lx
+            if ratio_source == "full":
+                s1, l1 = dense_psi_truncated(A, lat, Sp)
+                s0, l0 = dense_psi_truncated(A, lat, S)
+                rho = s1 * s0 * math.exp(l1 - l0)
+            elif m // Lx == n // Lx:
+                rho = (dense_row_sandwich(Ud[i], A, lat, Sp, i, Ld[i]) /
+                       dense_row_sandwich(Ud[i], A, lat, S, i, Ld[i]))
+            else:
+                rho = (dense_two_row_sandwich(Ud[i], A, lat, Sp, i, Ld[i + 1]) /
+                       dense_two_row_sandwich(Ud[i], A, lat, S, i, Ld[i + 1]))
+            E += J * 0.5 * rho
+    return E
 
 
 def mps_to_dense(mps):

@@ -351,6 +351,57 @@ def test_envs_agree_in_exact_regime():
         assert s == sg and _rel(l + logU[i] + logL[i], la) < 1e-12
 
 
+# --- truncated regime: sandwiches and the local energy against dense environments -----
+TRUNC_E_LATS = [Lattice(6, 6, 2, 3), Lattice(5, 5, 3, 4), Lattice(8, 8, 2, 4)]
+
+
+@pytest.mark.parametrize("lat", TRUNC_E_LATS)
+def test_truncated_sandwiches_equal_dense_environments(lat):
+    """Cuts truncated (Dc < D^floor(Lx/2)): every single-row sandwich <U_i|row i|L_i> and
+    two-row sandwich <U_i|rows i,i+1|L_{i+1}> of the oracle (MPS environments, QR/SVD
+    sweeps, partials rescaled per column) equals the same sandwich of the dense
+    projected environments (Eq. (4) ratios; truncation of Fig. 1(c) done on the dense
+    boundary state), at S and at an exchanged configuration, in ln|.| and sign."""
+    A, S = make_random(lat, 2, 91)
+    for b in range(len(S)):
+        s0 = S[b]
+        U, L, logU, logL = O.boundary_envs(A, lat, s0)
+        Ud = [P.dense_env_down(A, lat, s0, i) for i in range(lat.Ly)]
+        Ld = [P.dense_env_up(A, lat, s0, i) for i in range(lat.Ly)]
+        # an exchanged configuration: first anti-parallel vertical pair of each row pair
+        for i in range(lat.Ly):
+            for Sx in (s0, np.roll(s0.reshape(lat.Ly, lat.Lx), 1, axis=1).reshape(-1)):
+                sg, l = O.row_sandwich(U[i], O.row_tensors(A, lat, Sx, i), L[i])
+                w = P.dense_row_sandwich(Ud[i][0], A, lat, Sx, i, Ld[i][0])
+                assert sg == np.sign(w)
+                assert _rel(l + logU[i] + logL[i], math.log(abs(w)) + Ud[i][1] + Ld[i][1]) < 1e-10
+            if i + 1 < lat.Ly:
+                Sx = s0.copy()
+                Sx[i * lat.Lx: (i + 2) * lat.Lx] = np.roll(s0[i * lat.Lx: (i + 2) * lat.Lx], lat.Lx)
+                for Sy in (s0, Sx):
+                    sg, l = O.two_row_sandwich(U[i], O.row_tensors(A, lat, Sy, i),
+                                               O.row_tensors(A, lat, Sy, i + 1), L[i + 1])
+                    w = P.dense_two_row_sandwich(Ud[i][0], A, lat, Sy, i, Ld[i + 1][0])
+                    assert sg == np.sign(w)
+                    assert _rel(l + logU[i] + logL[i + 1],
+                                math.log(abs(w)) + Ud[i][1] + Ld[i + 1][1]) < 1e-10
+
+
+@pytest.mark.parametrize("lat", TRUNC_E_LATS)
+def test_truncated_local_energy_equals_dense_sandwiches(lat):
+    """E(S) of Eq. (4) in the truncated regime equals the local energy whose exchange
+    ratios come from dense sandwiches of the dense projected environments, to 1e-10
+    relative; and the reading matters here: ratios from the whole truncated contraction
+    give a different E (so a ratio taken from the wrong sandwich fails this pin)."""
+    A, S = make_random(lat, 3, 93)
+    for b in range(len(S)):
+        e = O.local_energy_one(A, lat, S[b])
+        e_d = P.dense_local_energy(A, lat, S[b])
+        assert _rel(e, e_d) < 1e-10, (b, e, e_d)
+        e_full = P.dense_local_energy(A, lat, S[b], ratio_source="full")
+        assert abs(e - e_full) > 1e-6 * max(1.0, abs(e))
+
+
 # --- Metropolis sampling (Sec. II-B, steps 1-3 of the sampling loop) -----------------
 def _sz0_configs(N):
     S = P.configs_from_index(N)
@@ -516,7 +567,7 @@ def test_vmc_steps_lower_the_exact_energy():
 
 
 # --------------------------------------------------------------------------
-# Spin-spin correlations and the structure factor (Sec. III-B)
+# Spin-spin correlations and the structure factor (Sec. III-A)
 # --------------------------------------------------------------------------
 def test_pair_correlations_with_exact_weights_equal_dense_expectation():
     """Exact regime (4x2, D=2, Dc=4): the correlation estimator averaged over all 70
