@@ -41,6 +41,10 @@ struct GemmArgs {
     // storage type of each operand: 0 = float64, 1 = float32 (the pointer then addresses
     // floats and every offset above counts floats)
     int a_f32, b_f32, c_f32;
+    // optional per-sample predicate: sample b is skipped (C left untouched) when
+    // skip[b * skip_bs] == 0
+    const int8_t* skip = nullptr;
+    long long skip_bs = 0;
 };
 
 __host__ __device__ inline long long idx_off(const Idx2& x, int i) {

@@ -28,143 +28,6 @@ __device__ inline typename ArithT<AR>::In to_in(double x) {
     }
 }
 
-// WG of 256 threads as a 16x16 grid; each thread owns a (TM/16) x (TN/16) micro-tile.
-// Cooperative load of a TK x TW tile (rows of TW + 1 in LDS): entry (kk, ww) = src[off_w[ww] + off_k[kk]] (zero where
-// either offset is negative), threads striding over the TK * TW entries.  Every load
-// reads a valid address (entry 0 of the operand for padding) and all are issued before
-// the first conversion, so they overlap instead of each waiting on its own.
-template <int TK, int TW, Arith AR>
-__device__ __forceinline__ void tile_load(typename ArithT<AR>::In* dst, const long long* off_w,
-                                          const long long* off_k, int f32, const double* srcd,
-                                          const float* srcf, int tid) {
-    using In = typename ArithT<AR>::In;
-    constexpr int NE = TK * TW, NI = (NE + 255) / 256;
-    long long o[NI];
-    bool ok[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int e = tid + 256 * i;
-        const bool in = NE % 256 == 0 || e < NE;
-        const long long ow = in ? off_w[e % TW] : -1, ok_ = in ? off_k[e / TW] : -1;
-        ok[i] = ow >= 0 && ok_ >= 0;
-        o[i] = ok[i] ? ow + ok_ : 0;
-    }
-    In v[NI];
-    if (f32) {
-        float x[NI];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) x[i] = srcf[o[i]];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) v[i] = ok[i] ? to_in<AR>((double)x[i]) : In(0);
-    } else {
-        double x[NI];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) x[i] = srcd[o[i]];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) v[i] = ok[i] ? to_in<AR>(x[i]) : In(0);
-    }
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int e = tid + 256 * i;
-        if (NE % 256 == 0 || e < NE) dst[(e / TW) * (TW + 1) + e % TW] = v[i];   // rows padded by one
-    }
-}
-
-template <int TM, int TN, int TK, Arith AR>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int tiles_m, int tiles_n) {
-    using In = typename ArithT<AR>::In;
-    using Acc = typename ArithT<AR>::Acc;
-    constexpr int RM = TM / 16, RN = TN / 16;
-    __shared__ In As[TK][TM + 1];
-    __shared__ In Bs[TK][TN + 1];
-    __shared__ long long aoff_m[TM], boff_n[TN], coff_m[TM], coff_n[TN];
-    __shared__ long long aoff_k[TK], boff_k[TK];
-
-    const int tiles = tiles_m * tiles_n;
-    const long long blk = blockIdx.x;
-    const int b = (int)(blk / tiles);
-    const int t = (int)(blk % tiles);
-    const int m0 = (t / tiles_n) * TM;
-    const int n0 = (t % tiles_n) * TN;
-    const int tid = threadIdx.x;
-    if (b >= g.batch) return;
-
-    // element offsets of this batch entry (in the operand's own storage type)
-    const long long a0 = (long long)b * g.a_bs + gather_off(g.ga, b);
-    const long long b0 = (long long)b * g.b_bs + gather_off(g.gb, b);
-    const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
-    const double* Ab = g.A + a0;
-    const double* Bb = g.B + b0;
-    double* Cb = g.C + c0;
-    const float* Af = reinterpret_cast<const float*>(g.A) + a0;
-    const float* Bf = reinterpret_cast<const float*>(g.B) + b0;
-    float* Cf = reinterpret_cast<float*>(g.C) + c0;
-
-    for (int i = tid; i < TM; i += 256) {
-        int m = m0 + i;
-        aoff_m[i] = m < g.M ? idx_off(g.am, m) : -1;
-        coff_m[i] = m < g.M ? idx_off(g.cm, m) : -1;
-    }
-    for (int i = tid; i < TN; i += 256) {
-        int n = n0 + i;
-        boff_n[i] = n < g.N ? idx_off(g.bn, n) : -1;
-        coff_n[i] = n < g.N ? idx_off(g.cn, n) : -1;
-    }
-
-    Acc acc[RM][RN];
-#pragma unroll
-    for (int i = 0; i < RM; ++i)
-#pragma unroll
-        for (int j = 0; j < RN; ++j) acc[i][j] = Acc(0);
-
-    const int tx = tid % 16, ty = tid / 16;
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
-        __syncthreads();
-        for (int i = tid; i < TK; i += 256) {
-            int k = k0 + i;
-            aoff_k[i] = k < g.K ? idx_off(g.ak, k) : -1;
-            boff_k[i] = k < g.K ? idx_off(g.bk, k) : -1;
-        }
-        __syncthreads();
-        // A tile: TK x TM, consecutive threads walk m (operand layouts vary, so no
-        // single order is coalesced for all of them); B tile likewise.  All loads of a
-        // tile are issued before any is used.
-        tile_load<TK, TM, AR>(&As[0][0], aoff_m, aoff_k, g.a_f32, Ab, Af, tid);
-        tile_load<TK, TN, AR>(&Bs[0][0], boff_n, boff_k, g.b_f32, Bb, Bf, tid);
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < TK; ++kk) {
-            Acc av[RM], bv[RN];
-#pragma unroll
-            for (int i = 0; i < RM; ++i) av[i] = (Acc)As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < RN; ++j) bv[j] = (Acc)Bs[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < RM; ++i)
-#pragma unroll
-                for (int j = 0; j < RN; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < RM; ++i) {
-        long long om = coff_m[ty + 16 * i];
-        if (om < 0) continue;
-#pragma unroll
-        for (int j = 0; j < RN; ++j) {
-            long long on = coff_n[tx + 16 * j];
-            if (on < 0) continue;
-            double v = g.alpha * (double)acc[i][j];
-            if (g.c_f32) {
-                if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
-                Cf[om + on] = (float)v;
-            } else {
-                if (g.beta != 0.0) v += g.beta * Cb[om + on];
-                Cb[om + on] = v;
-            }
-        }
-    }
-}
-
 // Row kernel for skinny products (N <= 64, K <= kRowsMaxK): the TPR threads of a row own
 // CPT consecutive columns each and accumulate them in registers, reading the A row
 // straight from memory with KC loads in flight (k in order, as in the tiled kernel, so
@@ -313,54 +176,19 @@ static GemmArgs transposed(const GemmArgs& g) {
     return t;
 }
 
-template <int TM, int TN, int TK>
-static hipError_t launch_t(const GemmArgs& g, Arith ar, hipStream_t st) {
-    int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
-    long long blocks = (long long)tm * tn * g.batch;
-    if (blocks == 0) return hipSuccess;
-    dim3 grid((unsigned)blocks), block(256);
-    switch (ar) {
-        case Arith::F64: hipLaunchKernelGGL((k_gemm<TM, TN, TK, Arith::F64>), grid, block, 0, st, g, tm, tn); break;
-        case Arith::F32: hipLaunchKernelGGL((k_gemm<TM, TN, TK, Arith::F32>), grid, block, 0, st, g, tm, tn); break;
-        case Arith::BF16: hipLaunchKernelGGL((k_gemm<TM, TN, TK, Arith::BF16>), grid, block, 0, st, g, tm, tn); break;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    // 14: row kernel; 15: row kernel on the transposed product (each falls back to the
-    // heuristic tile when the shape does not fit it)
-    if (tile == 14 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
-    if (tile == 15) {
+    // 1..12: matrix-core tiles; 13: row kernel; 14: row kernel on the transposed product
+    // (each falls back to the heuristic tile when the shape does not fit it).  Every form
+    // sums the products of an output in ascending k with one rounding per product (a
+    // 16x16x4 MFMA adds its four products in k order, like a chain of fma), so all of
+    // them give the same results.
+    if (tile == 13 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
+    if (tile == 14) {
         const GemmArgs t = transposed(g);
         if (gemm_rows_fits(t)) return launch_gemm_rows(t, ar, st);
     }
-    if (tile >= 14) tile = 0;
-    if (tile <= 0 || tile > kGemmTiles) {
-        // heuristic: smallest tile that covers small problems
-        if (g.M <= 16 && g.N <= 16) tile = 1;
-        else if (g.M <= 32 && g.N <= 32) tile = 2;
-        else if (g.N <= 16) tile = 3;
-        else if (g.M <= 16) tile = 4;
-        else tile = 5;
-    }
-    switch (tile) {
-        case 1: return launch_t<16, 16, 16>(g, ar, st);
-        case 2: return launch_t<32, 32, 16>(g, ar, st);
-        case 3: return launch_t<64, 16, 16>(g, ar, st);
-        case 4: return launch_t<16, 64, 16>(g, ar, st);
-        case 5: return launch_t<64, 64, 16>(g, ar, st);
-        case 6: return launch_t<32, 16, 32>(g, ar, st);
-        case 7: return launch_t<16, 32, 32>(g, ar, st);
-        case 8: return launch_t<128, 16, 16>(g, ar, st);
-        case 9: return launch_t<256, 16, 16>(g, ar, st);
-        case 10: return launch_t<16, 128, 16>(g, ar, st);
-        case 11: return launch_t<16, 256, 16>(g, ar, st);
-        case 12: return launch_t<128, 32, 16>(g, ar, st);
-        case 13: return launch_t<32, 128, 16>(g, ar, st);
-        default: return launch_t<64, 64, 16>(g, ar, st);
-    }
+    return launch_mgemm(g, ar, st, tile >= 13 ? 0 : tile);
 }
 
 }  // namespace peps

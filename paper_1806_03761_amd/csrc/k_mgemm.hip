@@ -1,0 +1,255 @@
+// Batched strided multi-index GEMM on the matrix cores (the contraction primitive of
+// the boundary apply, the single- and two-row sandwich steps and the environment
+// tensors).
+//
+// C(b) = A(b) x B(b) with each of M, N, K a pair of tensor legs with its own strides
+// (no permutation is materialised), an optional spin-selected operand slice, and an
+// optional per-sample predicate that skips samples whose result is not needed.
+//
+// A workgroup of four waves computes a TM x TN tile; wave (wm, wn) owns BM x BN blocks
+// of 16 x 16, each accumulated by 16x16x4 MFMAs (float64: v_mfma_f64_16x16x4f64,
+// float32: v_mfma_f32_16x16x4f32).  Operand tiles of TK = 16 k values are staged through
+// LDS in the compute type; the next stage's global loads are issued before the current
+// stage's MFMAs so their latency overlaps.  Every output sums its products in ascending
+// k (MFMA s takes k = 4s..4s+3), with no split of K over waves, so all tile shapes give
+// bitwise-identical results and the autotuner may pick any of them.
+#include "common.h"
+#include "kernels.h"
+
+namespace peps {
+
+namespace {
+
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+template <Arith AR> struct MT;
+template <> struct MT<Arith::F64> { using In = double; using Acc = mf64x4; };
+template <> struct MT<Arith::F32> { using In = float; using Acc = mf32x4; };
+template <> struct MT<Arith::BF16> { using In = float; using Acc = mf32x4; };
+
+template <Arith AR>
+__device__ __forceinline__ typename MT<AR>::In to_mt(double x) {
+    if constexpr (AR == Arith::F64) {
+        return x;
+    } else if constexpr (AR == Arith::F32) {
+        return (float)x;
+    } else {
+        // operands rounded to bfloat16 (nearest-even); their products are exact in float32
+        return __bfloat162float(__float2bfloat16((float)x));
+    }
+}
+
+template <Arith AR>
+__device__ __forceinline__ typename MT<AR>::Acc mfma(typename MT<AR>::In a, typename MT<AR>::In b,
+                                                     typename MT<AR>::Acc c) {
+    if constexpr (AR == Arith::F64) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int TK = 16;
+
+// Per-thread share of one operand tile (TK x TW entries): NI loads.  Entry e of the tile
+// maps to (k, w) either w-fastest (consecutive threads walk the free index) or k-fastest,
+// whichever index has unit stride in memory, so the loads coalesce.
+template <int TW>
+struct TileLd {
+    static constexpr int NE = TK * TW, NI = (NE + 255) / 256;
+};
+
+template <int TW, Arith AR>
+__device__ __forceinline__ void tile_issue(double (&x)[TileLd<TW>::NI], float (&xf)[TileLd<TW>::NI],
+                                           bool (&ok)[TileLd<TW>::NI], const long long* off_w, const Idx2& kx,
+                                           int k0, int K, bool kfast, int f32, const double* srcd,
+                                           const float* srcf, int tid) {
+    constexpr int NE = TileLd<TW>::NE, NI = TileLd<TW>::NI;
+    long long o[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + 256 * i;
+        const bool in = NE % 256 == 0 || e < NE;
+        const int kk = kfast ? e % TK : e / TW, w = kfast ? e / TK : e % TW;
+        const int k = k0 + kk;
+        const long long ow = in ? off_w[w] : -1;
+        ok[i] = in && ow >= 0 && k < K;
+        o[i] = ok[i] ? ow + idx_off(kx, k) : 0;
+    }
+    if (f32) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) xf[i] = srcf[o[i]];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) x[i] = srcd[o[i]];
+    }
+}
+
+template <int TW, Arith AR>
+__device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const double (&x)[TileLd<TW>::NI],
+                                           const float (&xf)[TileLd<TW>::NI], const bool (&ok)[TileLd<TW>::NI],
+                                           bool kfast, int f32, int tid) {
+    using In = typename MT<AR>::In;
+    constexpr int NE = TileLd<TW>::NE, NI = TileLd<TW>::NI;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = tid + 256 * i;
+        if (NE % 256 != 0 && e >= NE) continue;
+        const int kk = kfast ? e % TK : e / TW, w = kfast ? e / TK : e % TW;
+        const In v = ok[i] ? to_mt<AR>(f32 ? (double)xf[i] : x[i]) : In(0);
+        dst[kk * (TW + 1) + w] = v;
+    }
+}
+
+template <int WM, int WN, int BM, int BN, Arith AR>
+__global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tiles_n) {
+    using In = typename MT<AR>::In;
+    using Acc = typename MT<AR>::Acc;
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    __shared__ In As[TK * (TM + 1)];
+    __shared__ In Bs[TK * (TN + 1)];
+    __shared__ long long aoff_m[TM], boff_n[TN], coff_m[TM], coff_n[TN];
+
+    const int tiles = tiles_m * tiles_n;
+    const long long blk = blockIdx.x;
+    const int b = (int)(blk / tiles);
+    const int t = (int)(blk % tiles);
+    const int m0 = (t / tiles_n) * TM;
+    const int n0 = (t % tiles_n) * TN;
+    const int tid = threadIdx.x;
+    if (b >= g.batch) return;
+    if (g.skip && g.skip[(long long)b * g.skip_bs] == 0) return;
+
+    const long long a0 = (long long)b * g.a_bs + gather_off(g.ga, b);
+    const long long b0 = (long long)b * g.b_bs + gather_off(g.gb, b);
+    const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
+    const double* Ab = g.A + a0;
+    const double* Bb = g.B + b0;
+    const float* Af = reinterpret_cast<const float*>(g.A) + a0;
+    const float* Bf = reinterpret_cast<const float*>(g.B) + b0;
+
+    for (int i = tid; i < TM; i += 256) {
+        const int m = m0 + i;
+        aoff_m[i] = m < g.M ? idx_off(g.am, m) : -1;
+        coff_m[i] = m < g.M ? idx_off(g.cm, m) : -1;
+    }
+    for (int i = tid; i < TN; i += 256) {
+        const int n = n0 + i;
+        boff_n[i] = n < g.N ? idx_off(g.bn, n) : -1;
+        coff_n[i] = n < g.N ? idx_off(g.cn, n) : -1;
+    }
+    // unit stride along k (and not along the free index): walk k fastest
+    const bool akf = g.ak.s_inner == 1 && !(g.am.s_inner == 1 && g.am.inner > 1);
+    const bool bkf = g.bk.s_inner == 1 && !(g.bn.s_inner == 1 && g.bn.inner > 1);
+    __syncthreads();
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w % WM, wn = w / WM;
+    const int li = lane & 15, gq = lane >> 4;
+    Acc acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+    double xa[TileLd<TM>::NI], xb[TileLd<TN>::NI];
+    float xaf[TileLd<TM>::NI], xbf[TileLd<TN>::NI];
+    bool oka[TileLd<TM>::NI], okb[TileLd<TN>::NI];
+    tile_issue<TM, AR>(xa, xaf, oka, aoff_m, g.ak, 0, g.K, akf, g.a_f32, Ab, Af, tid);
+    tile_issue<TN, AR>(xb, xbf, okb, boff_n, g.bk, 0, g.K, bkf, g.b_f32, Bb, Bf, tid);
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        __syncthreads();
+        tile_store<TM, AR>(As, xa, xaf, oka, akf, g.a_f32, tid);
+        tile_store<TN, AR>(Bs, xb, xbf, okb, bkf, g.b_f32, tid);
+        __syncthreads();
+        if (k0 + TK < g.K) {
+            tile_issue<TM, AR>(xa, xaf, oka, aoff_m, g.ak, k0 + TK, g.K, akf, g.a_f32, Ab, Af, tid);
+            tile_issue<TN, AR>(xb, xbf, okb, boff_n, g.bk, k0 + TK, g.K, bkf, g.b_f32, Bb, Bf, tid);
+        }
+#pragma unroll
+        for (int s = 0; s < TK / 4; ++s) {
+            In av[BM], bv[BN];
+#pragma unroll
+            for (int i = 0; i < BM; ++i) av[i] = As[(4 * s + gq) * (TM + 1) + (wm * BM + i) * 16 + li];
+#pragma unroll
+            for (int j = 0; j < BN; ++j) bv[j] = Bs[(4 * s + gq) * (TN + 1) + (wn * BN + j) * 16 + li];
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int j = 0; j < BN; ++j) acc[i][j] = mfma<AR>(av[i], bv[j], acc[i][j]);
+        }
+    }
+    // lane (li, gq) holds column li of each 16 x 16 block, rows 4 gq + r (float32 MFMA) or
+    // gq + 4 r (float64 MFMA)
+    double* Cd = g.C + c0;
+    float* Cf = reinterpret_cast<float*>(g.C) + c0;
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+            const long long on = coff_n[(wn * BN + j) * 16 + li];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = AR == Arith::F64 ? gq + 4 * r : 4 * gq + r;
+                const long long om = coff_m[(wm * BM + i) * 16 + row];
+                if (om < 0 || on < 0) continue;
+                double v = g.alpha * (double)acc[i][j][r];
+                if (g.c_f32) {
+                    if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
+                    Cf[om + on] = (float)v;
+                } else {
+                    if (g.beta != 0.0) v += g.beta * Cd[om + on];
+                    Cd[om + on] = v;
+                }
+            }
+        }
+}
+
+template <int WM, int WN, int BM, int BN>
+hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    const int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+    const long long blocks = (long long)tm * tn * g.batch;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (ar) {
+        case Arith::F64: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::F64>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::F32: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::F32>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::BF16: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::BF16>), grid, block, 0, st, g, tm, tn); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// tiles 1..kGemmTiles: (TM x TN) = 32x32, 64x16, 16x64, 64x64, 128x16, 16x128, 64x32, 32x64,
+// 128x64, 64x128, 128x32, 32x128
+hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (tile <= 0 || tile > kGemmTiles) {
+        // heuristic: the smallest tile that covers small products, else 64 x 64
+        if (g.M <= 32 && g.N <= 32) tile = 1;
+        else if (g.N <= 16) tile = g.M >= 128 ? 5 : 2;
+        else if (g.M <= 16) tile = g.N >= 128 ? 6 : 3;
+        else if (g.N <= 32) tile = 7;
+        else if (g.M <= 32) tile = 8;
+        else tile = 4;
+    }
+    switch (tile) {
+        case 1: return launch_m<2, 2, 1, 1>(g, ar, st);
+        case 2: return launch_m<4, 1, 1, 1>(g, ar, st);
+        case 3: return launch_m<1, 4, 1, 1>(g, ar, st);
+        case 4: return launch_m<2, 2, 2, 2>(g, ar, st);
+        case 5: return launch_m<4, 1, 2, 1>(g, ar, st);
+        case 6: return launch_m<1, 4, 1, 2>(g, ar, st);
+        case 7: return launch_m<2, 2, 2, 1>(g, ar, st);
+        case 8: return launch_m<2, 2, 1, 2>(g, ar, st);
+        case 9: return launch_m<2, 2, 4, 2>(g, ar, st);
+        case 10: return launch_m<2, 2, 2, 4>(g, ar, st);
+        case 11: return launch_m<4, 1, 2, 2>(g, ar, st);
+        default: return launch_m<1, 4, 2, 2>(g, ar, st);
+    }
+}
+
+}  // namespace peps

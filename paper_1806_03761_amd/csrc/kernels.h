@@ -5,13 +5,16 @@
 
 namespace peps {
 
-// tile: 0 = heuristic choice, 1..kGemmTiles = a fixed tile shape (see k_gemm.hip)
-static constexpr int kGemmTiles = 15;
+// tile: 0 = heuristic choice, 1..12 = a matrix-core tile shape (k_mgemm.hip), 13/14 = the
+// row kernel (k_gemm.hip) on the product or its transpose
+static constexpr int kGemmTiles = 14;
 // row kernel for skinny products: N <= 64 and K <= 64 (gemm_rows_fits); same results as
 // launch_gemm
 bool gemm_rows_fits(const GemmArgs& g);
 hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
+// matrix-core GEMM (k_mgemm.hip): tile 1..12, 0 = heuristic
+hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();
 
 // column-group QR with TPC lanes per column group in WG-thread workgroups; false when the

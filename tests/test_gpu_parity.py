@@ -425,3 +425,53 @@ def _fused_forms_equal_plain(p, lat, A, S):
                 assert np.array_equal(x, y), (env, name, int((d > 0).sum()), d.size, float(d.max()))
     finally:
         p.profile_enable(())
+
+
+@pytest.mark.parametrize("grad_mode", [2, 3])
+def test_gradient_reduction_several_partitions(grad_mode):
+    """Eq. (5) sums over a batch of 300 samples, which the library splits into several
+    fixed partitions summed in order (the partitioned path the benchmark runs): the
+    weighted sum (grad_mode 2) and dE/dA (grad_mode 3) equal the oracle's at 1e-10."""
+    lat, A, S, _ = make_workload("4x4_D2_Dc4", 256)
+    A2, S2 = make_random(lat, 44, 77, "half")
+    S = np.concatenate([S, S2])
+    Ad, Sd = _dev(A, S)
+    per = O.log_derivative(A, lat, S)
+    if grad_mode == 2:
+        w = np.random.default_rng(5).standard_normal(len(S))
+        g, _, _, _ = _peps().log_derivative(Ad, Sd, lat, "f64", weights=torch.from_numpy(w).cuda())
+        (g,) = _np(g)
+        ref = np.einsum("b,bnse->nse", w, per)
+    else:
+        _, _, e, g, fl = _np(*_peps().evaluate(Ad, Sd, lat, "f64", grad_mode=3))
+        assert np.all(fl == 0)
+        _, _, e_o, _ = O.local_energy(A, lat, S)
+        Bn = len(S)
+        ref = 2.0 * np.einsum("b,bnse->nse", e_o, per) / Bn - 2.0 * (per.sum(0) / Bn) * e_o.mean()
+    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    _say("gradient reduction over %d samples, grad_mode %d: rel l2 err %.2e" % (len(S), grad_mode, err))
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_graded_boundary_spectra_f64(eps):
+    """Decaying boundary spectra (the regime of trained states): a random product state
+    embedded at D = 4 and gauge-dressed, plus eps times a Gaussian, so the boundary
+    singular values fall off by about eps per order.  Log-amplitude, local energy and
+    log-derivatives match the oracle at the f64 bounds."""
+    import pins_lib as P
+    lat = Lattice(8, 8, 4, 16)
+    rng = np.random.default_rng(13)
+    a = rng.uniform(0.5, 1.5, size=(lat.N, 2)) * rng.choice([-1, 1], size=(lat.N, 2))
+    A = P.gauge_dress(P.product_peps(lat, a, rng, 0.0), lat, rng, horizontal=True, vertical="orthogonal")
+    A = A + eps * rng.standard_normal(A.shape)
+    _, S = make_random(lat, 4, 29)
+    la, sg, e, d, fl = _np(*_peps().evaluate(*_dev(A, S), lat, "f64", grad_mode=1))
+    for b in range(len(S)):
+        la_o, sg_o, e_o, d_o, fl_o = O.full_path_one(A, lat, S[b])
+        assert fl[b] == 0 and fl_o == 0 and sg[b] == sg_o
+        el = abs(la[b] - la_o) / max(1, abs(la_o))
+        ee = abs(e[b] - e_o) / max(1, abs(e_o))
+        eg = np.linalg.norm(d[b] - d_o) / np.linalg.norm(d_o)
+        _say("graded eps=%g sample %d: log-amp %.2e E_loc %.2e grad %.2e" % (eps, b, el, ee, eg))
+        assert el <= TOL_AMP["f64"] and ee <= TOL_E["f64"] and eg <= TOL_G["f64"]

@@ -402,6 +402,30 @@ def test_truncated_local_energy_equals_dense_sandwiches(lat):
         assert abs(e - e_full) > 1e-6 * max(1.0, abs(e))
 
 
+def _graded_peps(lat, eps, seed):
+    """Gauge-dressed random product state plus eps * Gaussian: boundary singular values
+    that fall off by about eps per order (the decaying spectra of trained states)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.5, 1.5, size=(lat.N, 2)) * rng.choice([-1, 1], size=(lat.N, 2))
+    A = P.gauge_dress(P.product_peps(lat, a, rng, 0.0), lat, rng, horizontal=True,
+                      vertical="orthogonal")
+    return A + eps * rng.standard_normal(A.shape)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_graded_spectra_dense_projection(eps):
+    """Decaying boundary spectra: the amplitude equals the dense projection and the local
+    energy equals the dense-sandwich local energy (1e-10 relative)."""
+    lat = Lattice(6, 6, 3, 4)
+    A = _graded_peps(lat, eps, 14)
+    _, S = make_random(lat, 2, 31)
+    la, sg, e, _ = O.local_energy(A, lat, S)
+    for b in range(len(S)):
+        s, l = P.dense_psi_truncated(A, lat, S[b])
+        assert sg[b] == s and _rel(la[b], l) < 1e-10
+        assert _rel(e[b], P.dense_local_energy(A, lat, S[b])) < 1e-10
+
+
 # --- Metropolis sampling (Sec. II-B, steps 1-3 of the sampling loop) -----------------
 def _sz0_configs(N):
     S = P.configs_from_index(N)
