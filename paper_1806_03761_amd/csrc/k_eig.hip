@@ -1080,7 +1080,7 @@ size_t eig_scratch_doubles(int mz, int tin, int p, int Dc) {
 hipError_t launch_eig(const double* V, long long vs, const double* tau, long long ts, const double* G,
                       long long gs, int mz, int r, int tin, int p, int Dc, double* newU, long long us,
                       double* Gout, long long gos, double* scratch, long long ss, int batch,
-                      hipStream_t st) {
+                      hipStream_t st, const double* wyT, long long wys) {
     if (batch <= 0) return hipSuccess;
     EigArgs a;
     a.V = V; a.vs = vs; a.tau = tau; a.ts = ts; a.G = G; a.gs = gs;
@@ -1095,7 +1095,16 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const int rb = tri_rb(L.ns);
     const size_t zbytes = (size_t)L.ldz * tin * sizeof(double);
     a.gram_ready = (rb > 0 && zbytes <= cap / 4) ? 1 : 0;
-    a.z_ready = launch_applyq(a, cap / 4, zbytes, st) ? 1 : 0;
+    if (wyT && V && r > 0) {
+        // reflectors of the blocked QR: Z = Q [G; 0] by its WY blocks on the matrix cores
+        a.gram_ready = 0;
+        hipError_t ez = launch_applyq_blocked(V, vs, mz, r, wyT, wys, G, gs, r, tin, scratch + L.oZ, ss, L.ldz,
+                                              batch, st);
+        if (ez != hipSuccess) return ez;
+        a.z_ready = 1;
+    } else {
+        a.z_ready = launch_applyq(a, cap / 4, zbytes, st) ? 1 : 0;
+    }
     if (!a.z_ready) a.gram_ready = 0;
     if (a.z_ready) {
         hipError_t e0 = hipGetLastError();

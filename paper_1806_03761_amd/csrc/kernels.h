@@ -52,10 +52,26 @@ struct EigArgs {
     int gram_ready;   // set by the launcher: the Gram matrix already in the scratch Am slot
 };
 size_t eig_scratch_doubles(int mz, int tin, int p, int Dc);
+// wyT != nullptr: the reflectors came from the blocked QR, whose WY blocks (wyT, stride wys
+// per matrix) apply Q to [G; 0] on the matrix cores
 hipError_t launch_eig(const double* V, long long vs, const double* tau, long long ts, const double* G,
                       long long gs, int mz, int r, int tin, int p, int Dc, double* newU, long long us,
                       double* Gout, long long gos, double* scratch, long long ss, int batch,
-                      hipStream_t st);
+                      hipStream_t st, const double* wyT = nullptr, long long wys = 0);
+
+// blocked Householder QR (k_qrb.hip) for matrices beyond the register kernels: panels of
+// qrb_panel_width(m) columns factorised in registers, trailing updates in compact WY form
+// on the matrix cores.  Same reflector convention and outputs as launch_qr, plus the WY
+// T blocks (qrb_wy_doubles(m, n) doubles per matrix, stride tws).
+int qrb_panel_width(int m);
+long long qrb_wy_doubles(int m, int n);
+bool qrb_fits(int m, int n);
+hipError_t launch_qr_blocked(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
+                             long long ts, double* Tw, long long tws, int batch, hipStream_t st);
+// Z (column-major, ld ldz, stride zs per matrix) = Q [G; 0], Q from launch_qr_blocked
+hipError_t launch_applyq_blocked(const double* V, long long vs, int mz, int nrefl, const double* Tw,
+                                 long long tws, const double* G, long long gs, int rin, int tin, double* Z,
+                                 long long zs, int ldz, int batch, hipStream_t st);
 
 // misc
 // fused two-row sandwich step (float32, legs <= 4, boundary bonds <= 16; see k_pair.hip)

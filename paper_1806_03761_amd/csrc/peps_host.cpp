@@ -184,13 +184,15 @@ public:
             o_logL[i] = (need_L || i == Ly - 1) ? L.alloc(1) : 0;
         }
         // truncation buffers (max over every truncation of the plan)
-        s_X.assign(Lx, 1); s_tau.assign(Lx, 1);
+        s_X.assign(Lx, 1); s_tau.assign(Lx, 1); s_wy.assign(Lx, 0);
         s_R = 1; s_Y = 1; s_G = 1; s_svd = 0;
         auto visit = [&](const Trunc& t) {
             for (int j = 0; j < Lx; ++j) {
                 const long long rows = (long long)t.rho[j] * t.p, cols = t.K[j + 1];
                 s_X[j] = std::max(s_X[j], rows * cols);
                 s_tau[j] = std::max<long long>(s_tau[j], std::min(rows, cols));
+                if (j + 1 < Lx && use_qrb((int)rows, (int)cols))
+                    s_wy[j] = std::max(s_wy[j], qrb_wy_doubles((int)rows, (int)cols));
                 if (j + 1 < Lx) s_R = std::max(s_R, (long long)t.rho[j + 1] * t.K[j + 1]);
                 s_Y = std::max(s_Y, (long long)t.rho[j] * Dh[j] * t.pin * t.chi[j + 1]);
                 s_G = std::max(s_G, (long long)t.rho[j] * t.tau[j]);
@@ -205,10 +207,11 @@ public:
         for (int i = 0; i + 1 < Ly; ++i) visit(tU[i]);
         if (need_L)
             for (int i = Ly - 1; i >= 1; --i) visit(tL[i]);
-        o_X.resize(Lx); o_tau.resize(Lx);
+        o_X.resize(Lx); o_tau.resize(Lx); o_wy.assign(Lx, 0);
         for (int j = 0; j < Lx; ++j) {
             o_X[j] = L.alloc(s_X[j]);
             o_tau[j] = L.alloc(s_tau[j]);
+            if (s_wy[j] > 0) o_wy[j] = L.alloc(s_wy[j]);
         }
         o_R[0] = L.alloc(s_R); o_R[1] = L.alloc(s_R);
         o_Y = L.alloc(s_Y);
@@ -439,7 +442,15 @@ public:
                     bounds_msg = "internal bounds check failed in qr";
                     return hipErrorInvalidValue;
                 }
+                const bool blocked = use_qrb((int)rows, t.K[j + 1]);
+                if (blocked && qrb_wy_doubles((int)rows, t.K[j + 1]) > s_wy[j]) {
+                    bounds_msg = "internal bounds check failed in blocked qr";
+                    return hipErrorInvalidValue;
+                }
                 KL(timed(PEPS_KC_QR, Bcur * qr_flops((double)rows, t.K[j + 1]), [&] {
+                    if (blocked)
+                        return launch_qr_blocked(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
+                                                 buf(o_tau[j]), s_tau[j], buf(o_wy[j]), s_wy[j], Bcur, st_);
                     return launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
                                      buf(o_tau[j]), s_tau[j], Bcur, st_);
                 }));
@@ -485,10 +496,12 @@ public:
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
             KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, t.rho[j + 1], t.tau[j + 1], p, t.tau[j]), [&] {
+                const bool blocked = use_qrb(mz, t.K[j + 1]);
                 if (use_eig)
                     return launch_eig(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
                                       t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs,
-                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, st_);
+                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, st_,
+                                      blocked ? buf(o_wy[j]) : nullptr, s_wy[j]);
                 return launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
                                   t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]),
                                   s_G, buf(o_svd), s_svd, flags(), Bcur, st_);
@@ -874,7 +887,10 @@ public:
     const int8_t* Scur = nullptr;
     std::vector<size_t> o_envU, o_envL, o_logU, o_logL, o_X, o_tau, o_P, o_Q, o_lP, o_lQ, o_P2, o_Q2,
         o_lP2, o_lQ2;
-    std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2;
+    std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2, s_wy;
+    std::vector<size_t> o_wy;
+    // the blocked QR (matrix-core WY updates) for matrices beyond the register kernels
+    static bool use_qrb(int rows, int cols) { return (rows > 512 || cols > 128) && qrb_fits(rows, cols); }
     size_t o_site32 = 0;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0, o_gws;

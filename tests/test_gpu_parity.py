@@ -475,3 +475,23 @@ def test_graded_boundary_spectra_f64(eps):
         eg = np.linalg.norm(d[b] - d_o) / np.linalg.norm(d_o)
         _say("graded eps=%g sample %d: log-amp %.2e E_loc %.2e grad %.2e" % (eps, b, el, ee, eg))
         assert el <= TOL_AMP["f64"] and ee <= TOL_E["f64"] and eg <= TOL_G["f64"]
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 6, 36), (6, 3, 8, 64)])
+def test_blocked_qr_shapes_full_path(shape):
+    """Column matrices of up to 1296 x 216 (D = 6, Dc = 36) and 4096 x 512 (D = 8, Dc = 64),
+    the bulk shapes of the 16x16 and 24x24 lattices, take the blocked QR (register panels,
+    matrix-core WY updates) and the WY application of Q: amplitude, local energy and
+    log-derivatives equal the oracle at the f64 bounds."""
+    Lx, Ly, D, Dc = shape
+    lat = Lattice(Lx, Ly, D, Dc)
+    A, S = make_random(lat, 3, 40 + D)
+    la, sg, e, d, fl = _np(*_peps().evaluate(*_dev(A, S), lat, "f64", grad_mode=1))
+    for b in range(len(S)):
+        la_o, sg_o, e_o, d_o, fl_o = O.full_path_one(A, lat, S[b])
+        assert fl[b] == 0 and fl_o == 0 and sg[b] == sg_o
+        el = abs(la[b] - la_o) / max(1, abs(la_o))
+        ee = abs(e[b] - e_o) / max(1, abs(e_o))
+        eg = np.linalg.norm(d[b] - d_o) / np.linalg.norm(d_o)
+        _say("blocked-QR shape %s sample %d: log-amp %.2e E_loc %.2e grad %.2e" % (shape, b, el, ee, eg))
+        assert el <= TOL_AMP["f64"] and ee <= TOL_E["f64"] and eg <= TOL_G["f64"]
