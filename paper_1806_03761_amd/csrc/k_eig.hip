@@ -72,7 +72,9 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
     L.oW = L.oP + (long long)L.ldx * L.tk;
     L.nm = 0;
     L.oM = L.oW + L.nv;
-    L.total = L.oM;
+    L.oY = L.oM;                                   // refinement: Y (mp x tk) and W (np x tk)
+    L.oV = L.oY + (long long)L.mp * L.tk;
+    L.total = L.oV + (long long)L.np * L.tk;
     // LDS needs of the two workgroup kernels
     L.lds_prep = (long long)L.ldz * tin + (long long)L.lda * L.ns + 3LL * L.ns + L.nv + 8;
     // k_eig_fin stages X, tau and the eigenvalues; the reflectors and Z stay in global
@@ -187,8 +189,9 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
                 double pv = 0.0;
 #pragma unroll
                 for (int u = 0; u < RB; ++u) pv = fma(pr[u], vr[u], pv);
+                // one value per row group of G lanes: sum over the row groups of the wave
                 if (G == 8) pv += dpp_perm<0x140>(pv);   // the other row group of the 16 lanes
-                pv = add_xor16(pv);
+                if (G <= 16) pv = add_xor16(pv);
                 pv = add_xor32(pv);
                 if (lane == 0) s_red[wave] = pv;
             } else {
@@ -226,6 +229,146 @@ __device__ __forceinline__ void tri_reg(double* Am, double* d, double* e, double
     for (int u = 0; u < RB; ++u)
 #pragma unroll
         for (int w = 0; w < RB; ++w) {
+            const int i = r0 + u, j = c0 + w;
+            if (i == j && i < ns) d[i] = A[u][w];
+            if (i == ns - 2 && j == ns - 1) e[ns - 2] = A[u][w];
+        }
+    if (tid == 0) {
+        if (ns >= 2) tau[ns - 2] = 0.0;
+        if (ns >= 1) tau[ns - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// The same reduction for orders up to GR RBR = GC RBC (224 with the 32 x 16 grid of 7 x 14
+// blocks below), where a square grid would not fit the register file: thread (ti, tj) of
+// the GR x GC grid (tj fastest, so a row group is GC lanes of one wave) owns rows ti RBR ..
+// and columns tj RBC ..; the column entries of v and p are read from LDS inside the loops
+// instead of being held in registers.  Same steps, outputs and reflector storage as tri_reg.
+template <int RBR, int RBC, int GR, int GC>
+__device__ __forceinline__ void tri_reg_rect(double* Am, double* d, double* e, double* tau, double* vbuf, int ns,
+                                             int lda) {
+    constexpr int W = GR * RBR, NW = GR * GC / 64;
+    static_assert(GR * RBR == GC * RBC, "square coverage");
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ti = tid / GC, tj = tid % GC;
+    const int r0 = ti * RBR, c0 = tj * RBC;
+    double* pb = vbuf + 2 * W;
+    __shared__ double s_tau2[2];
+    __shared__ double s_red[NW];
+    double A[RBR][RBC];
+#pragma unroll
+    for (int u = 0; u < RBR; ++u)
+#pragma unroll
+        for (int w = 0; w < RBC; ++w)
+            A[u][w] = (r0 + u < ns && c0 + w < ns) ? Am[(long long)(c0 + w) * lda + r0 + u] : 0.0;
+    __syncthreads();   // Am rows are overwritten by reflectors below
+    auto pivot = [&](int kp) {
+        const int ku = __builtin_amdgcn_readfirstlane(kp - r0);
+        double sq = 0.0, al = 0.0;
+#pragma unroll
+        for (int u = 0; u < RBR; ++u)
+            if (u == ku) {
+#pragma unroll
+                for (int w = 0; w < RBC; ++w) {
+                    const int j = c0 + w;
+                    if (j >= kp + 2) sq = fma(A[u][w], A[u][w], sq);
+                    if (j == kp + 1) al = A[u][w];
+                }
+            }
+        sq = e_wave_sum(sq, GC);
+        al = e_wave_sum(al, GC);
+        double tk, be, sc;
+        if (sq == 0.0) {
+            tk = 0.0; be = al; sc = 0.0;
+        } else {
+            be = -copysign(sqrt(al * al + sq), al);
+            tk = (be - al) / be;
+            sc = 1.0 / (al - be);
+        }
+        double* vb = vbuf + (kp & 1) * W;
+#pragma unroll
+        for (int u = 0; u < RBR; ++u)
+            if (u == ku) {
+#pragma unroll
+                for (int w = 0; w < RBC; ++w) {
+                    const int j = c0 + w;
+                    const double v = (j >= kp + 2) ? sc * A[u][w] : (j == kp + 1 ? 1.0 : 0.0);
+                    vb[j] = v;
+                    if (tk != 0.0 && j >= kp + 2 && j < ns) Am[(long long)kp * lda + j] = v;
+                }
+            }
+        if (tj == 0) {
+            s_tau2[kp & 1] = tk;
+            tau[kp] = tk;
+            e[kp] = be;
+        }
+    };
+    if (ns > 2 && ti == 0) pivot(0);
+    __syncthreads();
+    for (int k = 0; k + 2 < ns; ++k) {
+        const int par = k & 1;
+        const double tk = s_tau2[par];
+        const bool fin = (wave + 1) * (64 / GC) * RBR <= k + 1;
+        if (tk != 0.0) {
+            const double* vb = vbuf + par * W;
+            double vr[RBR], pr[RBR];
+            if (!fin) {
+#pragma unroll
+                for (int u = 0; u < RBR; ++u) {
+                    vr[u] = vb[r0 + u];
+                    pr[u] = 0.0;
+                }
+#pragma unroll
+                for (int w = 0; w < RBC; ++w) {
+                    const double vc = vb[c0 + w];
+#pragma unroll
+                    for (int u = 0; u < RBR; ++u) pr[u] = fma(A[u][w], vc, pr[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < RBR; ++u) pr[u] = tk * e_wave_sum(pr[u], GC);
+                double pv = 0.0;
+#pragma unroll
+                for (int u = 0; u < RBR; ++u) pv = fma(pr[u], vr[u], pv);
+                // one value per row group of GC lanes: sum over the row groups of the wave
+                if (GC <= 16) pv = add_xor16(pv);
+                pv = add_xor32(pv);
+                if (lane == 0) s_red[wave] = pv;
+            } else {
+#pragma unroll
+                for (int u = 0; u < RBR; ++u) {
+                    pr[u] = 0.0;
+                    vr[u] = 0.0;
+                }
+                if (lane == 0) s_red[wave] = 0.0;
+            }
+            if (tj == 0)
+#pragma unroll
+                for (int u = 0; u < RBR; ++u) pb[r0 + u] = pr[u];
+            __syncthreads();
+            if (!fin) {
+                double sp = 0.0;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) sp += s_red[i];
+                const double K = 0.5 * tk * sp;
+                // A -= v w^T + w v^T with w = p - K v, written as v (p - 2 K v)^T + p v^T on
+                // the block so that no w is held in registers
+#pragma unroll
+                for (int w = 0; w < RBC; ++w) {
+                    const double vc = vb[c0 + w];
+                    const double yc = pb[c0 + w] - 2.0 * K * vc;
+#pragma unroll
+                    for (int u = 0; u < RBR; ++u) A[u][w] -= vr[u] * yc + pr[u] * vc;
+                }
+            }
+        }
+        if (k + 3 < ns && ti == (k + 1) / RBR) pivot(k + 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < RBR; ++u)
+#pragma unroll
+        for (int w = 0; w < RBC; ++w) {
             const int i = r0 + u, j = c0 + w;
             if (i == j && i < ns) d[i] = A[u][w];
             if (i == ns - 2 && j == ns - 1) e[ns - 2] = A[u][w];
@@ -405,6 +548,15 @@ __global__ __launch_bounds__(G * G) void k_eig_tridiag(EigArgs a) {
     const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
     double* gs = a.scratch + (long long)blockIdx.x * a.ss;
     tri_reg<RB, G>(gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, vbuf, L.ns, L.lda);
+}
+
+// tridiagonalisation of a Gram matrix of order <= 224 already in the Am slot (formed on
+// the matrix cores by launch_eig), 512 threads
+__global__ __launch_bounds__(512) void k_eig_tridiag_big(EigArgs a) {
+    __shared__ __align__(16) double vbuf[3 * 224];
+    const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
+    double* gs = a.scratch + (long long)blockIdx.x * a.ss;
+    tri_reg_rect<7, 14, 32, 16>(gs + L.oA, gs + L.oD, gs + L.oE, gs + L.oT, vbuf, L.ns, L.lda);
 }
 
 // launch k_eig_applyq for the first lane-group width (16, 32, 64) whose register
@@ -695,7 +847,9 @@ __global__ __launch_bounds__(256) void k_eig_tri(EigArgs a, int S, int mats_per_
     const int base = threadIdx.x - sub;
     // count(x) = number of eigenvalues < x
     for (int it = 0; it < 128; ++it) {
-        if (hi - lo <= 1e-9 * tnorm + pivmin) break;
+        // to the accuracy the tridiagonal supports (about eps times its norm), so that inverse
+        // iteration separates every eigenvalue the Gram matrix resolves
+        if (hi - lo <= 4.5e-16 * tnorm + pivmin) break;
         const double h = (hi - lo) / (double)(S + 1);
         const double x = lo + (double)(sub + 1) * h;
         int cnt = 0;
@@ -1049,6 +1203,166 @@ __global__ __launch_bounds__(NT) void k_eig_fin(EigArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// D: refinement of the kept subspace without squaring
+// ---------------------------------------------------------------------------
+// The Gram eigenvectors locate the kept right singular subspace only to about
+// eps sigma_1^2 / (sigma_t^2 - sigma_{t+1}^2), which is too coarse when the boundary spectrum
+// decays steeply.  One step of orthogonal iteration on M itself, Y = M V_t, Q = orth(Y),
+// V' = orth(M^T Q), rounds to about eps sigma_1 / (sigma_t - sigma_{t+1}) (every product
+// acts on orthonormal vectors) and contracts the starting error by (sigma_{t+1}/sigma_t)^2.
+// Only the subspace matters: the truncated state M V V^T is the same for any orthonormal
+// basis of it.  Outputs: the new tensor V'^T and U_t Sigma_t = M V' (the carried matrix).
+//
+__device__ inline double e_block_max(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+// Orthonormal basis of the n x t column-major block X (stride n, t <= n) in place, by
+// Householder QR followed by the explicit Q = H_0 ... H_{t-1} [I; 0] (LAPACK's dgeqr2 /
+// dorg2r steps; the reflectors are scaled by the column's largest entry so no squared norm
+// underflows).  Q is orthonormal to working precision whatever the rank of X, and its
+// first columns span X's first columns when those are independent.  tq: t doubles.
+__device__ inline void hh_orth(double* X, int n, int t, double* tq, double* h, double* red) {
+    const int tid = threadIdx.x;
+    const int g = tid >> 2, l = tid & 3;
+    for (int k = 0; k < t; ++k) {
+        double* xk = X + (long long)k * n;
+        double mx = 0.0;
+        for (int r = k + tid; r < n; r += NT) mx = fmax(mx, fabs(xk[r]));
+        mx = e_block_max(mx, red);
+        double sq = 0.0;
+        const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
+        for (int r = k + 1 + tid; r < n; r += NT) {
+            const double y = xk[r] * inv;
+            sq = fma(y, y, sq);
+        }
+        sq = e_block_sum(sq, red);
+        const double al = xk[k] * inv;
+        double tk = 0.0, be = al, sc = 0.0;
+        if (mx > 0.0 && sq > 0.0) {
+            be = -copysign(sqrt(al * al + sq), al);
+            tk = (be - al) / be;
+            sc = inv / (al - be);
+        }
+        __syncthreads();
+        if (tk != 0.0)
+            for (int r = k + 1 + tid; r < n; r += NT) xk[r] *= sc;   // v below the pivot
+        if (tid == 0) tq[k] = tk;
+        __syncthreads();
+        if (tk != 0.0) {
+            // w_c = v^T X[k:, c] for the later columns, 4 lanes per column
+            for (int c0 = k + 1; c0 < t; c0 += NT / 4) {
+                const int c = c0 + g;
+                double dot = 0.0;
+                if (c < t) {
+                    const double* xc = X + (long long)c * n;
+                    if (l == 0) dot = xc[k];
+                    for (int r = k + 1 + l; r < n; r += 4) dot = fma(xk[r], xc[r], dot);
+                }
+                dot = e_wave_sum(dot, 4);
+                if (c < t && l == 0) h[c] = tk * dot;
+            }
+            __syncthreads();
+            for (long long e2 = tid; e2 < (long long)(t - k - 1) * (n - k); e2 += NT) {
+                const int c = k + 1 + (int)(e2 / (n - k)), r = k + (int)(e2 % (n - k));
+                const double v = r == k ? 1.0 : xk[r];
+                X[(long long)c * n + r] -= h[c] * v;
+            }
+            __syncthreads();
+        }
+    }
+    // explicit Q, last reflector first; column k is formed after H_k has acted on the later ones
+    for (int k = t - 1; k >= 0; --k) {
+        double* xk = X + (long long)k * n;
+        const double tk = tq[k];
+        if (tk != 0.0 && k + 1 < t) {
+            for (int c0 = k + 1; c0 < t; c0 += NT / 4) {
+                const int c = c0 + g;
+                double dot = 0.0;
+                if (c < t) {
+                    const double* xc = X + (long long)c * n;
+                    for (int r = k + 1 + l; r < n; r += 4) dot = fma(xk[r], xc[r], dot);   // Q[k][c] = 0 here
+                }
+                dot = e_wave_sum(dot, 4);
+                if (c < t && l == 0) h[c] = tk * dot;
+            }
+            __syncthreads();
+            for (long long e2 = tid; e2 < (long long)(t - k - 1) * (n - k); e2 += NT) {
+                const int c = k + 1 + (int)(e2 / (n - k)), r = k + (int)(e2 % (n - k));
+                const double v = r == k ? 1.0 : xk[r];
+                X[(long long)c * n + r] -= h[c] * v;
+            }
+            __syncthreads();
+        }
+        for (int r = tid; r < n; r += NT) {
+            double q;
+            if (r < k) q = 0.0;
+            else if (r == k) q = 1.0 - tk;
+            else q = -tk * xk[r];
+            xk[r] = q;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(NT) void k_eig_refine(EigArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double h[NT];
+    __shared__ double red[NT / 64];
+    const EigLayout L = eig_layout(a.mz, a.tin, a.p, a.Dc);
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int mp = L.mp, np = L.np, tk = L.tk, tin = a.tin, p = a.p, ldz = L.ldz;
+    double* gs = a.scratch + (long long)b * a.ss;
+    const double* Z = gs + L.oZ;
+    double* U = a.newU + (long long)b * a.us;
+    double* Go = a.Gout + (long long)b * a.gos;
+    double* Y = kLds ? lds : gs + L.oY;                    // mp x tk, column-major
+    double* Wv = kLds ? lds + (long long)mp * tk : gs + L.oV;   // np x tk, column-major
+    auto Mel = [&](int ar, int c) { return Z[(long long)(c % tin) * ldz + (long long)ar * p + c / tin]; };
+    // Y = M V_t (V_t^T is the current tensor, row-major tk x np)
+    for (int e2 = tid; e2 < mp * tk; e2 += NT) {
+        const int ar = e2 % mp, k = e2 / mp;
+        const double* vk = U + (long long)k * np;
+        double acc = 0.0;
+        for (int c = 0; c < np; ++c) acc = fma(Mel(ar, c), vk[c], acc);
+        Y[(long long)k * mp + ar] = acc;
+    }
+    __syncthreads();
+    __shared__ double tq[NT];
+    hh_orth(Y, mp, tk, tq, h, red);
+    // W = M^T Q
+    for (int e2 = tid; e2 < np * tk; e2 += NT) {
+        const int c = e2 % np, k = e2 / np;
+        const double* qk = Y + (long long)k * mp;
+        double acc = 0.0;
+        for (int ar = 0; ar < mp; ++ar) acc = fma(Mel(ar, c), qk[ar], acc);
+        Wv[(long long)k * np + c] = acc;
+    }
+    __syncthreads();
+    hh_orth(Wv, np, tk, tq, h, red);
+    // outputs: V'^T and M V'
+    for (int e2 = tid; e2 < tk * np; e2 += NT) {
+        const int k = e2 / np, c = e2 % np;
+        U[e2] = Wv[(long long)k * np + c];
+    }
+    for (int e2 = tid; e2 < mp * tk; e2 += NT) {
+        const int ar = e2 / tk, k = e2 % tk;
+        const double* vk = Wv + (long long)k * np;
+        double acc = 0.0;
+        for (int c = 0; c < np; ++c) acc = fma(Mel(ar, c), vk[c], acc);
+        Go[e2] = acc;
+    }
+}
+
 // k_eig_fin with register-resident vectors (16-lane groups) when ns and tk fit one of the
 // blockings; false when none does
 template <int RPT, int CPG>
@@ -1069,7 +1383,8 @@ static bool launch_fin_reg(const EigArgs& a, const EigLayout& L, size_t bf, size
            fin_try<2, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 1>(a, rpt, cpg, bf, cap, st) ||
            fin_try<4, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 2>(a, rpt, cpg, bf, cap, st) ||
            fin_try<4, 4>(a, rpt, cpg, bf, cap, st) || fin_try<16, 1>(a, rpt, cpg, bf, cap, st) ||
-           fin_try<16, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 4>(a, rpt, cpg, bf, cap, st);
+           fin_try<16, 2>(a, rpt, cpg, bf, cap, st) || fin_try<8, 4>(a, rpt, cpg, bf, cap, st) ||
+           fin_try<16, 4>(a, rpt, cpg, bf, cap, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1113,6 +1428,29 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
     const size_t bp = (size_t)L.lds_prep * sizeof(double), bf = (size_t)L.lds_fin * sizeof(double);
     const bool in_lds_prep = bp <= cap;
     const size_t bpl = in_lds_prep ? bp : 0;
+    if (rb == 0 && a.z_ready && L.ns <= 224) {
+        // orders 65..224: the Gram matrix of the reshaped centre on the matrix cores, then the
+        // 512-thread register tridiagonalisation.  M[ar][c] = Z[(c % tin) ldz + ar p + c / tin].
+        GemmArgs g{};
+        const Idx2 col{tin, 1, (long long)L.ldz}, row{1 << 30, 0, (long long)p};
+        g.M = g.N = L.ns;
+        g.K = L.gram_right ? L.mp : L.np;
+        g.batch = batch;
+        g.am = L.gram_right ? col : row;
+        g.ak = L.gram_right ? row : col;
+        g.bk = g.ak;
+        g.bn = g.am;
+        g.cm = Idx2{1 << 30, 0, (long long)L.lda};
+        g.cn = Idx2{1 << 30, 0, 1};
+        g.a_bs = g.b_bs = g.c_bs = ss;
+        g.A = g.B = scratch + L.oZ;
+        g.C = scratch + L.oA;
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        hipError_t eg = launch_mgemm(g, Arith::F64, st, 0);
+        if (eg != hipSuccess) return eg;
+        hipLaunchKernelGGL(k_eig_tridiag_big, dim3(batch), dim3(512), 0, st, a);
+    } else
     switch (a.gram_ready ? -rb : tri_rb(L.ns) * 2 + (in_lds_prep ? 1 : 0)) {
         case -1: hipLaunchKernelGGL((k_eig_tridiag<2, 8>), dim3(batch), dim3(64), 0, st, a); break;
         case -2: hipLaunchKernelGGL((k_eig_tridiag<4, 8>), dim3(batch), dim3(64), 0, st, a); break;
@@ -1148,6 +1486,12 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
         if (bf <= cap) hipLaunchKernelGGL((k_eig_fin<true, 0, 0, 0>), dim3(batch), dim3(NT), bf, st, a);
         else hipLaunchKernelGGL((k_eig_fin<false, 0, 0, 0>), dim3(batch), dim3(NT), 0, st, a);
     }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    const size_t br = (size_t)(L.mp + L.np) * L.tk * sizeof(double);
+    if (br <= cap / 2) hipLaunchKernelGGL(k_eig_refine<true>, dim3(batch), dim3(NT), br, st, a);
+    else hipLaunchKernelGGL(k_eig_refine<false>, dim3(batch), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ hipError_t launch_center0(const double* V, long long vs, const double* tau, long
 // truncation SVD through the Gram eigenproblem (three launches, see k_eig.hip)
 struct EigLayout {
     int mp, np, gram_right, ns, tk, ldz, lda, ldx, nv;
-    long long oZ, oA, oD, oE, oT, oX, oL, oP, oW, oM, nm, total, lds_prep, lds_fin;
+    long long oZ, oA, oD, oE, oT, oX, oL, oP, oW, oM, oY, oV, nm, total, lds_prep, lds_fin;
 };
 struct EigArgs {
     const double* V; long long vs;
