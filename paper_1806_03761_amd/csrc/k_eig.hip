@@ -1325,6 +1325,13 @@ __global__ __launch_bounds__(NT) void k_eig_refine(EigArgs a) {
     const double* Z = gs + L.oZ;
     double* U = a.newU + (long long)b * a.us;
     double* Go = a.Gout + (long long)b * a.gos;
+    // the Gram route already resolves the subspace when every kept eigenvalue is within 1e-6
+    // of the largest (sigma_t >= 1e-3 sigma_1): its angle error, about eps lambda_1 / gap, then
+    // moves the state by less than 1e-13 relative.  Only steeper spectra are refined.
+    {
+        const double l0 = gs[L.oL], lt = gs[L.oL + (tk > 0 ? tk - 1 : 0)];
+        if (tk <= 0 || !(l0 > 0.0) || lt >= 1e-6 * l0) return;
+    }
     double* Y = kLds ? lds : gs + L.oY;                    // mp x tk, column-major
     double* Wv = kLds ? lds + (long long)mp * tk : gs + L.oV;   // np x tk, column-major
     auto Mel = [&](int ar, int c) { return Z[(long long)(c % tin) * ldz + (long long)ar * p + c / tin]; };

@@ -108,9 +108,14 @@ __global__ __launch_bounds__(NT) void k_ratio(const double* F, long long fs, con
                                               long long gs, int n, const double* la,
                                               const double* lb, const double* lnW,
                                               const double* sgW, double* ratio, int nbonds,
-                                              int bond) {
+                                              int bond, const int8_t* skip) {
     __shared__ double red[NT / 64];
     const int b = blockIdx.x;
+    // a bond of equal spins has no exchange term: its flipped partials were not formed
+    if (skip && skip[(long long)b * nbonds + bond] == 0) {
+        if (threadIdx.x == 0) ratio[(long long)b * nbonds + bond] = 0.0;
+        return;
+    }
     const double* Fb = F + (long long)b * fs;
     const double* Gb = G + (long long)b * gs;
     // each thread's terms in ascending i, their loads issued 8 strides at a time
@@ -141,10 +146,11 @@ __global__ __launch_bounds__(NT) void k_ratio(const double* F, long long fs, con
 }
 hipError_t launch_ratio(const double* F, long long fs, const double* G, long long gs, int n,
                         const double* la, const double* lb, const double* lnW, const double* sgW,
-                        double* ratio, int nbonds, int bond, int batch, hipStream_t st) {
+                        double* ratio, int nbonds, int bond, int batch, hipStream_t st,
+                        const int8_t* skip) {
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ratio, dim3(batch), dim3(NT), 0, st, F, fs, G, gs, n, la, lb, lnW, sgW,
-                       ratio, nbonds, bond);
+                       ratio, nbonds, bond, skip);
     return hipGetLastError();
 }
 
@@ -167,6 +173,33 @@ hipError_t launch_sandwich_value(const double* P, long long ps, const double* la
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sandwich_value, dim3((batch + 255) / 256), dim3(256), 0, st, P, ps, lam,
                        lnW, sgW, batch);
+    return hipGetLastError();
+}
+
+// act[b][bond] = [the two spins of the bond differ], bonds in the order of k_eloc
+__global__ void k_bond_active(const int8_t* S, int Lx, int Ly, int8_t* act, int nbonds, int batch) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)batch * nbonds) return;
+    const int b = (int)(e / nbonds), k = (int)(e % nbonds);
+    const int nH = Ly * (Lx - 1), nV = (Ly - 1) * Lx, nD = (Ly - 1) * (Lx - 1);
+    int m, n;
+    if (k < nH) {
+        m = (k / (Lx - 1)) * Lx + k % (Lx - 1); n = m + 1;
+    } else if (k < nH + nV) {
+        m = k - nH; n = m + Lx;
+    } else if (k < nH + nV + nD) {
+        const int q = k - nH - nV; m = (q / (Lx - 1)) * Lx + q % (Lx - 1); n = m + Lx + 1;
+    } else {
+        const int q = k - nH - nV - nD; m = (q / (Lx - 1)) * Lx + q % (Lx - 1) + 1; n = m + Lx - 1;
+    }
+    const int8_t* s = S + (long long)b * Lx * Ly;
+    act[e] = s[m] != s[n] ? 1 : 0;
+}
+hipError_t launch_bond_active(const int8_t* S, int Lx, int Ly, int8_t* act, int nbonds, int batch, hipStream_t st) {
+    const long long n = (long long)batch * nbonds;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bond_active, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S, Lx, Ly, act, nbonds,
+                       batch);
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
     float* Big = Le + 1024;      // incoming partial, later half of the third temporary
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
+    if (a.skip && a.skip[(long long)b * a.skip_bs] == 0) return;
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
     const int Du = a.Du, Dq = a.Dq, h = a.h, h1 = a.h1;
     const double* X = a.X + (long long)b * a.xs;
@@ -369,6 +370,7 @@ __global__ __launch_bounds__(256) void k_row_step(RowArgs a) {
     float* Ts = Le + 1024;       // second temporary
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
+    if (a.skip && a.skip[(long long)b * a.skip_bs] == 0) return;
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1, Du = a.Du, Dd = a.Dd, h = a.h, h1 = a.h1;
     const double* X = a.X + (long long)b * a.xs;
     const double* U = a.U + (long long)b * a.us;
@@ -610,6 +612,7 @@ __global__ __launch_bounds__(256, FWD ? 4 : 3) void k_pair_mfma(PairArgs a) {
     extern __shared__ __align__(16) float sm[];
     const int b = blockIdx.x, tid = threadIdx.x;
     if (b >= a.batch) return;
+    if (a.skip && a.skip[(long long)b * a.skip_bs] == 0) return;
     const int w = tid >> 6, li = tid & 15, g = (tid >> 4) & 3;
     float* T12 = sm + w * 1024;   // this wave's first, then second temporary, 64 rows x 16
     const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;

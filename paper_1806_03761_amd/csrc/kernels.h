@@ -87,6 +87,8 @@ struct PairArgs {
     const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
     int mfma;                            // 1: the matrix-core form (float32 MFMA)
+    const int8_t* skip = nullptr;        // sample b skipped when skip[b * skip_bs] == 0
+    long long skip_bs = 0;
 };
 bool pair_step_fits(const PairArgs& a);
 // fused single-row sandwich step (float32, legs <= 4, boundary bonds <= 16)
@@ -100,6 +102,8 @@ struct RowArgs {
     double* Y; long long ys;
     const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
+    const int8_t* skip = nullptr;        // sample b skipped when skip[b * skip_bs] == 0
+    long long skip_bs = 0;
 };
 bool row_step_fits(const RowArgs& a);
 hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st);
@@ -114,7 +118,11 @@ hipError_t launch_rescale(double* x, long long xs, int n, const double* lin, dou
                           int batch, hipStream_t st);
 hipError_t launch_ratio(const double* F, long long fs, const double* G, long long gs, int n,
                         const double* la, const double* lb, const double* lnW, const double* sgW,
-                        double* ratio, int nbonds, int bond, int batch, hipStream_t st);
+                        double* ratio, int nbonds, int bond, int batch, hipStream_t st,
+                        const int8_t* skip = nullptr);
+// act[b][bond] = 1 where the two spins of the bond differ (bond order of launch_eloc)
+hipError_t launch_bond_active(const int8_t* S, int Lx, int Ly, int8_t* act, int nbonds, int batch,
+                              hipStream_t st);
 hipError_t launch_sandwich_value(const double* P, long long ps, const double* lam, double* lnW,
                                  double* sgW, int batch, hipStream_t st);
 struct ElocArgs {

@@ -289,6 +289,7 @@ public:
         o_site32 = fuse_pairs ? L.alloc(0, (long long)N * 512) : 0;   // float32 site tables
         nbonds = Ly * (Lx - 1) + (Ly - 1) * Lx + 2 * (Ly - 1) * (Lx - 1);
         o_ratio = want_e ? L.alloc(nbonds) : 0;
+        o_act = want_e ? L.alloc(0, ((long long)Bc * nbonds + 7) / 8) : 0;   // int8 [Bc][nbonds]
         o_delta = want_g ? L.alloc((long long)N * D4) : 0;
         o_flags = L.alloc(1);   // int8 flags in a double-sized slot per sample
         o_eloc = L.alloc(1);
@@ -345,6 +346,7 @@ public:
         g.A = A.p; g.B = B.p; g.C = C.p;
         g.alpha = 1.0; g.beta = 0.0;
         g.a_f32 = A.f32; g.b_f32 = B.f32; g.c_f32 = C.f32;
+        g.skip = skip_; g.skip_bs = skip_bs_;
         char kb[96];
         snprintf(kb, sizeof kb, "%d,%d,%d,%d,%d,%d", M, Nn, K, Bcur, (int)arith,
                  (int)A.f32 | ((int)B.f32 << 1) | ((int)C.f32 << 2));
@@ -543,6 +545,7 @@ public:
         a.sel = Scur + (long long)i * Lx + j; a.sel_bs = N; a.flip = flip;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
         a.lin = lin; a.lout = lout;
+        a.skip = skip_; a.skip_bs = skip_bs_;
         step_rescaled = lout != nullptr;
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.cl * a.cu1 * a.h1 * a.Dd * a.h * a.Du +
@@ -620,6 +623,7 @@ public:
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
         a.lin = lin; a.lout = lout;
         a.mfma = pair_mfma ? 1 : 0;
+        a.skip = skip_; a.skip_bs = skip_bs_;
         step_rescaled = lout != nullptr;
         const double fl = 2.0 * Bcur *
                           ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
@@ -696,6 +700,17 @@ public:
     }
 
     int8_t* flags() const { return (int8_t*)buf(o_flags); }
+    int8_t* act() const { return (int8_t*)buf(o_act); }
+    // the GEMMs and fused steps launched between skip_on(bond) and skip_off() leave out the
+    // samples whose two spins on `bond` are equal (no exchange term, so no flipped partial)
+    void skip_on(int bond) {
+        skip_ = act() + bond;
+        skip_bs_ = nbonds;
+    }
+    void skip_off() {
+        skip_ = nullptr;
+        skip_bs_ = 0;
+    }
 
     // launch `f` between two events when its kernel class is being profiled
     template <class F>
@@ -736,6 +751,7 @@ public:
         Scur = S;
         hipStream_t st = st_;
         KL(launch_check_configs(S, N, Bn, flags(), st));
+        if (want_eloc) KL(launch_bond_active(S, Lx, Ly, act(), nbonds, Bn, st));
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
         if (fuse_pairs) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
@@ -780,12 +796,14 @@ public:
                     Op P = (j == 0) ? ones() : op(o_P[j], s_P[j]);
                     Op Q = (j + 2 == Lx) ? ones() : op(o_Q[j + 2], s_P[j + 2]);
                     Op F = op(o_F, s_F), G = op(o_Gf, s_F);
+                    const int bond = i * (Lx - 1) + j;
+                    skip_on(bond);
                     CK(row_fwd(i, j, P, 1, F));
                     CK(row_bwd(i, j + 1, Q, 1, G));
+                    skip_off();
                     const int n = (int)(chiU[i][j + 1] * Dh[j + 1] * chiL[i][j + 1]);
                     KL(launch_ratio(F.p, F.bs, G.p, G.bs, n, buf(o_lP[j]), buf(o_lQ[j + 2]),
-                                    buf(o_lnW), buf(o_sgW), buf(o_ratio), nbonds,
-                                    i * (Lx - 1) + j, Bn, st));
+                                    buf(o_lnW), buf(o_sgW), buf(o_ratio), nbonds, bond, Bn, st, act()));
                 }
             }
             if (want_grad)
@@ -821,24 +839,31 @@ public:
                     const int n1 = (int)(chiU[i][j + 1] * Dh[j + 1] * Dh[j + 1] * chiL[i + 1][j + 1]);
                     // vertical bond (i,j)-(i+1,j)
                     Op Q1 = (j + 1 == Lx) ? ones() : op(o_Q2[j + 1], s_P2[j + 1]);
+                    // flipped partials only for the samples whose two spins differ
+                    const int bv = nH + i * Lx + j;
+                    skip_on(bv);
                     CK(pair_fwd(i, j, P, 1, 1, F));
+                    skip_off();
                     KL(launch_ratio(F.p, F.bs, Q1.p, Q1.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 1]),
-                                    buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds, nH + i * Lx + j,
-                                    Bn, st));
+                                    buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds, bv, Bn, st, act()));
                     if (j + 1 < Lx) {
                         Op Q2 = (j + 2 == Lx) ? ones() : op(o_Q2[j + 2], s_P2[j + 2]);
                         // diagonal (i,j)-(i+1,j+1)
+                        const int bd = nH + nV + i * (Lx - 1) + j;
+                        skip_on(bd);
                         CK(pair_fwd(i, j, P, 1, 0, F));
                         CK(pair_bwd(i, j + 1, Q2, 0, 1, G));
+                        skip_off();
                         KL(launch_ratio(F.p, F.bs, G.p, G.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 2]),
-                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds,
-                                        nH + nV + i * (Lx - 1) + j, Bn, st));
+                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds, bd, Bn, st, act()));
                         // anti-diagonal (i,j+1)-(i+1,j)
+                        const int ba = nH + nV + nD + i * (Lx - 1) + j;
+                        skip_on(ba);
                         CK(pair_fwd(i, j, P, 0, 1, F));
                         CK(pair_bwd(i, j + 1, Q2, 1, 0, G));
+                        skip_off();
                         KL(launch_ratio(F.p, F.bs, G.p, G.bs, n1, buf(o_lP2[j]), buf(o_lQ2[j + 2]),
-                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds,
-                                        nH + nV + nD + i * (Lx - 1) + j, Bn, st));
+                                        buf(o_lnW2), buf(o_sgW2), buf(o_ratio), nbonds, ba, Bn, st, act()));
                     }
                 }
             }
@@ -891,7 +916,9 @@ public:
     std::vector<size_t> o_wy;
     // the blocked QR (matrix-core WY updates) for matrices beyond the register kernels
     static bool use_qrb(int rows, int cols) { return (rows > 512 || cols > 128) && qrb_fits(rows, cols); }
-    size_t o_site32 = 0;
+    size_t o_site32 = 0, o_act = 0;
+    const int8_t* skip_ = nullptr;
+    long long skip_bs_ = 0;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0, o_gws;
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
