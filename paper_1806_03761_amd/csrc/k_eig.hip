@@ -74,7 +74,8 @@ __host__ __device__ inline EigLayout eig_layout(int mz, int tin, int p, int Dc) 
     L.oM = L.oW + L.nv;
     L.oY = L.oM;                                   // refinement: Y (mp x tk) and W (np x tk)
     L.oV = L.oY + (long long)L.mp * L.tk;
-    L.total = L.oV + (long long)L.np * L.tk;
+    L.oQ = L.oV + (long long)L.np * L.tk;          // W blocks of the GEMM application of Q
+    L.total = L.oQ + 64LL * tin;
     // LDS needs of the two workgroup kernels
     L.lds_prep = (long long)L.ldz * tin + (long long)L.lda * L.ns + 3LL * L.ns + L.nv + 8;
     // k_eig_fin stages X, tau and the eigenvalues; the reflectors and Z stay in global
@@ -1421,7 +1422,7 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
         // reflectors of the blocked QR: Z = Q [G; 0] by its WY blocks on the matrix cores
         a.gram_ready = 0;
         hipError_t ez = launch_applyq_blocked(V, vs, mz, r, wyT, wys, G, gs, r, tin, scratch + L.oZ, ss, L.ldz,
-                                              batch, st);
+                                              scratch + L.oQ, ss, batch, st);
         if (ez != hipSuccess) return ez;
         a.z_ready = 1;
     } else {

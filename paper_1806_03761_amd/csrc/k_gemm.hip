@@ -178,17 +178,17 @@ static GemmArgs transposed(const GemmArgs& g) {
 
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    // 1..12: matrix-core tiles; 13: row kernel; 14: row kernel on the transposed product
-    // (each falls back to the heuristic tile when the shape does not fit it).  Every form
-    // sums the products of an output in ascending k with one rounding per product (a
-    // 16x16x4 MFMA adds its four products in k order, like a chain of fma), so all of
-    // them give the same results.
-    if (tile == 13 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
-    if (tile == 14) {
+    // 1..kMfmaTiles: matrix-core tiles; kMfmaTiles + 1: row kernel; kMfmaTiles + 2: row kernel
+    // on the transposed product (each falls back to the heuristic tile when the shape does
+    // not fit it).  Every form sums the products of an output in ascending k with one
+    // rounding per product (a 16x16x4 MFMA adds its four products in k order, like a chain
+    // of fma), so all of them give the same results.
+    if (tile == kMfmaTiles + 1 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
+    if (tile == kMfmaTiles + 2) {
         const GemmArgs t = transposed(g);
         if (gemm_rows_fits(t)) return launch_gemm_rows(t, ar, st);
     }
-    return launch_mgemm(g, ar, st, tile >= 13 ? 0 : tile);
+    return launch_mgemm(g, ar, st, tile > kMfmaTiles ? 0 : tile);
 }
 
 }  // namespace peps

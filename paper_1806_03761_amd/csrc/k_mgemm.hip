@@ -47,22 +47,20 @@ __device__ __forceinline__ typename MT<AR>::Acc mfma(typename MT<AR>::In a, type
     else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int TK = 16;
-
 // Per-thread share of one operand tile (TK x TW entries): NI loads.  Entry e of the tile
 // maps to (k, w) either w-fastest (consecutive threads walk the free index) or k-fastest,
-// whichever index has unit stride in memory, so the loads coalesce.
-template <int TW>
+// whichever index has unit stride in memory, so the loads coalesce.  TK = 16, or 12 where
+// K is a multiple of 12 (no padded k stage).
+template <int TK, int TW>
 struct TileLd {
     static constexpr int NE = TK * TW, NI = (NE + 255) / 256;
 };
 
-template <int TW, Arith AR>
-__device__ __forceinline__ void tile_issue(double (&x)[TileLd<TW>::NI], float (&xf)[TileLd<TW>::NI],
-                                           bool (&ok)[TileLd<TW>::NI], const long long* off_w, const Idx2& kx,
-                                           int k0, int K, bool kfast, int f32, const double* srcd,
+template <int TK, int TW, int NI, Arith AR>
+__device__ __forceinline__ void tile_issue(double (&x)[NI], float (&xf)[NI], bool (&ok)[NI], const long long* off_w,
+                                           const Idx2& kx, int k0, int K, bool kfast, int f32, const double* srcd,
                                            const float* srcf, int tid) {
-    constexpr int NE = TileLd<TW>::NE, NI = TileLd<TW>::NI;
+    constexpr int NE = TK * TW;
     long long o[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -83,12 +81,11 @@ __device__ __forceinline__ void tile_issue(double (&x)[TileLd<TW>::NI], float (&
     }
 }
 
-template <int TW, Arith AR>
-__device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const double (&x)[TileLd<TW>::NI],
-                                           const float (&xf)[TileLd<TW>::NI], const bool (&ok)[TileLd<TW>::NI],
-                                           bool kfast, int f32, int tid) {
+template <int TK, int TW, int NI, Arith AR>
+__device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const double (&x)[NI], const float (&xf)[NI],
+                                           const bool (&ok)[NI], bool kfast, int f32, int tid) {
     using In = typename MT<AR>::In;
-    constexpr int NE = TileLd<TW>::NE, NI = TileLd<TW>::NI;
+    constexpr int NE = TK * TW;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         const int e = tid + 256 * i;
@@ -99,7 +96,7 @@ __device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const doubl
     }
 }
 
-template <int WM, int WN, int BM, int BN, Arith AR>
+template <int WM, int WN, int BM, int BN, int TK, Arith AR>
 __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tiles_n) {
     using In = typename MT<AR>::In;
     using Acc = typename MT<AR>::Acc;
@@ -152,19 +149,20 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-    double xa[TileLd<TM>::NI], xb[TileLd<TN>::NI];
-    float xaf[TileLd<TM>::NI], xbf[TileLd<TN>::NI];
-    bool oka[TileLd<TM>::NI], okb[TileLd<TN>::NI];
-    tile_issue<TM, AR>(xa, xaf, oka, aoff_m, g.ak, 0, g.K, akf, g.a_f32, Ab, Af, tid);
-    tile_issue<TN, AR>(xb, xbf, okb, boff_n, g.bk, 0, g.K, bkf, g.b_f32, Bb, Bf, tid);
+    constexpr int NIA = TileLd<TK, TM>::NI, NIB = TileLd<TK, TN>::NI;
+    double xa[NIA], xb[NIB];
+    float xaf[NIA], xbf[NIB];
+    bool oka[NIA], okb[NIB];
+    tile_issue<TK, TM, NIA, AR>(xa, xaf, oka, aoff_m, g.ak, 0, g.K, akf, g.a_f32, Ab, Af, tid);
+    tile_issue<TK, TN, NIB, AR>(xb, xbf, okb, boff_n, g.bk, 0, g.K, bkf, g.b_f32, Bb, Bf, tid);
     for (int k0 = 0; k0 < g.K; k0 += TK) {
         __syncthreads();
-        tile_store<TM, AR>(As, xa, xaf, oka, akf, g.a_f32, tid);
-        tile_store<TN, AR>(Bs, xb, xbf, okb, bkf, g.b_f32, tid);
+        tile_store<TK, TM, NIA, AR>(As, xa, xaf, oka, akf, g.a_f32, tid);
+        tile_store<TK, TN, NIB, AR>(Bs, xb, xbf, okb, bkf, g.b_f32, tid);
         __syncthreads();
         if (k0 + TK < g.K) {
-            tile_issue<TM, AR>(xa, xaf, oka, aoff_m, g.ak, k0 + TK, g.K, akf, g.a_f32, Ab, Af, tid);
-            tile_issue<TN, AR>(xb, xbf, okb, boff_n, g.bk, k0 + TK, g.K, bkf, g.b_f32, Bb, Bf, tid);
+            tile_issue<TK, TM, NIA, AR>(xa, xaf, oka, aoff_m, g.ak, k0 + TK, g.K, akf, g.a_f32, Ab, Af, tid);
+            tile_issue<TK, TN, NIB, AR>(xb, xbf, okb, boff_n, g.bk, k0 + TK, g.K, bkf, g.b_f32, Bb, Bf, tid);
         }
 #pragma unroll
         for (int s = 0; s < TK / 4; ++s) {
@@ -205,7 +203,7 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
         }
 }
 
-template <int WM, int WN, int BM, int BN>
+template <int WM, int WN, int BM, int BN, int TK = 16>
 hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
     constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
     const int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
@@ -214,27 +212,32 @@ hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(256);
     switch (ar) {
-        case Arith::F64: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::F64>), grid, block, 0, st, g, tm, tn); break;
-        case Arith::F32: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::F32>), grid, block, 0, st, g, tm, tn); break;
-        case Arith::BF16: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, Arith::BF16>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::F64: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F64>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::F32: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F32>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::BF16: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::BF16>), grid, block, 0, st, g, tm, tn); break;
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-// tiles 1..kGemmTiles: (TM x TN) = 32x32, 64x16, 16x64, 64x64, 128x16, 16x128, 64x32, 32x64,
-// 128x64, 64x128, 128x32, 32x128
+// tiles 1..kMfmaTiles (TM x TN, k stage): 32x32, 64x16, 16x64, 64x64, 128x16, 16x128, 64x32, 32x64,
+// 128x64, 64x128, 128x32, 32x128 (k stage 16); 64x48, 128x48, 48x64, 48x128 (16); 64x48, 128x48,
+// 48x64, 64x64 (k stage 12: no padded stage when K is a multiple of 12, e.g. 36 or 216)
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (tile <= 0 || tile > kGemmTiles) {
-        // heuristic: the smallest tile that covers small products, else 64 x 64
+    if (tile <= 0 || tile > kMfmaTiles) {
+        // heuristic: the smallest tile that covers small products, 48-wide where a leg of
+        // 36 or 48 would leave a 64-wide tile part-empty, else 64 x 64
+        const bool k12 = g.K % 12 == 0 && g.K % 16 != 0;
         if (g.M <= 32 && g.N <= 32) tile = 1;
         else if (g.N <= 16) tile = g.M >= 128 ? 5 : 2;
         else if (g.M <= 16) tile = g.N >= 128 ? 6 : 3;
+        else if (g.N <= 48 && g.N > 32) tile = k12 ? 18 : 14;
+        else if (g.M <= 48 && g.M > 32) tile = k12 ? 19 : 15;
         else if (g.N <= 32) tile = 7;
         else if (g.M <= 32) tile = 8;
-        else tile = 4;
+        else tile = k12 ? 20 : 4;
     }
     switch (tile) {
         case 1: return launch_m<2, 2, 1, 1>(g, ar, st);
@@ -248,7 +251,15 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         case 9: return launch_m<2, 2, 4, 2>(g, ar, st);
         case 10: return launch_m<2, 2, 2, 4>(g, ar, st);
         case 11: return launch_m<4, 1, 2, 2>(g, ar, st);
-        default: return launch_m<1, 4, 2, 2>(g, ar, st);
+        case 12: return launch_m<1, 4, 2, 2>(g, ar, st);
+        case 13: return launch_m<4, 1, 1, 3>(g, ar, st);
+        case 14: return launch_m<4, 1, 2, 3>(g, ar, st);
+        case 15: return launch_m<1, 4, 3, 1>(g, ar, st);
+        case 16: return launch_m<1, 4, 3, 2>(g, ar, st);
+        case 17: return launch_m<4, 1, 1, 3, 12>(g, ar, st);
+        case 18: return launch_m<4, 1, 2, 3, 12>(g, ar, st);
+        case 19: return launch_m<1, 4, 3, 1, 12>(g, ar, st);
+        default: return launch_m<2, 2, 2, 2, 12>(g, ar, st);
     }
 }
 

@@ -5,15 +5,16 @@
 
 namespace peps {
 
-// tile: 0 = heuristic choice, 1..12 = a matrix-core tile shape (k_mgemm.hip), 13/14 = the
-// row kernel (k_gemm.hip) on the product or its transpose
-static constexpr int kGemmTiles = 14;
+// tile: 0 = heuristic choice, 1..kMfmaTiles = a matrix-core tile shape (k_mgemm.hip), the two
+// after them = the row kernel (k_gemm.hip) on the product or its transpose
+static constexpr int kMfmaTiles = 20;
+static constexpr int kGemmTiles = kMfmaTiles + 2;
 // row kernel for skinny products: N <= 64 and K <= 64 (gemm_rows_fits); same results as
 // launch_gemm
 bool gemm_rows_fits(const GemmArgs& g);
 hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
-// matrix-core GEMM (k_mgemm.hip): tile 1..12, 0 = heuristic
+// matrix-core GEMM (k_mgemm.hip): tile 1..kMfmaTiles, 0 = heuristic
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();
 
@@ -37,7 +38,7 @@ hipError_t launch_center0(const double* V, long long vs, const double* tau, long
 // truncation SVD through the Gram eigenproblem (three launches, see k_eig.hip)
 struct EigLayout {
     int mp, np, gram_right, ns, tk, ldz, lda, ldx, nv;
-    long long oZ, oA, oD, oE, oT, oX, oL, oP, oW, oM, oY, oV, nm, total, lds_prep, lds_fin;
+    long long oZ, oA, oD, oE, oT, oX, oL, oP, oW, oM, oY, oV, oQ, nm, total, lds_prep, lds_fin;
 };
 struct EigArgs {
     const double* V; long long vs;
@@ -66,12 +67,19 @@ hipError_t launch_eig(const double* V, long long vs, const double* tau, long lon
 int qrb_panel_width(int m);
 long long qrb_wy_doubles(int m, int n);
 bool qrb_fits(int m, int n);
+long long qrb_vc_doubles(int m);
+long long qrb_wq_doubles(int n);
+// Vc (qrb_vc_doubles(m) per matrix) and Wq (qrb_wq_doubles(n)) hold the 32-reflector updates
+// (trailing columns updated by two GEMMs per pair of panels); Vc == nullptr: 16-column
+// WY updates only
 hipError_t launch_qr_blocked(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
-                             long long ts, double* Tw, long long tws, int batch, hipStream_t st);
+                             long long ts, double* Tw, long long tws, double* Vc, long long vcs, double* Wq,
+                             long long wqs, int batch, hipStream_t st);
 // Z (column-major, ld ldz, stride zs per matrix) = Q [G; 0], Q from launch_qr_blocked
+// Wq: 64 tin doubles per matrix (stride wqs) for the GEMM form (16-column panels)
 hipError_t launch_applyq_blocked(const double* V, long long vs, int mz, int nrefl, const double* Tw,
                                  long long tws, const double* G, long long gs, int rin, int tin, double* Z,
-                                 long long zs, int ldz, int batch, hipStream_t st);
+                                 long long zs, int ldz, double* Wq, long long wqs, int batch, hipStream_t st);
 
 // misc
 // fused two-row sandwich step (float32, legs <= 4, boundary bonds <= 16; see k_pair.hip)

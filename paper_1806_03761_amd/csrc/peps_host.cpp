@@ -185,14 +185,18 @@ public:
         }
         // truncation buffers (max over every truncation of the plan)
         s_X.assign(Lx, 1); s_tau.assign(Lx, 1); s_wy.assign(Lx, 0);
+        s_vc = 0; s_wq = 0;
         s_R = 1; s_Y = 1; s_G = 1; s_svd = 0;
         auto visit = [&](const Trunc& t) {
             for (int j = 0; j < Lx; ++j) {
                 const long long rows = (long long)t.rho[j] * t.p, cols = t.K[j + 1];
                 s_X[j] = std::max(s_X[j], rows * cols);
                 s_tau[j] = std::max<long long>(s_tau[j], std::min(rows, cols));
-                if (j + 1 < Lx && use_qrb((int)rows, (int)cols))
+                if (j + 1 < Lx && use_qrb((int)rows, (int)cols)) {
                     s_wy[j] = std::max(s_wy[j], qrb_wy_doubles((int)rows, (int)cols));
+                    s_vc = std::max(s_vc, qrb_vc_doubles((int)rows));
+                    s_wq = std::max(s_wq, qrb_wq_doubles((int)cols));
+                }
                 if (j + 1 < Lx) s_R = std::max(s_R, (long long)t.rho[j + 1] * t.K[j + 1]);
                 s_Y = std::max(s_Y, (long long)t.rho[j] * Dh[j] * t.pin * t.chi[j + 1]);
                 s_G = std::max(s_G, (long long)t.rho[j] * t.tau[j]);
@@ -213,6 +217,8 @@ public:
             o_tau[j] = L.alloc(s_tau[j]);
             if (s_wy[j] > 0) o_wy[j] = L.alloc(s_wy[j]);
         }
+        o_vc = s_vc > 0 ? L.alloc(s_vc) : 0;
+        o_wq = s_wq > 0 ? L.alloc(s_wq) : 0;
         o_R[0] = L.alloc(s_R); o_R[1] = L.alloc(s_R);
         o_Y = L.alloc(s_Y);
         o_G[0] = L.alloc(s_G); o_G[1] = L.alloc(s_G);
@@ -445,14 +451,16 @@ public:
                     return hipErrorInvalidValue;
                 }
                 const bool blocked = use_qrb((int)rows, t.K[j + 1]);
-                if (blocked && qrb_wy_doubles((int)rows, t.K[j + 1]) > s_wy[j]) {
+                if (blocked && (qrb_wy_doubles((int)rows, t.K[j + 1]) > s_wy[j] ||
+                                qrb_vc_doubles((int)rows) > s_vc || qrb_wq_doubles(t.K[j + 1]) > s_wq)) {
                     bounds_msg = "internal bounds check failed in blocked qr";
                     return hipErrorInvalidValue;
                 }
                 KL(timed(PEPS_KC_QR, Bcur * qr_flops((double)rows, t.K[j + 1]), [&] {
                     if (blocked)
                         return launch_qr_blocked(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
-                                                 buf(o_tau[j]), s_tau[j], buf(o_wy[j]), s_wy[j], Bcur, st_);
+                                                 buf(o_tau[j]), s_tau[j], buf(o_wy[j]), s_wy[j], buf(o_vc), s_vc,
+                                                 buf(o_wq), s_wq, Bcur, st_);
                     return launch_qr(X.p, X.bs, (int)rows, t.K[j + 1], buf(o_R[j & 1]), s_R,
                                      buf(o_tau[j]), s_tau[j], Bcur, st_);
                 }));
@@ -914,6 +922,8 @@ public:
         o_lP2, o_lQ2;
     std::vector<long long> s_envU, s_envL, s_X, s_tau, s_P, s_P2, s_wy;
     std::vector<size_t> o_wy;
+    size_t o_vc = 0, o_wq = 0;
+    long long s_vc = 0, s_wq = 0;
     // the blocked QR (matrix-core WY updates) for matrices beyond the register kernels
     static bool use_qrb(int rows, int cols) { return (rows > 512 || cols > 128) && qrb_fits(rows, cols); }
     size_t o_site32 = 0, o_act = 0;
