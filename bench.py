@@ -6,11 +6,16 @@ single- and two-row sandwiches, every J1/J2 spin-flip ratio, the local energy,
 and the energy gradient dE/dA of the Monte Carlo estimator (log-derivatives of
 every site contracted with 2(E - <E>)/B).
 
-Workload: 8x8 open J1-J2 lattice (J2/J1 = 0.5), D = 4, Dc = 16, 4096 samples
-(one per Markov chain, seeded S^z = 0 configurations), site tensors N(0,1)
-normalised per site; contraction GEMMs in f32, QR/SVD/logs in f64.
+Headline workload: 16x16 open J1-J2 lattice (J2/J1 = 0.5), D = 6, Dc = 36, 1024
+samples (one per Markov chain, seeded S^z = 0 configurations), site tensors N(0,1)
+normalised per site; every contraction and factorisation in float64 (the paper's
+arithmetic).  Inputs are resident in HBM before the timed region.  Beside it the
+line reports the same workload with float32 and bfloat16 contractions (with their
+errors against the float64 results), the plain path (batch 1, float64), the 8x8
+workload, a 24x24 subset, and the oracle on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME] [--prec f64]
+                    [--no-legs] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -22,6 +27,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+MI355X_PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense MFMA TFLOP/s
 
 
 def _oracle_worker(args):
@@ -37,31 +44,37 @@ def _oracle_worker(args):
     return hi - lo
 
 
-def cpu_baseline(name: str, per_core: int = 96):
-    """Time the FP64 oracle (amplitude + local energy + log-derivatives, one sample at a
-    time per process) on the host cores, over a bounded sample of the workload (96 per
-    process: about 15 s of wall time on 16 cores)."""
+def start_cpu_baseline(name: str, per_proc: int):
+    """Start the FP64 oracle (amplitude + local energy + log-derivatives, one sample at a
+    time per process, numpy single-threaded) on up to 16 host cores over the first samples
+    of the workload; returns a handle for finish_cpu_baseline."""
     import multiprocessing as mp
-    cores = max(1, min(16, os.cpu_count() or 1))
-    n = per_core * cores
-    tasks = [(name, k * per_core, (k + 1) * per_core) for k in range(cores)]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
-        pool.map(_oracle_worker, [(name, 0, 1)] * cores)      # import warm-up
-        t0 = time.perf_counter()
-        done = sum(pool.map(_oracle_worker, tasks))
-        dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} of the 4096 configurations, {per_core} per process, "
-                      f"{cores} processes, numpy single-threaded; wall {dt:.1f} s"}
+    procs = max(1, min(16, os.cpu_count() or 1))
+    tasks = [(name, k * per_proc, (k + 1) * per_proc) for k in range(procs)]
+    pool = mp.get_context("spawn").Pool(procs)
+    pool.map(_oracle_worker, [(name, 0, 0)] * procs)           # imports warmed up
+    t0 = time.perf_counter()
+    res = pool.map_async(_oracle_worker, tasks)
+    return pool, res, t0, procs, per_proc
 
 
-# HBM traffic per launch of each kernel class, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE) over one evaluation, scaled by the same counters on a
-# 256 MiB device copy (command and figures in profiles/); valid only for the kernel
-# sources they were taken on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": "f8afcdcd88d66ed4",
-           "bytes_per_launch": {"svd": 640246418, "qr": 460538203, "gemm": 143312682, "fused": 102274218}}
+def finish_cpu_baseline(h, name):
+    pool, res, t0, procs, per_proc = h
+    done = sum(res.get())
+    dt = time.perf_counter() - t0
+    pool.close()
+    pool.join()
+    return {"value": done / dt, "unit": "samples/s", "cores": procs, "kind": "oracle",
+            "sample": f"the first {done} configurations of the {name} workload, {per_proc} per "
+                      f"process, {procs} processes, numpy single-threaded, run during the warm-up "
+                      f"steps; wall {dt:.1f} s"}
+
+
+# HBM traffic per launch of the dominant kernel class, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) over one evaluation of the headline workload, scaled by the
+# same counters on a 256 MiB device copy (profiles/); valid only for the kernel sources
+# they were measured on (hash below), otherwise reported as null.
+TRAFFIC = {"sources": None, "workload": "16x16_D6_Dc36", "bytes_per_launch": {}}
 
 
 def _sources_hash() -> str:
@@ -75,17 +88,40 @@ def _sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+CLASSES = ("gemm", "fused", "qr", "svd")
+CLASS_NAMES = {"svd": "truncation step (Q application, Gram matrix, tridiagonalisation, bisection, "
+                      "eigenvectors, subspace refinement)",
+               "qr": "blocked Householder QR (register panels + 32-reflector WY GEMMs)",
+               "gemm": "k_mgemm contraction GEMMs (apply, sandwiches, environments)",
+               "fused": "fused sandwich steps (k_pair_mfma / k_row_step)"}
+
+
+def _read(peps, classes):
+    out = {}
+    for cls in classes:
+        kms, n, fl = peps.profile_read(cls)
+        out[cls] = {"ms_total": kms, "launches": n, "avg_us": 1e3 * kms / max(n, 1),
+                    "tflops": fl / max(kms, 1e-12) / 1e9}
+    return out
+
+
+def _rel_errors(x, ref, floor=1.0):
+    import numpy as np
+    x, ref = np.asarray(x, np.float64), np.asarray(ref, np.float64)
+    e = np.abs(x - ref) / np.maximum(floor, np.abs(ref))
+    return {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)), "max": float(e.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--workload", default="16x16_D6_Dc36")
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--no-legs", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-mcmc", action="store_true", help="skip the Metropolis sampling leg")
-    ap.add_argument("--no-corr", action="store_true", help="skip the correlation-estimator leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (3 times): the reference "
@@ -96,6 +132,7 @@ def main():
               "multi-GPU sharding is described in the design notes, not run)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -109,50 +146,46 @@ def main():
         return
 
     from paper_1806_03761_amd import peps
-    from paper_1806_03761_amd.workloads import make_workload
+    from paper_1806_03761_amd.workloads import WORKLOADS, make_workload
 
-    name = "8x8_D4_Dc16"
+    name = args.workload
     lat, A, S, _ = make_workload(name, args.batch)
     B = S.shape[0]
     dev = torch.device("cuda:0")
+    peps.set_workspace_limit(200 << 30)
     Ad = torch.from_numpy(A).to(dev)
     Sd = torch.from_numpy(S).to(dev)
     N, D4 = lat.N, lat.D ** 4
     grad = torch.empty((N, 2, D4), dtype=torch.float64, device=dev)
 
-    def step():
-        return peps.evaluate(Ad, Sd, lat, args.prec, grad_mode=3, out=grad)
+    def step(prec=args.prec, Ax=Ad, Sx=Sd, latx=lat, out=grad):
+        return peps.evaluate(Ax, Sx, latx, prec, grad_mode=3, out=out)
 
     tuned = 0
     if not args.no_tune:
         tuned = peps.autotune(Ad, Sd, lat, args.prec)     # untimed: picks GEMM tiles by measurement
+    cpu_h = None
+    if not args.no_cpu_baseline:
+        cpu_h = start_cpu_baseline(name, 1)
     # warm-up steps with every kernel class bracketed by HIP events: the per-class
     # breakdown, and which class dominates
-    classes = ("gemm", "fused", "qr", "svd")
-
-    def read(classes_):
-        out = {}
-        for cls in classes_:
-            kms, n, fl = peps.profile_read(cls)
-            out[cls] = {"ms_total": kms, "launches": n, "avg_us": 1e3 * kms / max(n, 1),
-                        "tflops": fl / max(kms, 1e-12) / 1e9}
-        return out
-
-    peps.profile_enable(classes)
+    peps.profile_enable(CLASSES)
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
-    kern = read(classes)
+    kern = _read(peps, CLASSES)
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    cpu = finish_cpu_baseline(cpu_h, name) if cpu_h else None
     # timed region: only the dominant class is bracketed by events (on the library's
     # stream), which keeps the instrumentation out of the throughput
     peps.profile_enable((dom,))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        res_f64 = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    timed = read((dom,))[dom]
+    timed = _read(peps, (dom,))[dom]
     peps.profile_enable(())
     ms = dt * 1e3 / args.steps
     value = B * args.steps / dt
@@ -170,90 +203,86 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": "8x8 open J1-J2 (J2/J1=0.5), D=4, Dc=16, f32 contraction GEMMs, "
-                               "f64 QR/SVD; amplitude + local energy + dE/dA",
+        "config": {"workload": f"{lat.Lx}x{lat.Ly} open J1-J2 (J2/J1={lat.J2}), D={lat.D}, Dc={lat.Dc}, "
+                               f"{B} samples, {args.prec} contractions and f64 QR/SVD; amplitude + "
+                               f"local energy + dE/dA",
                    "lattice": [lat.Lx, lat.Ly], "D": lat.D, "Dc": lat.Dc, "batch": B,
                    "gemm_precision": args.prec, "factorisation_precision": "f64",
                    "autotuned_gemm_shapes": tuned},
     }
-    # every class runs on the vector ALUs (fma), none on the matrix cores: MI355X vector
-    # peaks fp64 78.6 TFLOP/s, fp32 157.3 TFLOP/s.  The factorisations are fp64; the
-    # contractions compute in fp32 for f32 and bf16 (bf16 only rounds the apply inputs)
-    con_peak = 78.6 if args.prec == "f64" else 157.3
-    peak = 78.6 if dom in ("svd", "qr") else con_peak
-    names = {"svd": "truncation step (k_eig_applyq + k_eig_tridiag + k_eig_tri + k_eig_fin)",
-             "qr": "k_qr_cols", "gemm": "k_gemm / k_gemm_rows", "fused": "k_pair_mfma / k_row_step"}
+    peak = MI355X_PEAK["f64"] if dom in ("svd", "qr") else MI355X_PEAK[args.prec if args.prec != "bf16" else "f32"]
     traffic = None
-    if TRAFFIC["sources"] == _sources_hash() and args.prec == "f32" and B == 4096:
+    if TRAFFIC["sources"] == _sources_hash() and TRAFFIC["workload"] == name and B == WORKLOADS[name].batch:
         traffic = TRAFFIC["bytes_per_launch"].get(dom)
-    res["roofline"] = {"kernel": names[dom], "bound": "alu", "achieved": timed["tflops"],
+    res["roofline"] = {"kernel": CLASS_NAMES[dom], "class": dom, "bound": "mfma", "achieved": timed["tflops"],
                        "peak": peak, "unit": "TFLOP/s", "frac": timed["tflops"] / peak,
-                       "traffic": traffic, "avg_launch_us": timed["avg_us"],
-                       "launches": timed["launches"]}
-    res["kernels_warmup"] = kern
-    if not args.no_mcmc:
-        # Metropolis sampling on the same 4096 chains: one step = proposal, contraction of
-        # W(S') (amplitude only) and the accept/reject of every chain
-        Sm = Sd.clone()
-        la_m, sg_m, _ = peps.log_amplitude(Ad, Sm, lat, args.prec)
-        g = torch.Generator(device=dev)
-        g.manual_seed(7)
-        U = torch.rand((args.steps + 1, B, 2), dtype=torch.float64, device=dev, generator=g)
-        peps.metropolis_step(Ad, Sm, lat, U[0], la_m, sg_m, args.prec)
-        acc = torch.zeros(B, dtype=torch.int64, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            acc += peps.metropolis_step(Ad, Sm, lat, U[k + 1], la_m, sg_m, args.prec)
-        torch.cuda.synchronize()
-        dtm = time.perf_counter() - t0
-        res["mcmc"] = {"value": B * args.steps / dtm, "unit": "chain-steps/s",
-                       "ms_per_step": dtm * 1e3 / args.steps, "chains": B,
-                       "acceptance": acc.sum().item() / (B * args.steps)}
-        # one optimisation-loop iteration: ln|W| of the chains, 4 Metropolis steps, the
-        # sampled energy and gradient over the chains, the GO update of the tensors
-        Av = Ad.clone()
-        n_mc, iters = 4, 2
-        Uv = torch.rand((iters + 1, n_mc, B, 2), dtype=torch.float64, device=dev, generator=g)
-        Pv = torch.rand((iters + 1,) + tuple(Ad.shape), dtype=torch.float64, device=dev, generator=g)
-        peps.vmc_step(Av, Sm, lat, Uv[0], Pv[0], 1e-3, args.prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(iters):
-            Ev, _ = peps.vmc_step(Av, Sm, lat, Uv[k + 1], Pv[k + 1], 1e-3, args.prec)
-        torch.cuda.synchronize()
-        dtv = time.perf_counter() - t0
-        res["vmc"] = {"ms_per_iteration": dtv * 1e3 / iters, "chains": B, "metropolis_steps": n_mc,
-                      "energy": Ev[0].item()}
-    if not args.no_corr:
-        # correlation estimator on the first 1024 samples: <S_i . S_j> over the central
-        # 4x4 block (136 pairs i <= j, the anti-parallel ones contracted in full) and
-        # m^2 at (pi, pi)
-        nb = min(B, 1024)
-        sites = [i * lat.Lx + j for i in range(2, lat.Ly - 2) for j in range(2, lat.Lx - 2)]
-        peps.correlation_matrix(Ad, Sd[:nb], lat, sites, args.prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        C, _ = peps.correlation_matrix(Ad, Sd[:nb], lat, sites, args.prec)
-        m2 = peps.structure_factor(C, lat, sites, [(3.141592653589793, 3.141592653589793)])
-        torch.cuda.synchronize()
-        dtc = time.perf_counter() - t0
-        res["corr"] = {"ms": dtc * 1e3, "samples": nb, "pairs": len(sites) * (len(sites) + 1) // 2,
-                       "samples_per_s": nb / dtc, "m2_pi_pi": m2[0].item()}
-    if not args.no_plain:
-        # plain path: the same library, batch 1, f64 GEMMs, one sample at a time
-        nplain = 8
-        for b in range(2):
+                       "traffic": traffic, "avg_launch_us": timed["avg_us"], "launches": timed["launches"]}
+    # every class against the dtype's matrix-core peak (the factorisations against fp64)
+    res["kernels_warmup"] = {k: dict(v, frac_of_peak=v["tflops"] / (MI355X_PEAK["f64"] if k in ("svd", "qr") else peak))
+                             for k, v in kern.items()}
+    if not args.no_legs:
+        la0, sg0, e0, g0, fl0 = (t.detach().cpu().numpy() for t in res_f64)
+        legs = {}
+        # the same workload with narrower contraction arithmetic: throughput and the error
+        # of every result against the float64 results above (which match the oracle to
+        # 1e-10 on the tested subsets)
+        for pr in ("f32", "bf16"):
+            if pr == args.prec:
+                continue
+            g1 = torch.empty_like(grad)
+            step(pr, out=g1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r1 = step(pr, out=g1)
+            torch.cuda.synchronize()
+            d1 = time.perf_counter() - t1
+            la1, sg1, e1, gg1, fl1 = (t.detach().cpu().numpy() for t in r1)
+            ok = (fl0 == 0) & (fl1 == 0)
+            legs[pr] = {"samples_per_s": B / d1, "ms_per_step": d1 * 1e3,
+                        "err_log_amp_vs_f64": _rel_errors(la1[ok], la0[ok]),
+                        "sign_mismatches": int((sg1[ok] != sg0[ok]).sum()),
+                        "err_e_loc_vs_f64": _rel_errors(e1[ok], e0[ok]),
+                        "err_grad_rel_l2_vs_f64": float(np.linalg.norm(gg1 - g0) / np.linalg.norm(g0))}
+        # plain path: the same library at batch 1, float64, one sample at a time
+        nplain = 2
+        for b in range(1):
             peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         for b in range(nplain):
             peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
         torch.cuda.synchronize()
-        res["plain"] = {"value": nplain / (time.perf_counter() - t0), "unit": "samples/s",
-                        "sample": f"{nplain} samples one at a time, f64 GEMMs"}
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(name)
+        legs["plain"] = {"value": nplain / (time.perf_counter() - t1), "unit": "samples/s",
+                         "sample": f"{nplain} samples one at a time, f64, batch 1"}
+        # the 8x8, D = 4, Dc = 16 workload (4096 samples), float64 and float32
+        lat2, A2, S2, _ = make_workload("8x8_D4_Dc16")
+        A2d, S2d = torch.from_numpy(A2).to(dev), torch.from_numpy(S2).to(dev)
+        g2 = torch.empty((lat2.N, 2, lat2.D ** 4), dtype=torch.float64, device=dev)
+        for pr in ("f64", "f32"):
+            peps.autotune(A2d, S2d, lat2, pr)
+            step(pr, A2d, S2d, lat2, g2)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                step(pr, A2d, S2d, lat2, g2)
+            torch.cuda.synchronize()
+            legs["8x8_D4_Dc16_" + pr] = {"samples_per_s": 5 * S2.shape[0] / (time.perf_counter() - t1),
+                                         "batch": int(S2.shape[0])}
+        del A2d, S2d, g2
+        # 24x24, D = 8, Dc = 64: one step over the first 8 of its 512 samples
+        lat4, A4, S4, _ = make_workload("24x24_D8_Dc64", 8)
+        A4d, S4d = torch.from_numpy(A4).to(dev), torch.from_numpy(S4).to(dev)
+        g4 = torch.empty((lat4.N, 2, lat4.D ** 4), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step("f64", A4d, S4d, lat4, g4)
+        torch.cuda.synchronize()
+        legs["24x24_D8_Dc64_f64"] = {"samples_per_s": S4.shape[0] / (time.perf_counter() - t1),
+                                     "sample": "first 8 of the 512 configurations, one step (includes "
+                                               "first-use workspace set-up)"}
+        res["legs"] = legs
+    if cpu:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 

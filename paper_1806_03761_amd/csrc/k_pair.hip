@@ -25,7 +25,6 @@ namespace peps {
 
 static constexpr int kPD = 4;    // PEPS legs (horizontal and vertical) of the fused path
 static constexpr int kPX = 16;   // boundary bonds of the fused path
-static constexpr int kPairLds = 2 * 1024 + 8192;   // floats
 
 bool pair_step_fits(const PairArgs& a) {
     const int legs[5] = {a.h, a.h1, a.Du, a.Dm, a.Dq};
@@ -34,7 +33,7 @@ bool pair_step_fits(const PairArgs& a) {
         if (v < 1 || v > kPD) return false;
     for (int v : bonds)
         if (v < 1 || v > kPX) return false;
-    return kPairLds * sizeof(float) <= get_lds_cap() - 1024;
+    return true;
 }
 
 // Site tensors of the whole lattice as float32, zero padded to 4 per leg, in the two
@@ -82,271 +81,9 @@ __device__ inline double step_rescale(double local_max, const double* lin, doubl
     return ok ? 1.0 / m : 1.0;
 }
 
-template <bool FWD>
-__global__ __launch_bounds__(256) void k_pair_step(PairArgs a) {
-    extern __shared__ __align__(16) float sm[];
-    float* Ue = sm;              // upper environment, 16 x 16 x 4
-    float* Le = Ue + 1024;       // lower environment
-    float* Big = Le + 1024;      // incoming partial, later half of the third temporary
-    const int b = blockIdx.x, tid = threadIdx.x;
-    if (b >= a.batch) return;
-    if (a.skip && a.skip[(long long)b * a.skip_bs] == 0) return;
-    const int cu = a.cu, cu1 = a.cu1, cl = a.cl, cl1 = a.cl1;
-    const int Du = a.Du, Dq = a.Dq, h = a.h, h1 = a.h1;
-    const double* X = a.X + (long long)b * a.xs;
-    const double* U = a.U + (long long)b * a.us;
-    const double* L = a.L + (long long)b * a.ls;
-    // block-uniform site tables: FWD reads the natural order, BWD the second one
-    const float* S1 = a.site1 + (long long)((a.sel1[(long long)b * a.sel_bs] ^ a.flip1) & 1) * 512 + (FWD ? 0 : 256);
-    const float* S2 = a.site2 + (long long)((a.sel2[(long long)b * a.sel_bs] ^ a.flip2) & 1) * 512 + (FWD ? 0 : 256);
-
-    // ---- staging (float32, zero padded) ----
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {   // constant trip count: all loads issued together
-        const int e = tid + 256 * it;
-        int c, u, cp;
-        if (FWD) { c = e >> 6; cp = (e >> 2) & 15; u = e & 3; }     // Ue[c][c'][u]
-        else { u = e >> 8; cp = (e >> 4) & 15; c = e & 15; }        // Ue[u][c'][c]
-        Ue[e] = (float)ld_or0(c < cu && u < Du && cp < cu1, U, ((long long)c * Du + u) * cu1 + cp);
-        int l, q, lp;
-        if (FWD) { l = e >> 6; q = (e >> 4) & 3; lp = e & 15; }     // Le[l][q][l']
-        else { lp = e >> 6; l = (e >> 2) & 15; q = e & 3; }         // Le[l'][l][q]
-        Le[e] = (float)ld_or0(l < cl && q < Dq && lp < cl1, L, ((long long)l * Dq + q) * cl1 + lp);
-    }
-#pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const int e = tid + 256 * it;
-        if (FWD) {   // Big[c][l][b][b'] = P[c][b][b'][l]
-            const int c = e >> 8, l = (e >> 4) & 15, bb = (e >> 2) & 3, bp = e & 3;
-            Big[e] = (float)ld_or0(c < cu && l < cl && bb < h && bp < h, X, (long long)c * h * h * cl + ((long long)bb * h + bp) * cl + l);
-        } else {     // Big[l'][c'][a][a'] = Q[c'][a][a'][l']
-            const int lp = e >> 8, cp = (e >> 4) & 15, aa = (e >> 2) & 3, ap = e & 3;
-            Big[e] = (float)ld_or0(lp < cl1 && cp < cu1 && aa < h1 && ap < h1, X, (((long long)cp * h1 + aa) * h1 + ap) * cl1 + lp);
-        }
-    }
-    __syncthreads();
-
-    // ---- three contractions with the slice of thread (l, c') in registers ----
-    const int l = tid >> 4, cp = tid & 15;
-    float T1[kPD][kPD][kPD], T2[kPD][kPD][kPD];
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y)
-#pragma unroll
-            for (int z = 0; z < kPD; ++z) T1[x][y][z] = 0.f;
-    if (FWD) {
-        // T1[b][b'][u] = sum_c P[c][b][b'][l] U[c][u][c']
-        float4 pn[kPD], un;   // operands of the next c, loaded one iteration ahead
-#pragma unroll
-        for (int x = 0; x < kPD; ++x) pn[x] = ld4(Big + (l * kPD + x) * kPD);
-        un = ld4(Ue + cp * kPD);
-        for (int c = 0; c < cu; ++c) {
-            float pv[kPD][kPD];
-#pragma unroll
-            for (int x = 0; x < kPD; ++x) {
-                pv[x][0] = pn[x].x; pv[x][1] = pn[x].y; pv[x][2] = pn[x].z; pv[x][3] = pn[x].w;
-            }
-            const float uv[kPD] = {un.x, un.y, un.z, un.w};
-            if (c + 1 < cu) {
-#pragma unroll
-                for (int x = 0; x < kPD; ++x) pn[x] = ld4(Big + (((c + 1) * kPX + l) * kPD + x) * kPD);
-                un = ld4(Ue + ((c + 1) * kPX + cp) * kPD);
-            }
-#pragma unroll
-            for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                for (int y = 0; y < kPD; ++y)
-#pragma unroll
-                    for (int z = 0; z < kPD; ++z) T1[x][y][z] = fmaf(pv[x][y], uv[z], T1[x][y][z]);
-        }
-    } else {
-        // T1[q][a][a'] = sum_l' L[l][q][l'] Q[c'][a][a'][l']
-        float4 qn[kPD], ln;
-#pragma unroll
-        for (int x = 0; x < kPD; ++x) qn[x] = ld4(Big + (cp * kPD + x) * kPD);
-        ln = ld4(Le + l * kPD);
-        for (int lp = 0; lp < cl1; ++lp) {
-            float qv[kPD][kPD];
-#pragma unroll
-            for (int x = 0; x < kPD; ++x) {
-                qv[x][0] = qn[x].x; qv[x][1] = qn[x].y; qv[x][2] = qn[x].z; qv[x][3] = qn[x].w;
-            }
-            const float lv[kPD] = {ln.x, ln.y, ln.z, ln.w};
-            if (lp + 1 < cl1) {
-#pragma unroll
-                for (int x = 0; x < kPD; ++x) qn[x] = ld4(Big + (((lp + 1) * kPX + cp) * kPD + x) * kPD);
-                ln = ld4(Le + ((lp + 1) * kPX + l) * kPD);
-            }
-#pragma unroll
-            for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                for (int y = 0; y < kPD; ++y)
-#pragma unroll
-                    for (int z = 0; z < kPD; ++z) T1[x][y][z] = fmaf(lv[x], qv[y][z], T1[x][y][z]);
-        }
-    }
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y)
-#pragma unroll
-            for (int z = 0; z < kPD; ++z) T2[x][y][z] = 0.f;
-    // FWD: T2[b'][a][m] = sum_{b,u} T1[b][b'][u] S1[b][u][a][m]
-    // BWD: T2[b'][m][a] = sum_{a',q} S2[a'][q][b'][m] T1[q][a][a']   (S2 in the second order)
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y) {
-            const float* sp = (FWD ? S1 : S2) + (x * kPD + y) * 16;
-#pragma unroll
-            for (int p = 0; p < kPD; ++p)
-#pragma unroll
-                for (int r = 0; r < kPD; ++r)
-#pragma unroll
-                    for (int s = 0; s < kPD; ++s) {
-                        const float sv = sp[r * kPD + s];
-                        if (FWD) T2[p][r][s] = fmaf(T1[x][p][y], sv, T2[p][r][s]);
-                        else T2[r][s][p] = fmaf(sv, T1[y][p][x], T2[r][s][p]);
-                    }
-        }
-    // the third temporary reuses T1
-    // FWD: T3[a][a'][q] = sum_{b',m} T2[b'][a][m] S2[b'][m][a'][q]
-    // BWD: T3[b][u][b'] = sum_{a,m} S1[a][m][b][u] T2[b'][m][a]     (S1 in the second order)
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y)
-#pragma unroll
-            for (int z = 0; z < kPD; ++z) T1[x][y][z] = 0.f;
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y) {
-            const float* sp = (FWD ? S2 : S1) + (x * kPD + y) * 16;
-#pragma unroll
-            for (int p = 0; p < kPD; ++p)
-#pragma unroll
-                for (int r = 0; r < kPD; ++r)
-#pragma unroll
-                    for (int s = 0; s < kPD; ++s) {
-                        const float sv = sp[r * kPD + s];
-                        if (FWD) T1[p][r][s] = fmaf(T2[x][p][y], sv, T1[p][r][s]);
-                        else T1[r][s][p] = fmaf(sv, T2[p][y][x], T1[r][s][p]);
-                    }
-        }
-    // ---- last contraction, each thread a 4 x 4 block of outputs, over the third
-    // temporary staged in LDS in two halves of its contracted index (l forward, u
-    // backward; the halves keep the ascending order of every sum) ----
-    float acc[kPD][kPD];
-#pragma unroll
-    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-        for (int y = 0; y < kPD; ++y) acc[x][y] = 0.f;
-    const int c2 = tid >> 4, aa = (tid >> 2) & 3, lg = tid & 3;        // FWD roles
-    const int bb = tid >> 6, l2 = (tid >> 2) & 15, cg = tid & 3;        // BWD roles
-    for (int half = 0; half < 2; ++half) {
-        __syncthreads();   // the previous readers of Big are done
-        if (FWD) {
-            // Big[l - 8 half][q][c'][a][a']
-            if ((l >> 3) == half) {
-#pragma unroll
-                for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                    for (int q = 0; q < kPD; ++q)
-                        *reinterpret_cast<float4*>(Big + (((l & 7) * kPD + q) * kPX + cp) * 16 + x * kPD) =
-                            make_float4(T1[x][0][q], T1[x][1][q], T1[x][2][q], T1[x][3][q]);
-            }
-        } else {
-            // Big[u - 2 half][c'][l][b][b']
-#pragma unroll
-            for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    *reinterpret_cast<float4*>(Big + ((y * kPX + cp) * kPX + l) * 16 + x * kPD) =
-                        make_float4(T1[x][y + 2 * half][0], T1[x][y + 2 * half][1], T1[x][y + 2 * half][2],
-                                    T1[x][y + 2 * half][3]);
-        }
-        __syncthreads();
-        if (FWD) {
-            // Pout[c'][a][a'][l'] = sum_{l,q} T3[l][c'][a][a'][q] L[l][q][l']
-            const int lend = cl < 8 * half + 8 ? cl : 8 * half + 8;
-            for (int lw = 8 * half; lw < lend; ++lw) {
-                float4 t[kPD], lv[kPD];
-#pragma unroll
-                for (int q = 0; q < kPD; ++q) {
-                    t[q] = ld4(Big + (((lw & 7) * kPD + q) * kPX + c2) * 16 + aa * kPD);
-                    lv[q] = ld4(Le + (lw * kPD + q) * kPX + lg * kPD);
-                }
-#pragma unroll
-                for (int q = 0; q < kPD; ++q) {
-                    const float tv[kPD] = {t[q].x, t[q].y, t[q].z, t[q].w};
-                    const float wv[kPD] = {lv[q].x, lv[q].y, lv[q].z, lv[q].w};
-#pragma unroll
-                    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                        for (int y = 0; y < kPD; ++y) acc[x][y] = fmaf(tv[x], wv[y], acc[x][y]);
-                }
-            }
-        } else {
-            // Qout[c][b][b'][l] = sum_{u,c'} U[c][u][c'] T3[b][u][b'][l][c']
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                const int u = y + 2 * half;
-                for (int cc = 0; cc < cu1; ++cc) {
-                    const float4 t = ld4(Big + ((y * kPX + cc) * kPX + l2) * 16 + bb * kPD);
-                    const float4 uv = ld4(Ue + (u * kPX + cc) * kPX + cg * kPD);
-                    const float tv[kPD] = {t.x, t.y, t.z, t.w}, wv[kPD] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-                    for (int x = 0; x < kPD; ++x)
-#pragma unroll
-                        for (int z = 0; z < kPD; ++z) acc[x][z] = fmaf(wv[z], tv[x], acc[x][z]);
-                }
-            }
-        }
-    }
-    double* Y = a.Y + (long long)b * a.ys;
-    double scale = 1.0;
-    if (a.lout) {
-        // padding entries are exact zeros, so the max over all of acc is the sample's max
-        double mx = 0.0;
-#pragma unroll
-        for (int x = 0; x < kPD; ++x)
-#pragma unroll
-            for (int y = 0; y < kPD; ++y) mx = fmax(mx, fabs((double)acc[x][y]));
-        __shared__ double red[4];
-        scale = step_rescale(mx, a.lin, a.lout, b, red);
-    }
-    if (FWD) {
-        if (c2 < cu1 && aa < h1) {
-#pragma unroll
-            for (int x = 0; x < kPD; ++x) {
-                if (x >= h1) break;
-                double* yo = Y + (((long long)c2 * h1 + aa) * h1 + x) * cl1;
-#pragma unroll
-                for (int y = 0; y < kPD; ++y)
-                    if (lg * kPD + y < cl1) yo[lg * kPD + y] = (double)acc[x][y] * scale;
-            }
-        }
-    } else {
-        if (bb < h && l2 < cl) {
-            const long long ms = (long long)h * h * cl;
-#pragma unroll
-            for (int y = 0; y < kPD; ++y) {
-                const int c = cg * kPD + y;
-                if (c >= cu) break;
-#pragma unroll
-                for (int x = 0; x < kPD; ++x)
-                    if (x < h) Y[(long long)c * ms + ((long long)bb * h + x) * cl + l2] = (double)acc[x][y] * scale;
-            }
-        }
-    }
-}
-
 // Fused single-row sandwich step (three GEMMs: environment, site, environment) in
-// float32, same scheme as the two-row step: thread (l, c') holds its D^2 slices of the
-// two temporaries in registers, the last contraction goes through LDS, every sum keeps
-// the order of its unfused GEMM.
+// float32: thread (l, c') holds its D^2 slices of the two temporaries in registers,
+// the last contraction goes through LDS, every sum keeps the order of its unfused GEMM.
 //   FWD: P[c][b][l] -> Pout[c'][a][l'];  BWD: Q[c'][a][l'] -> Qout[c][b][l]
 //   U[c][u][c'], L[l][d][l'], S[b][u][a][d] site (i,j) (left, up, right, down).
 static constexpr int kRowLds = 3 * 1024 + 4096;   // floats
@@ -545,13 +282,14 @@ hipError_t launch_row_step(const RowArgs& a, bool fwd, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// The two-row step on the matrix cores: the same four contractions as k_pair_step,
-// as 16x16x4 float32 MFMA tiles.  A 16x16x4 MFMA accumulates its four products into
+// The fused two-row step on the matrix cores: the four contractions of the unfused
+// chain (upper environment, two site tensors, lower environment) as 16x16x4 float32
+// MFMA tiles.  A 16x16x4 MFMA accumulates its four products into
 // each output in k order with one rounding per product, like a chain of fma, so a
-// 16-long sum split over four MFMAs keeps the ascending order of the vector form when
-// MFMA s takes k = 4s .. 4s+3, i.e. lane (i, g) supplies k = 4s + g as element s of its
-// operand.  Sums longer than 16 chain the MFMAs block by block, and padding adds exact
-// zeros, so every output is the vector form's value bit for bit.
+// 16-long sum split over four MFMAs keeps ascending k order when MFMA s takes
+// k = 4s .. 4s+3, i.e. lane (i, g) supplies k = 4s + g as element s of its operand.
+// Sums longer than 16 chain the MFMAs block by block, and padding adds exact zeros, so
+// every output is the unfused GEMM chain's value bit for bit.
 //
 // Work split (one sample per workgroup, four waves): a free bond is taken in chunks of
 // four (c' forward, l backward: free through all four contractions), and inside a
@@ -803,16 +541,10 @@ __global__ __launch_bounds__(256, FWD ? 4 : 3) void k_pair_mfma(PairArgs a) {
 hipError_t launch_pair_step(const PairArgs& a, bool fwd, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (!pair_step_fits(a)) return hipErrorInvalidValue;
-    if (a.mfma) {
-        const size_t mb = (fwd ? pair_mfma_lds<true>() : pair_mfma_lds<false>()) * sizeof(float);
-        if (mb + 64 > get_lds_cap()) return hipErrorInvalidValue;
-        if (fwd) hipLaunchKernelGGL(k_pair_mfma<true>, dim3(a.batch), dim3(256), mb, st, a);
-        else hipLaunchKernelGGL(k_pair_mfma<false>, dim3(a.batch), dim3(256), mb, st, a);
-        return hipGetLastError();
-    }
-    const size_t bytes = kPairLds * sizeof(float);
-    if (fwd) hipLaunchKernelGGL(k_pair_step<true>, dim3(a.batch), dim3(256), bytes, st, a);
-    else hipLaunchKernelGGL(k_pair_step<false>, dim3(a.batch), dim3(256), bytes, st, a);
+    const size_t mb = (fwd ? pair_mfma_lds<true>() : pair_mfma_lds<false>()) * sizeof(float);
+    if (mb + 64 > get_lds_cap()) return hipErrorInvalidValue;
+    if (fwd) hipLaunchKernelGGL(k_pair_mfma<true>, dim3(a.batch), dim3(256), mb, st, a);
+    else hipLaunchKernelGGL(k_pair_mfma<false>, dim3(a.batch), dim3(256), mb, st, a);
     return hipGetLastError();
 }
 

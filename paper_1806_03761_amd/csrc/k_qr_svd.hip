@@ -4,11 +4,6 @@
 //            one workgroup per matrix, column-major, LDS-resident when it fits.
 //            The reflectors stay in X (below the diagonal) for the later
 //            implicit application of Q; R is written to its own buffer.
-//  k_svd     centre formation Z = Q G (implicit Q, reflectors applied in reverse)
-//            followed by a one-sided (Hestenes) Jacobi SVD of Z reshaped to
-//            (left bond) x (phys, right bond); the t = min(Dc, rows, cols)
-//            leading right singular vectors become the new boundary tensor and
-//            U_t Sigma_t is carried to the next column on the left.
 //  k_center0 the same centre formation for the first column, then the norm is
 //            pulled out into the running log scale.
 #include "common.h"
@@ -17,7 +12,6 @@
 namespace peps {
 
 static constexpr int NT = 256;
-static constexpr double kTiny = 1e-292;    // squared-norm floor of the Jacobi rotations
 
 __device__ inline double wave_sum(double v, int width) { return lane_group_sum(v, width); }
 
@@ -500,226 +494,6 @@ __device__ void form_center(const double* V, const double* tau, const double* G,
     if (V) apply_q(V, tau, mz, r, Z, ldz, tin, vbuf);
 }
 
-// ---------------------------------------------------------------------------
-// SVD truncation step
-// ---------------------------------------------------------------------------
-// Modes:  V != nullptr: Z = Q G (Q from reflectors V/tau, G row-major r x tin)
-//         V == nullptr: Z = G read as a column-major mz x tin matrix (tin = 1 here)
-// M = Z reshaped to m' x n' with m' = mz/p, n' = p*tin, M[a][d*tin+t] = Z[a*p+d][t].
-// Outputs: newU row-major tk x n' (new boundary tensor (tk, p, tin)), Gout row-major
-// m' x tk (U_t Sigma_t).  tk = min(Dc, m', n').
-//   m' >  n': one-sided Jacobi on the columns of M with the rotations accumulated
-//             in J (= V); U_t Sigma_t are the rotated columns.
-//   m' <= n': one-sided Jacobi on the columns of M^T (no accumulation): they
-//             become sigma_k v_k; U_t Sigma_t = M V_t is formed at the end.
-struct SvdArgs {
-    const double* V; long long vs;
-    const double* tau; long long ts;
-    const double* G; long long gs;
-    int mz, r, tin, p, Dc;
-    double* newU; long long us;
-    double* Gout; long long gos;
-    double* scratch; long long ss;   // global scratch when LDS is too small
-    int use_lds, max_sweeps;
-    int8_t* flags;                    // set to 3 when Jacobi does not converge
-};
-
-struct SvdLayout {
-    int mp, np, caseA, len, cnt, ldz, ldx, ldj;
-    long long oZ, oX, oJ, oV, oS, oP, total;   // offsets in doubles
-};
-
-__host__ __device__ inline SvdLayout svd_layout(int mz, int tin, int p) {
-    SvdLayout L;
-    L.mp = mz / p;
-    L.np = p * tin;
-    L.caseA = L.mp > L.np;
-    L.len = L.caseA ? L.mp : L.np;
-    L.cnt = L.caseA ? L.np : L.mp;
-    L.ldz = mz + pad_for(tpc_for(tin));
-    const int npairs = (L.cnt + (L.cnt & 1)) / 2;
-    const int tpp = tpc_for(npairs);
-    L.ldx = L.len + pad_for(tpp);
-    L.ldj = L.caseA ? L.cnt + pad_for(tpp) : 0;
-    L.oZ = 0;
-    L.oX = L.oZ + (long long)L.ldz * tin;
-    L.oJ = L.oX + (long long)L.ldx * L.cnt;
-    L.oV = L.oJ + (long long)L.ldj * L.cnt;
-    L.oS = L.oV + mz;
-    L.oP = L.oS + L.cnt;
-    L.total = L.oP + (L.cnt + 1) / 2 + 2;
-    return L;
-}
-
-__global__ __launch_bounds__(NT) void k_svd(SvdArgs a) {
-    extern __shared__ double lds[];
-    __shared__ double red[NT / 64];
-    __shared__ int s_rot;
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int mz = a.mz, tin = a.tin, p = a.p;
-    const SvdLayout L = svd_layout(mz, tin, p);
-    const int mp = L.mp, np = L.np, len = L.len, cnt = L.cnt, ldx = L.ldx, ldj = L.ldj, ldz = L.ldz;
-    const bool caseA = L.caseA;
-    const int tk = min(a.Dc, cnt);
-    double* base = a.use_lds ? lds : a.scratch + (long long)b * a.ss;
-    double* Z = base + L.oZ;
-    double* X = base + L.oX;
-    double* J = base + L.oJ;
-    double* vbuf = base + L.oV;
-    double* sig = base + L.oS;
-    int* perm = (int*)(base + L.oP);
-
-    form_center(a.V ? a.V + (long long)b * a.vs : nullptr, a.tau + (long long)b * a.ts,
-                a.G + (long long)b * a.gs, mz, a.V ? a.r : mz, tin, Z, ldz, vbuf);
-    // X = M (case A) or M^T, column-major with stride ldx; M[ar][d*tin+t] = Z[t][ar*p+d]
-    for (int e = tid; e < mz * tin; e += NT) {
-        const int t = e / mz, i = e % mz;
-        const int ar = i / p, d = i % p;
-        const int col = d * tin + t;
-        const double v = Z[(long long)t * ldz + i];
-        if (caseA) X[(long long)col * ldx + ar] = v;
-        else X[(long long)ar * ldx + col] = v;
-    }
-    __syncthreads();
-    // exact power-of-two prescale so that the largest entry is in [0.5, 1): the
-    // underflow floor below is then relative to the matrix
-    int ex = 0;
-    {
-        double mx = 0.0;
-        for (int e = tid; e < len * cnt; e += NT) mx = fmax(mx, fabs(X[(e / len) * ldx + e % len]));
-        mx = block_max(mx, red);
-        if (mx > 0.0 && isfinite(mx)) frexp(mx, &ex);
-        for (int e = tid; e < len * cnt; e += NT) {
-            double* x = X + (e / len) * ldx + e % len;
-            *x = ldexp(*x, -ex);
-        }
-    }
-    if (caseA)
-        for (int e = tid; e < cnt * cnt; e += NT) J[(e / cnt) * ldj + e % cnt] = ((e / cnt) == (e % cnt)) ? 1.0 : 0.0;
-    __syncthreads();
-
-    const int cpad = cnt + (cnt & 1);
-    const int npairs = cpad / 2;
-    const int tpp = tpc_for(npairs);
-    const int ngroups = NT / tpp;
-    const int g = tid / tpp, l = tid % tpp;
-    const double tol = 2.220446049250313e-16 * sqrt((double)len);
-    int sweep = 0;
-    for (; sweep < a.max_sweeps; ++sweep) {
-        if (tid == 0) s_rot = 0;
-        __syncthreads();
-        for (int rd = 0; rd < cpad - 1; ++rd) {
-            for (int p0 = 0; p0 < npairs; p0 += ngroups) {
-                const int pi = p0 + g;
-                int cp = -1, cq = -1;
-                if (pi < npairs) {
-                    const int k1 = pi, k2 = cpad - 1 - pi;
-                    cp = (k1 == 0) ? 0 : ((k1 - 1 + rd) % (cpad - 1)) + 1;
-                    cq = (k2 == 0) ? 0 : ((k2 - 1 + rd) % (cpad - 1)) + 1;
-                    if (cp >= cnt || cq >= cnt) cp = cq = -1;
-                }
-                const bool act = cp >= 0;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                double* xp = X + (long long)(act ? cp : 0) * ldx;
-                double* xq = X + (long long)(act ? cq : 0) * ldx;
-                if (act) {
-                    for (int i = l; i < len; i += tpp) {
-                        const double u = xp[i], v = xq[i];
-                        al += u * u;
-                        be += v * v;
-                        ga += u * v;
-                    }
-                }
-                al = wave_sum(al, tpp);
-                be = wave_sum(be, tpp);
-                ga = wave_sum(ga, tpp);
-                // sqrt(al)*sqrt(be), not sqrt(al*be): the product underflows for tiny
-                // columns.  Pairs with a squared column norm below 1e-292 of the largest
-                // entry squared are left alone: their contribution to the state is below
-                // 1e-146 and their rotations cannot be resolved.
-                if (act && al > kTiny && be > kTiny && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    // smaller root of t^2 + 2 zeta t - 1 = 0; for |zeta| > 1e150 zeta^2
-                    // would overflow and t = 1/(2 zeta) to working precision
-                    const double t = fabs(zeta) > 1e150
-                                         ? 0.5 / zeta
-                                         : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    for (int i = l; i < len; i += tpp) {
-                        const double u = xp[i], v = xq[i];
-                        xp[i] = c * u - s * v;
-                        xq[i] = s * u + c * v;
-                    }
-                    if (caseA) {
-                        double* jp = J + (long long)cp * ldj;
-                        double* jq = J + (long long)cq * ldj;
-                        for (int i = l; i < cnt; i += tpp) {
-                            const double u = jp[i], v = jq[i];
-                            jp[i] = c * u - s * v;
-                            jq[i] = s * u + c * v;
-                        }
-                    }
-                    if (l == 0 && s != 0.0) s_rot = 1;   // an underflowed rotation changes nothing
-                }
-            }
-            __syncthreads();
-        }
-        if (s_rot == 0) break;
-        __syncthreads();
-    }
-    if (sweep == a.max_sweeps && tid == 0 && a.flags && a.flags[b] == 0) a.flags[b] = 3;
-
-    // singular values (of the prescaled matrix) and descending order (ties by index)
-    for (int k = tid; k < cnt; k += NT) {
-        const double* xk = X + (long long)k * ldx;
-        double s2 = 0.0;
-        for (int i = 0; i < len; ++i) s2 += xk[i] * xk[i];
-        sig[k] = sqrt(s2);
-    }
-    __syncthreads();
-    for (int k = tid; k < cnt; k += NT) {
-        int rank = 0;
-        const double sk = sig[k];
-        for (int j = 0; j < cnt; ++j) rank += (sig[j] > sk) || (sig[j] == sk && j < k);
-        perm[rank] = k;
-    }
-    __syncthreads();
-    double* U = a.newU + (long long)b * a.us;
-    double* Go = a.Gout + (long long)b * a.gos;
-    if (caseA) {
-        // V = J (np x np), U_t Sigma_t = rotated columns of M (mp)
-        for (int e = tid; e < tk * np; e += NT) {
-            const int rr = e / np, c = e % np;
-            U[e] = J[(long long)perm[rr] * ldj + c];
-        }
-        for (int e = tid; e < mp * tk; e += NT) {
-            const int i = e / tk, rr = e % tk;
-            Go[e] = ldexp(X[(long long)perm[rr] * ldx + i], ex);
-        }
-    } else {
-        // columns of X = M^T are sigma_k v_k: V_t = normalised columns; then U_t Sigma_t = M V_t
-        for (int e = tid; e < tk * np; e += NT) {
-            const int rr = e / np, c = e % np;
-            const int k = perm[rr];
-            const double s = sig[k];
-            const double v = s > 0.0 ? X[(long long)k * ldx + c] / s : 0.0;
-            U[e] = v;
-            X[(long long)k * ldx + c] = v;     // keep V_t in place for the product below
-        }
-        __syncthreads();
-        for (int e = tid; e < mp * tk; e += NT) {
-            const int ar = e / tk, rr = e % tk;
-            const double* vk = X + (long long)perm[rr] * ldx;
-            double acc = 0.0;
-            for (int d = 0; d < p; ++d) {
-                const double* zrow = Z + ar * p + d;   // Z[t][ar*p+d] = M[ar][d*tin+t]
-                for (int t = 0; t < tin; ++t) acc += zrow[(long long)t * ldz] * vk[d * tin + t];
-            }
-            Go[e] = acc;
-        }
-    }
-}
-
 // First column: Z = Q_0 G_1 (mz x tin), nu = ||Z||, newU_0 = Z / nu (row-major mz x tin),
 // logs[b] = logs_in[b] + ln nu.
 __global__ __launch_bounds__(NT) void k_center0(const double* V, long long vs, const double* tau,
@@ -772,24 +546,6 @@ hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long
     const int use = bytes <= lds_cap() - 1024;
     hipLaunchKernelGGL(k_qr, dim3(batch), dim3(NT), use ? bytes : 0, st, X, xs, m, n, R, rs, tau,
                        ts, use);
-    return hipGetLastError();
-}
-
-size_t svd_scratch_doubles(int mz, int tin, int p) { return (size_t)svd_layout(mz, tin, p).total; }
-
-hipError_t launch_svd(const double* V, long long vs, const double* tau, long long ts,
-                      const double* G, long long gs, int mz, int r, int tin, int p, int Dc,
-                      double* newU, long long us, double* Gout, long long gos, double* scratch,
-                      long long ss, int8_t* flags, int batch, hipStream_t st) {
-    if (batch <= 0) return hipSuccess;
-    SvdArgs a;
-    a.V = V; a.vs = vs; a.tau = tau; a.ts = ts; a.G = G; a.gs = gs;
-    a.mz = mz; a.r = r; a.tin = tin; a.p = p; a.Dc = Dc;
-    a.newU = newU; a.us = us; a.Gout = Gout; a.gos = gos;
-    a.scratch = scratch; a.ss = ss; a.max_sweeps = 40; a.flags = flags;
-    const size_t bytes = svd_scratch_doubles(mz, tin, p) * sizeof(double);
-    a.use_lds = bytes <= lds_cap() - 1024;
-    hipLaunchKernelGGL(k_svd, dim3(batch), dim3(NT), a.use_lds ? bytes : 0, st, a);
     return hipGetLastError();
 }
 

@@ -24,11 +24,6 @@ bool launch_qr_cols(double* X, long long xs, int m, int n, double* R, long long 
                     long long ts, int batch, int tpc, int wg, hipStream_t st);
 hipError_t launch_qr(double* X, long long xs, int m, int n, double* R, long long rs, double* tau,
                      long long ts, int batch, hipStream_t st);
-size_t svd_scratch_doubles(int mz, int tin, int p);
-hipError_t launch_svd(const double* V, long long vs, const double* tau, long long ts,
-                      const double* G, long long gs, int mz, int r, int tin, int p, int Dc,
-                      double* newU, long long us, double* Gout, long long gos, double* scratch,
-                      long long ss, int8_t* flags, int batch, hipStream_t st);
 size_t center0_scratch_doubles(int mz, int tin);
 hipError_t launch_center0(const double* V, long long vs, const double* tau, long long ts,
                           const double* G, long long gs, int mz, int r, int tin, double* newU,
@@ -94,7 +89,6 @@ struct PairArgs {
     double* Y; long long ys;             // outgoing partial
     const double* lin; double* lout;     // lout != nullptr: max-abs rescale, log into lout
     int batch;
-    int mfma;                            // 1: the matrix-core form (float32 MFMA)
     const int8_t* skip = nullptr;        // sample b skipped when skip[b * skip_bs] == 0
     long long skip_bs = 0;
 };

@@ -114,15 +114,9 @@ public:
         // environment-tensor GEMMs then run in f32 (f32 and f64 use one type throughout)
         ar = prec == PEPS_PREC_F64 ? Arith::F64 : (prec == PEPS_PREC_F32 ? Arith::F32 : Arith::BF16);
         ar_sw = prec == PEPS_PREC_F64 ? Arith::F64 : Arith::F32;
-        const char* sv = getenv("PEPS_SVD");
-        use_eig = !(sv && strcmp(sv, "jacobi") == 0);
         // fused single- and two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the GEMM form)
         const char* fz = getenv("PEPS_FUSE");
         fuse_pairs = ar_sw == Arith::F32 && D <= 4 && !(fz && strcmp(fz, "0") == 0);
-        // the two-row step on the matrix cores (PEPS_PAIR=valu keeps the vector form,
-        // which matches the GEMM path bit for bit)
-        const char* pz = getenv("PEPS_PAIR");
-        pair_mfma = !(pz && strcmp(pz, "valu") == 0);
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -202,10 +196,8 @@ public:
                 s_G = std::max(s_G, (long long)t.rho[j] * t.tau[j]);
                 const int tin = t.tau[j + 1];
                 const long long mz = rows;
-                size_t sc = (j == 0) ? center0_scratch_doubles((int)mz, tin)
-                                     : svd_scratch_doubles((int)mz, tin, t.p);
-                if ((j == 0 || !use_eig) && sc * sizeof(double) > lds_cap_bytes())
-                    s_svd = std::max<long long>(s_svd, sc);
+                const size_t sc = center0_scratch_doubles((int)mz, tin);
+                if (j == 0 && sc * sizeof(double) > lds_cap_bytes()) s_svd = std::max<long long>(s_svd, sc);
             }
         };
         for (int i = 0; i + 1 < Ly; ++i) visit(tU[i]);
@@ -230,14 +222,10 @@ public:
                 s_eig = std::max<long long>(s_eig, (long long)eig_scratch_doubles(mz, tin, t.p, Dc));
             }
         };
-        if (use_eig) {
-            for (int i = 0; i + 1 < Ly; ++i) visit_eig(tU[i]);
-            if (need_L)
-                for (int i = Ly - 1; i >= 1; --i) visit_eig(tL[i]);
-            o_eig = L.alloc(s_eig);
-        } else {
-            o_eig = 0;
-        }
+        for (int i = 0; i + 1 < Ly; ++i) visit_eig(tU[i]);
+        if (need_L)
+            for (int i = Ly - 1; i >= 1; --i) visit_eig(tL[i]);
+        o_eig = L.alloc(s_eig);
         // single-row partials
         s_P.assign(Lx + 1, 1);
         for (int i = 0; i < Ly; ++i)
@@ -344,7 +332,7 @@ public:
             return hipErrorInvalidValue;
         if (dry) return hipSuccess;
         GemmArgs g;
-        const double fl = 2.0 * M * Nn * K * (double)Bcur;
+        const double fl = 2.0 * M * Nn * K * (double)active_samples();
         g.M = M; g.N = Nn; g.K = K; g.batch = Bcur;
         g.am = am; g.ak = ak; g.bk = bk; g.bn = bn; g.cm = cm; g.cn = cn;
         g.a_bs = A.bs; g.b_bs = B.bs; g.c_bs = C.bs;
@@ -470,13 +458,11 @@ public:
         for (int j = 0; j < Lx; ++j) {
             const long long mz = (long long)t.rho[j] * p;
             const int tin = t.tau[j + 1];
-            const size_t sc = (j == 0) ? center0_scratch_doubles((int)mz, tin)
-                                       : svd_scratch_doubles((int)mz, tin, p);
+            const size_t sc = center0_scratch_doubles((int)mz, tin);
             const bool in_lds = sc * sizeof(double) <= lds_cap_bytes();
             const long long rin = (j + 1 < Lx) ? t.rho[j + 1] : mz;     // rows of G / reflectors
-            bool ok = use_eig ? (j == 0 || (long long)eig_scratch_doubles((int)mz, tin, p, Dc) <= s_eig)
-                              : (in_lds || (long long)sc <= s_svd);
-            if (j == 0) ok = in_lds || (long long)sc <= s_svd;
+            bool ok = j == 0 ? (in_lds || (long long)sc <= s_svd)
+                             : (long long)eig_scratch_doubles((int)mz, tin, p, Dc) <= s_eig;
             ok = ok && mz * (j + 1 < Lx ? t.K[j + 1] : 1) <= s_X[j];
             ok = ok && (j + 1 == Lx || (rin <= s_tau[j] && rin * tin <= s_G));
             ok = ok && (long long)t.rho[j] * t.tau[j] <= s_G;
@@ -493,13 +479,8 @@ public:
             Op Eout = down ? envU(row + 1, j) : envL(row - 1, j);
             const int mz = t.rho[j] * p;
             KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, 0, 1, p, t.tau[j]), [&] {
-                if (use_eig)
-                    return launch_eig(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
-                                      Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_eig), s_eig, Bcur,
-                                      st_);
-                return launch_svd(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
-                                  Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_svd), s_svd, flags(), Bcur,
-                                  st_);
+                return launch_eig(nullptr, 0, buf(o_tau[0]), 0, buf(o_X[j]), s_X[j], mz, mz, 1, p, Dc,
+                                  Eout.p, Eout.bs, buf(o_G[0]), s_G, buf(o_eig), s_eig, Bcur, st_);
             }));
         }
         for (int j = Lx - 2; j >= 1; --j) {
@@ -507,14 +488,9 @@ public:
             const int mz = t.rho[j] * p;
             KL(timed(PEPS_KC_SVD, Bcur * svd_flops(mz, t.rho[j + 1], t.tau[j + 1], p, t.tau[j]), [&] {
                 const bool blocked = use_qrb(mz, t.K[j + 1]);
-                if (use_eig)
-                    return launch_eig(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
-                                      t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs,
-                                      buf(o_G[cur ^ 1]), s_G, buf(o_eig), s_eig, Bcur, st_,
-                                      blocked ? buf(o_wy[j]) : nullptr, s_wy[j]);
-                return launch_svd(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
-                                  t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]),
-                                  s_G, buf(o_svd), s_svd, flags(), Bcur, st_);
+                return launch_eig(buf(o_X[j]), s_X[j], buf(o_tau[j]), s_tau[j], buf(o_G[cur]), s_G, mz,
+                                  t.rho[j + 1], t.tau[j + 1], p, Dc, Eout.p, Eout.bs, buf(o_G[cur ^ 1]), s_G,
+                                  buf(o_eig), s_eig, Bcur, st_, blocked ? buf(o_wy[j]) : nullptr, s_wy[j]);
             }));
             cur ^= 1;
         }
@@ -555,7 +531,7 @@ public:
         a.lin = lin; a.lout = lout;
         a.skip = skip_; a.skip_bs = skip_bs_;
         step_rescaled = lout != nullptr;
-        const double fl = 2.0 * Bcur *
+        const double fl = 2.0 * active_samples() *
                           ((double)a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.cl * a.cu1 * a.h1 * a.Dd * a.h * a.Du +
                            (double)a.cu1 * a.h1 * a.cl1 * a.cl * a.Dd);
         return timed(PEPS_KC_FUSED, fl, [&] { return launch_row_step(a, fwd, st_); });
@@ -630,10 +606,9 @@ public:
         a.flip1 = f1; a.flip2 = f2;
         a.Y = Y.p; a.ys = Y.bs; a.batch = Bcur;
         a.lin = lin; a.lout = lout;
-        a.mfma = pair_mfma ? 1 : 0;
         a.skip = skip_; a.skip_bs = skip_bs_;
         step_rescaled = lout != nullptr;
-        const double fl = 2.0 * Bcur *
+        const double fl = 2.0 * active_samples() *
                           ((double)a.h * a.h * a.cl * a.Du * a.cu1 * a.cu + (double)a.h * a.cl * a.cu1 * a.h1 * a.Dm * a.h * a.Du +
                            (double)a.cl * a.cu1 * a.h1 * a.h1 * a.Dq * a.h * a.Dm + (double)a.cu1 * a.h1 * a.h1 * a.cl1 * a.cl * a.Dq);
         return timed(PEPS_KC_FUSED, fl, [&] { return launch_pair_step(a, fwd, st_); });
@@ -714,10 +689,20 @@ public:
     void skip_on(int bond) {
         skip_ = act() + bond;
         skip_bs_ = nbonds;
+        skip_bond_ = bond;
     }
     void skip_off() {
         skip_ = nullptr;
         skip_bs_ = 0;
+        skip_bond_ = -1;
+    }
+    // samples a launch works on, for the algorithmic flop counts of the profiling records
+    // (the active-bond table is read back only while kernel classes are being timed)
+    double active_samples() const {
+        if (skip_bond_ < 0 || act_host_.empty()) return (double)Bcur;
+        long long n = 0;
+        for (int b = 0; b < Bcur; ++b) n += act_host_[(size_t)b * nbonds + skip_bond_] != 0;
+        return (double)n;
     }
 
     // launch `f` between two events when its kernel class is being profiled
@@ -745,10 +730,15 @@ public:
         const double r = std::min(m, n);
         return 2.0 * r * r * (std::max(m, n) - r / 3.0);
     }
+    // truncation step of one centre: the implicit-Q application forming it (4 tin (mz r - r^2/2)),
+    // a thin SVD of the m' x n' centre counted as min(14 m n^2 + 8 n^3, 6 m n^2 + 20 n^3)
+    // (m = max, n = min; the Golub-Kahan-Reinsch and R-bidiagonalisation counts), and the
+    // carried U_t Sigma_t (2 m' n' t)
     static double svd_flops(double mz, double r, double tin, double p, double tk) {
         const double mp = mz / p, np = p * tin;
         const double a = std::max(mp, np), b = std::min(mp, np);
-        return 4.0 * tin * (mz * r - 0.5 * r * r) + 4.0 * a * b * b + 8.0 * b * b * b + 2.0 * mp * np * tk;
+        const double svd = std::min(14.0 * a * b * b + 8.0 * b * b * b, 6.0 * a * b * b + 20.0 * b * b * b);
+        return 4.0 * tin * (mz * r - 0.5 * r * r) + svd + 2.0 * mp * np * tk;
     }
 
     // ---- one chunk ----
@@ -760,6 +750,12 @@ public:
         hipStream_t st = st_;
         KL(launch_check_configs(S, N, Bn, flags(), st));
         if (want_eloc) KL(launch_bond_active(S, Lx, Ly, act(), nbonds, Bn, st));
+        act_host_.clear();
+        if (want_eloc && !dry && ctx->prof_mask) {
+            act_host_.resize((size_t)Bn * nbonds);
+            CK(hipMemcpyAsync(act_host_.data(), act(), act_host_.size(), hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+        }
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
         if (fuse_pairs) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
@@ -929,14 +925,14 @@ public:
     size_t o_site32 = 0, o_act = 0;
     const int8_t* skip_ = nullptr;
     long long skip_bs_ = 0;
+    int skip_bond_ = -1;
+    std::vector<int8_t> act_host_;
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0, o_gws;
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
     size_t o_eig = 0;
-    bool use_eig = true;   // truncation SVD through the Gram eigenproblem (else Jacobi)
     bool fuse_pairs = false;
     bool step_rescaled = false;   // the last sandwich step also applied the max-abs rescale
-    bool pair_mfma = true;
 };
 
 size_t g_lds_cap = 160 * 1024;   // gfx950; replaced by the device attribute at peps_create

@@ -53,7 +53,14 @@ WORKLOADS = {
     "8x8_D4_Dc16": Workload("8x8_D4_Dc16", Lattice(8, 8, 4, 16), 4096, 2, 102, "frobenius", "f32"),
     "16x16_D6_Dc36": Workload("16x16_D6_Dc36", Lattice(16, 16, 6, 36), 1024, 3, 103, "frobenius", "f32"),
     "24x24_D8_Dc64": Workload("24x24_D8_Dc64", Lattice(24, 24, 8, 64), 512, 4, 104, "frobenius", "bf16"),
+    # the three lattices of the mixed batch (2048 samples split 1024 / 614 / 410)
+    "mix_8x8_D4_Dc16": Workload("mix_8x8_D4_Dc16", Lattice(8, 8, 4, 16), 1024, 51, 151, "frobenius", "f32"),
+    "mix_12x12_D6_Dc36": Workload("mix_12x12_D6_Dc36", Lattice(12, 12, 6, 36), 614, 52, 152, "frobenius", "f32"),
+    "mix_16x16_D8_Dc64": Workload("mix_16x16_D8_Dc64", Lattice(16, 16, 8, 64), 410, 53, 153, "frobenius", "f32"),
 }
+
+# the mixed batch: (workload, samples) in its 50/30/20 split of 2048
+MIXED_BATCH = (("mix_8x8_D4_Dc16", 1024), ("mix_12x12_D6_Dc36", 614), ("mix_16x16_D8_Dc64", 410))
 
 
 def make_tensors(lat: Lattice, seed: int, scaling: str) -> np.ndarray:
