@@ -130,6 +130,28 @@ peps_status peps_evaluate(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           const double* weights, double* log_abs, int8_t* sign,
                           double* e_loc, double* out, int8_t* flags);
 
+/* peps_evaluate for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results (per-sample outputs bit for bit; the grad_mode 2 and 3 sums may
+ * differ by rounding, as they are summed over the chunks below), with the workspace in a
+ * fixed device array of peps_noalloc_scratch_bytes() bytes (64 MiB) that each device
+ * holds from library load to process end, instead of the context's allocated workspace.
+ * The batch is processed in chunks sized to that array; a lattice whose single sample
+ * does not fit returns PEPS_ERR_INVALID_ARG with a message, before any work.
+ * The call allocates no device memory (no hipMalloc or hipFree, no library routine that
+ * does) and records no profiling events.  Every context and call on one device shares
+ * that device's array, which keeps the last call's contents (nothing in it is assumed
+ * to be zero on entry): calls whose work overlaps on one device (several streams or
+ * contexts) race and must be serialised by the caller.  The caller passes inputs and
+ * outputs as for peps_evaluate. */
+peps_status peps_evaluate_noalloc(peps_ctx* ctx, const peps_lattice* lat, peps_precision prec,
+                                  const double* A, const int8_t* S, int64_t batch,
+                                  int32_t grad_mode, const double* weights, double* log_abs,
+                                  int8_t* sign, double* e_loc, double* out, int8_t* flags);
+
+/* Size in bytes of the fixed scratch array of peps_evaluate_noalloc. */
+size_t peps_noalloc_scratch_bytes(void);
+
 /* One Metropolis step of every chain: the sampling loop of Sec. II-B (steps 1-3: a
  * proposed configuration, its weight by contraction, accept or reject) for weights
  * W(S)^2, the importance sampling of the energy estimator Eq. (3).

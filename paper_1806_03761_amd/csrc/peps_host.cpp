@@ -8,6 +8,7 @@
 #include <cmath>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +51,7 @@ struct peps_ctx {
     size_t ws_bytes = 0;
     size_t ws_limit = 0;
     double* ones = nullptr;   // 4096 ones
+    char* scratch = nullptr;  // device address of this device's fixed scratch array
     char* mc = nullptr;       // sampling buffers (peps_metropolis_step, peps_vmc_step)
     size_t mc_bytes = 0;
     char* corr = nullptr;     // exchanged configurations and their amplitudes (peps_pair_correlations)
@@ -63,6 +65,28 @@ static void drop_graphs(peps_ctx* c) {
         hipGraphDestroy(g.graph);
     }
     c->graphs.clear();
+}
+
+// Fixed device scratch of the allocation-free evaluation (peps_evaluate_noalloc): each
+// device that loads the library holds its own copy until the process ends, shared by
+// every context and call on that device.  Host code never passes `scratch` itself (in
+// host code the name is a stand-in, not a device address): it takes this device's
+// address from hipGetSymbolAddress once, with the device current (scratch_address).
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;   // device -> address of its scratch copy
+
+// this device's scratch address; the device must be current
+static char* scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[device] = static_cast<char*>(p);
+    return static_cast<char*>(p);
 }
 
 namespace peps {
@@ -708,7 +732,7 @@ public:
     // launch `f` between two events when its kernel class is being profiled
     template <class F>
     hipError_t timed(int cls, double flops, F f) {
-        if (dry || !(ctx->prof_mask & (1u << cls))) return f();
+        if (dry || quiet || !(ctx->prof_mask & (1u << cls))) return f();
         hipEvent_t ev[2];
         for (int k = 0; k < 2; ++k) {
             if (!ctx->ev_pool.empty()) {
@@ -751,7 +775,7 @@ public:
         KL(launch_check_configs(S, N, Bn, flags(), st));
         if (want_eloc) KL(launch_bond_active(S, Lx, Ly, act(), nbonds, Bn, st));
         act_host_.clear();
-        if (want_eloc && !dry && ctx->prof_mask) {
+        if (want_eloc && !dry && !quiet && ctx->prof_mask) {
             act_host_.resize((size_t)Bn * nbonds);
             CK(hipMemcpyAsync(act_host_.data(), act(), act_host_.size(), hipMemcpyDeviceToHost, st));
             CK(hipStreamSynchronize(st));
@@ -927,6 +951,7 @@ public:
     long long skip_bs_ = 0;
     int skip_bond_ = -1;
     std::vector<int8_t> act_host_;
+    bool quiet = false;       // no profiling events (the allocation-free entry point)
     size_t o_R[2], o_G[2], o_Y, o_svd, o_T[3], o_F, o_Gf, o_lnW, o_sgW, o_lnW2, o_sgW2, o_lnWf, o_sgWf,
         o_zero, o_ratio, o_delta, o_flags, o_eloc, o_acc, o_G1, o_G0, o_gws;
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
@@ -986,7 +1011,8 @@ peps_status peps_create(peps_ctx** ctx, int device) {
         return PEPS_ERR_OOM;
     }
     launch_fill(c->ones, kOnes, 1.0, nullptr);
-    if (hipDeviceSynchronize() != hipSuccess) {
+    c->scratch = scratch_address(device);
+    if (!c->scratch || hipDeviceSynchronize() != hipSuccess) {
         hipFree(c->ones);
         delete c;
         return PEPS_ERR_HIP;
@@ -1127,10 +1153,12 @@ static hipError_t enqueue_job(Runner& r, const JobIn& j, int64_t Bc) {
     return hipSuccess;
 }
 
+// noalloc: the workspace is this device's fixed scratch array (chunks sized to fit it);
+// no device allocation and no profiling events
 static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
                            const int8_t* S, int64_t batch, bool want_e, int grad_mode,
                            const double* weights, double* log_abs, int8_t* sign, double* e_loc,
-                           double* out, int8_t* flags) {
+                           double* out, int8_t* flags, bool noalloc = false) {
     if (!c) return PEPS_ERR_INVALID_ARG;
     c->err.clear();
     if (!lat) return fail(c, PEPS_ERR_INVALID_ARG, "lattice is NULL");
@@ -1141,15 +1169,32 @@ static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision 
     Runner r(c, *lat, prec);
     size_t per, fixed;
     job_sizes(r, j, &per, &fixed);
-    const size_t limit = default_limit(c);
-    if (per + fixed > limit) return fail(c, PEPS_ERR_OOM, "one sample needs %zu bytes > limit %zu", per + fixed, limit);
+    const size_t limit = noalloc ? kScratchBytes : default_limit(c);
+    if (per + fixed > limit) {
+        if (noalloc)
+            return fail(c, PEPS_ERR_INVALID_ARG, "one sample needs %zu bytes > the fixed scratch of %zu bytes",
+                        per + fixed, limit);
+        return fail(c, PEPS_ERR_OOM, "one sample needs %zu bytes > limit %zu", per + fixed, limit);
+    }
     int64_t Bc = std::min<int64_t>(batch, (int64_t)((limit - fixed) / per));
     Bc = std::max<int64_t>(1, std::min<int64_t>(Bc, 1 << 20));
     r.layout((int)Bc, j.want_e, grad_mode != 0);
-    st = ensure_ws(c, r.L.bytes);
-    if (st != PEPS_OK) return st;
+    if (noalloc) {
+        while (r.L.bytes > limit && Bc > 1) {   // alignment padding can add a little
+            --Bc;
+            r.layout((int)Bc, j.want_e, grad_mode != 0);
+        }
+        if (r.L.bytes > limit || !c->scratch)
+            return fail(c, PEPS_ERR_INVALID_ARG, "workspace of %zu bytes > the fixed scratch of %zu bytes",
+                        r.L.bytes, limit);
+        r.base_ = c->scratch;
+        r.quiet = true;
+    } else {
+        st = ensure_ws(c, r.L.bytes);
+        if (st != PEPS_OK) return st;
+        r.base_ = c->ws;
+    }
     r.st_ = c->stream;
-    r.base_ = c->ws;
     hipError_t e = enqueue_job(r, j, Bc);
     if (e != hipSuccess)
         return fail(c, PEPS_ERR_HIP, "HIP error: %s %s", hipGetErrorString(e), r.bounds_msg.c_str());
@@ -1632,5 +1677,14 @@ peps_status peps_evaluate(peps_ctx* c, const peps_lattice* lat, peps_precision p
     return run_all(c, lat, prec, A, S, batch, e_loc != nullptr, grad_mode, weights, log_abs, sign, e_loc,
                    out, flags);
 }
+
+peps_status peps_evaluate_noalloc(peps_ctx* c, const peps_lattice* lat, peps_precision prec, const double* A,
+                                  const int8_t* S, int64_t batch, int32_t grad_mode, const double* weights,
+                                  double* log_abs, int8_t* sign, double* e_loc, double* out, int8_t* flags) {
+    return run_all(c, lat, prec, A, S, batch, e_loc != nullptr, grad_mode, weights, log_abs, sign, e_loc,
+                   out, flags, true);
+}
+
+size_t peps_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 }  // extern "C"

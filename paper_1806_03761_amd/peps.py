@@ -66,6 +66,8 @@ _SIGS = {
     "peps_tune_load": [_P, ctypes.c_char_p],
     "peps_evaluate": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                       ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+    "peps_evaluate_noalloc": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
+                              ctypes.c_int32, _P, _P, _P, _P, _P, _P],
     "peps_metropolis_step": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                              _P, _P, _P, _P],
     "peps_go_update": [_P, ctypes.POINTER(_Lattice), _P, _P, _P, ctypes.c_double],
@@ -91,12 +93,14 @@ def load_library(path: str = LIB_PATH):
                 fn.restype = ctypes.c_int
             lib.peps_last_error.argtypes = [_P]
             lib.peps_last_error.restype = ctypes.c_char_p
+            lib.peps_noalloc_scratch_bytes.argtypes = []
+            lib.peps_noalloc_scratch_bytes.restype = ctypes.c_size_t
             _lib = lib
     return _lib
 
 
 def exported_symbols():
-    return list(_SIGS) + ["peps_last_error"]
+    return list(_SIGS) + ["peps_last_error", "peps_noalloc_scratch_bytes"]
 
 
 def _context(device: int):
@@ -199,6 +203,11 @@ def tune_load(path: str, device: int = 0):
     _check(lib, ctx, lib.peps_tune_load(ctx, path.encode()), "peps_tune_load")
 
 
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed device scratch array of peps_evaluate_noalloc."""
+    return int(load_library().peps_noalloc_scratch_bytes())
+
+
 def set_workspace_limit(nbytes: int, device: int = 0):
     lib, ctx = _context(device)
     lib.peps_set_workspace_limit(ctx, int(nbytes))
@@ -260,9 +269,11 @@ def log_derivative(A, S, lat, prec: str = "f64", weights=None):
     return out, la, sg, fl
 
 
-def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out=None):
+def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out=None, noalloc=False):
     """Whole path from one set of environments: (log_abs, sign, e_loc, grad, flags).
-    grad_mode 0 none, 1 per-sample, 2 weighted sum, 3 dE/dA of the energy estimator."""
+    grad_mode 0 none, 1 per-sample, 2 weighted sum, 3 dE/dA of the energy estimator.
+    noalloc: through peps_evaluate_noalloc (workspace in the library's fixed device
+    scratch array instead of an allocated one)."""
     lib, ctx, A, S = _prep(A, S, lat)
     B = S.shape[0]
     N, D4 = lat.Lx * lat.Ly, lat.D ** 4
@@ -276,9 +287,10 @@ def evaluate(A, S, lat, prec: str = "f64", grad_mode: int = 3, weights=None, out
         out = torch.empty(shape, dtype=torch.float64, device=dev)
     if weights is not None:
         weights = weights.to(device=dev, dtype=torch.float64).contiguous()
-    st = lib.peps_evaluate(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, grad_mode,
-                           _ptr(weights), _ptr(la), _ptr(sg), _ptr(e), _ptr(out), _ptr(fl))
-    _check(lib, ctx, st, "peps_evaluate")
+    fn = lib.peps_evaluate_noalloc if noalloc else lib.peps_evaluate
+    st = fn(ctx, ctypes.byref(_lat(lat)), PREC[prec], _ptr(A), _ptr(S), B, grad_mode,
+            _ptr(weights), _ptr(la), _ptr(sg), _ptr(e), _ptr(out), _ptr(fl))
+    _check(lib, ctx, st, "peps_evaluate_noalloc" if noalloc else "peps_evaluate")
     return la, sg, e, out, fl
 
 
