@@ -29,6 +29,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense MFMA TFLOP/s
+T_START = time.time()
+# wall-clock budget of one run: a leg (below) starts only if its estimated cost still
+# fits, so a default run stays within a few minutes whatever the step time
+BUDGET_S = float(os.environ.get("BENCH_BUDGET_S", "480"))
+
+
+def _log(msg: str) -> None:
+    print(f"[bench {time.time() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
+def _fits(seconds: float) -> bool:
+    return time.time() - T_START + seconds < BUDGET_S
 
 
 def _oracle_worker(args):
@@ -164,27 +176,36 @@ def main():
     tuned = 0
     if not args.no_tune:
         tuned = peps.autotune(Ad, Sd, lat, args.prec)     # untimed: picks GEMM tiles by measurement
+    _log(f"{name}: batch {B}, {tuned} GEMM shapes tuned")
     cpu_h = None
     if not args.no_cpu_baseline:
         cpu_h = start_cpu_baseline(name, 1)
     # warm-up steps with every kernel class bracketed by HIP events: the per-class
     # breakdown, and which class dominates
     peps.profile_enable(CLASSES)
-    for _ in range(max(args.warmup, 1)):
+    for k in range(max(args.warmup, 1)):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        _log(f"warm-up step {k + 1}")
     kern = _read(peps, CLASSES)
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
     cpu = finish_cpu_baseline(cpu_h, name) if cpu_h else None
+    _log("cpu baseline done" if cpu else "no cpu baseline")
+    # progress lines in the timed region only for slow steps (the host runs ahead of the
+    # GPU, so a line marks an enqueue, not a completion; it adds no synchronisation)
+    dt_step_log = 1 if kern and sum(v["ms_total"] for v in kern.values()) > 2000 * max(args.warmup, 1) else 0
     # timed region: only the dominant class is bracketed by events (on the library's
     # stream), which keeps the instrumentation out of the throughput
     peps.profile_enable((dom,))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         res_f64 = step()
+        if dt_step_log and (k + 1) % dt_step_log == 0:
+            _log(f"timed step {k + 1} enqueued")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    _log(f"timed region {dt:.1f} s")
     timed = _read(peps, (dom,))[dom]
     peps.profile_enable(())
     ms = dt * 1e3 / args.steps
@@ -226,9 +247,14 @@ def main():
         # the same workload with narrower contraction arithmetic: throughput and the error
         # of every result against the float64 results above (which match the oracle to
         # 1e-10 on the tested subsets)
+        step_s = ms / 1e3
         for pr in ("f32", "bf16"):
             if pr == args.prec:
                 continue
+            if not _fits(2.2 * step_s):
+                legs[pr] = {"skipped": "time budget of the run"}
+                continue
+            _log(f"leg {pr}")
             g1 = torch.empty_like(grad)
             step(pr, out=g1)
             torch.cuda.synchronize()
@@ -245,20 +271,27 @@ def main():
                         "err_grad_rel_l2_vs_f64": float(np.linalg.norm(gg1 - g0) / np.linalg.norm(g0))}
         # plain path: the same library at batch 1, float64, one sample at a time
         nplain = 2
-        for b in range(1):
-            peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for b in range(nplain):
-            peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
-        torch.cuda.synchronize()
-        legs["plain"] = {"value": nplain / (time.perf_counter() - t1), "unit": "samples/s",
-                         "sample": f"{nplain} samples one at a time, f64, batch 1"}
+        if _fits(20.0):
+            _log("leg plain")
+            peps.evaluate(Ad, Sd[0:1], lat, "f64", grad_mode=1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for b in range(nplain):
+                peps.evaluate(Ad, Sd[b:b + 1], lat, "f64", grad_mode=1)
+            torch.cuda.synchronize()
+            legs["plain"] = {"value": nplain / (time.perf_counter() - t1), "unit": "samples/s",
+                             "sample": f"{nplain} samples one at a time, f64, batch 1"}
+        else:
+            legs["plain"] = {"skipped": "time budget of the run"}
         # the 8x8, D = 4, Dc = 16 workload (4096 samples), float64 and float32
         lat2, A2, S2, _ = make_workload("8x8_D4_Dc16")
         A2d, S2d = torch.from_numpy(A2).to(dev), torch.from_numpy(S2).to(dev)
         g2 = torch.empty((lat2.N, 2, lat2.D ** 4), dtype=torch.float64, device=dev)
         for pr in ("f64", "f32"):
+            if not _fits(15.0):
+                legs["8x8_D4_Dc16_" + pr] = {"skipped": "time budget of the run"}
+                continue
+            _log(f"leg 8x8_D4_Dc16 {pr}")
             peps.autotune(A2d, S2d, lat2, pr)
             step(pr, A2d, S2d, lat2, g2)
             torch.cuda.synchronize()
@@ -269,20 +302,26 @@ def main():
             legs["8x8_D4_Dc16_" + pr] = {"samples_per_s": 5 * S2.shape[0] / (time.perf_counter() - t1),
                                          "batch": int(S2.shape[0])}
         del A2d, S2d, g2
-        # 24x24, D = 8, Dc = 64: one step over the first 8 of its 512 samples
-        lat4, A4, S4, _ = make_workload("24x24_D8_Dc64", 8)
-        A4d, S4d = torch.from_numpy(A4).to(dev), torch.from_numpy(S4).to(dev)
-        g4 = torch.empty((lat4.N, 2, lat4.D ** 4), dtype=torch.float64, device=dev)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step("f64", A4d, S4d, lat4, g4)
-        torch.cuda.synchronize()
-        legs["24x24_D8_Dc64_f64"] = {"samples_per_s": S4.shape[0] / (time.perf_counter() - t1),
-                                     "sample": "first 8 of the 512 configurations, one step (includes "
-                                               "first-use workspace set-up)"}
+        # 24x24, D = 8, Dc = 64: one step over the first 2 of its 512 samples
+        if _fits(150.0):
+            _log("leg 24x24_D8_Dc64 f64")
+            lat4, A4, S4, _ = make_workload("24x24_D8_Dc64", 2)
+            A4d, S4d = torch.from_numpy(A4).to(dev), torch.from_numpy(S4).to(dev)
+            g4 = torch.empty((lat4.N, 2, lat4.D ** 4), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step("f64", A4d, S4d, lat4, g4)
+            torch.cuda.synchronize()
+            legs["24x24_D8_Dc64_f64"] = {"samples_per_s": S4.shape[0] / (time.perf_counter() - t1),
+                                         "sample": "first 2 of the 512 configurations, one step, f64 (includes "
+                                                   "first-use workspace set-up)"}
+            del A4d, S4d, g4
+        else:
+            legs["24x24_D8_Dc64_f64"] = {"skipped": "time budget of the run"}
         res["legs"] = legs
     if cpu:
         res["cpu_baseline"] = cpu
+    res["run_wall_s"] = time.time() - T_START
     print(json.dumps(res), flush=True)
 
 

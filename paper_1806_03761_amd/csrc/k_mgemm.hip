@@ -8,11 +8,13 @@
 //
 // A workgroup of four waves computes a TM x TN tile; wave (wm, wn) owns BM x BN blocks
 // of 16 x 16, each accumulated by 16x16x4 MFMAs (float64: v_mfma_f64_16x16x4f64,
-// float32: v_mfma_f32_16x16x4f32).  Operand tiles of TK = 16 k values are staged through
-// LDS in the compute type; the next stage's global loads are issued before the current
-// stage's MFMAs so their latency overlaps.  Every output sums its products in ascending
+// float32: v_mfma_f32_16x16x4f32).  Operand tiles of TK k values (16, or 12, 32, 36 where
+// they divide K) are staged through LDS in the compute type; the next stage's global
+// loads are issued before the current stage's MFMAs so their latency overlaps.  Every output sums its products in ascending
 // k (MFMA s takes k = 4s..4s+3), with no split of K over waves, so all tile shapes give
 // bitwise-identical results and the autotuner may pick any of them.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -49,41 +51,70 @@ __device__ __forceinline__ typename MT<AR>::Acc mfma(typename MT<AR>::In a, type
 
 // Per-thread share of one operand tile (TK x TW entries): NI loads.  Entry e of the tile
 // maps to (k, w) either w-fastest (consecutive threads walk the free index) or k-fastest,
-// whichever index has unit stride in memory, so the loads coalesce.  TK = 16, or 12 where
-// K is a multiple of 12 (no padded k stage).
+// whichever index has unit stride in memory, so the loads coalesce.  TK = 16, or 12, 32
+// or 36 where it divides K (no padded k stage).
 template <int TK, int TW>
 struct TileLd {
     static constexpr int NE = TK * TW, NI = (NE + 255) / 256;
 };
 
-template <int TK, int TW, int NI, Arith AR>
-__device__ __forceinline__ void tile_issue(double (&x)[NI], float (&xf)[NI], bool (&ok)[NI], const long long* off_w,
-                                           const Idx2& kx, int k0, int K, bool kfast, int f32, const double* srcd,
-                                           const float* srcf, int tid) {
+// Offsets of this thread's tile entries along the free index (fixed for the whole K
+// loop, so read from LDS once; 32-bit, as the launcher checks that every in-sample
+// offset fits), and the entry's k within a stage.
+template <int TK, int TW, int NI>
+__device__ __forceinline__ void tile_map(int (&ow)[NI], int (&kk)[NI], const long long* off_w, bool kfast, int tid) {
     constexpr int NE = TK * TW;
-    long long o[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         const int e = tid + 256 * i;
         const bool in = NE % 256 == 0 || e < NE;
-        const int kk = kfast ? e % TK : e / TW, w = kfast ? e / TK : e % TW;
-        const int k = k0 + kk;
-        const long long ow = in ? off_w[w] : -1;
-        ok[i] = in && ow >= 0 && k < K;
-        o[i] = ok[i] ? ow + idx_off(kx, k) : 0;
+        kk[i] = kfast ? e % TK : e / TW;
+        const int w = kfast ? e / TK : e % TW;
+        ow[i] = in ? (int)off_w[w] : -1;
+    }
+}
+
+// Global loads of one stage: entry i at ow[i] + koff[kk[i]] (koff: the stage's k offsets,
+// -1 past K), zero where either is absent (bit i of ok clear).  The raw 64 or 32 bits
+// are kept until the LDS store, so one register pair serves both storage types and no
+// instruction waits on a load before the next stage's MFMAs.
+template <int NI>
+__device__ __forceinline__ void tile_issue(unsigned long long (&x)[NI], unsigned& ok, const int (&ow)[NI],
+                                           const int (&kk)[NI], const long long* koff, int f32, const double* srcd,
+                                           const float* srcf) {
+    long long o[NI];
+    ok = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const long long ko = koff[kk[i]];
+        const bool v = ow[i] >= 0 && ko >= 0;
+        ok |= (unsigned)v << i;
+        o[i] = v ? ow[i] + ko : 0;
     }
     if (f32) {
 #pragma unroll
-        for (int i = 0; i < NI; ++i) xf[i] = srcf[o[i]];
+        for (int i = 0; i < NI; ++i) x[i] = __float_as_uint(srcf[o[i]]);
     } else {
 #pragma unroll
-        for (int i = 0; i < NI; ++i) x[i] = srcd[o[i]];
+        for (int i = 0; i < NI; ++i) x[i] = (unsigned long long)__double_as_longlong(srcd[o[i]]);
+    }
+}
+
+// k offsets of stage k0 of both operands (threads 0 .. 2 TK - 1): the only divisions of
+// the multi-index k, once per stage and workgroup
+template <int TK>
+__device__ __forceinline__ void stage_koff(long long* ka, long long* kb, const Idx2& ak, const Idx2& bk, int k0,
+                                           int K, int tid) {
+    if (tid < 2 * TK) {
+        const int kk = tid % TK, k = k0 + kk;
+        const long long v = k < K ? idx_off(tid < TK ? ak : bk, k) : -1;
+        (tid < TK ? ka : kb)[kk] = v;
     }
 }
 
 template <int TK, int TW, int NI, Arith AR>
-__device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const double (&x)[NI], const float (&xf)[NI],
-                                           const bool (&ok)[NI], bool kfast, int f32, int tid) {
+__device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const unsigned long long (&x)[NI], unsigned ok,
+                                           bool kfast, int f32, int tid) {
     using In = typename MT<AR>::In;
     constexpr int NE = TK * TW;
 #pragma unroll
@@ -91,8 +122,8 @@ __device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const doubl
         const int e = tid + 256 * i;
         if (NE % 256 != 0 && e >= NE) continue;
         const int kk = kfast ? e % TK : e / TW, w = kfast ? e / TK : e % TW;
-        const In v = ok[i] ? to_mt<AR>(f32 ? (double)xf[i] : x[i]) : In(0);
-        dst[kk * (TW + 1) + w] = v;
+        const double d = f32 ? (double)__uint_as_float((unsigned)x[i]) : __longlong_as_double((long long)x[i]);
+        dst[kk * (TW + 1) + w] = ((ok >> i) & 1) ? to_mt<AR>(d) : In(0);
     }
 }
 
@@ -104,6 +135,7 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
     __shared__ In As[TK * (TM + 1)];
     __shared__ In Bs[TK * (TN + 1)];
     __shared__ long long aoff_m[TM], boff_n[TN], coff_m[TM], coff_n[TN];
+    __shared__ long long koff[2][2][TK];   // [stage parity][operand][k in stage]
 
     const int tiles = tiles_m * tiles_n;
     const long long blk = blockIdx.x;
@@ -150,19 +182,29 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
     constexpr int NIA = TileLd<TK, TM>::NI, NIB = TileLd<TK, TN>::NI;
-    double xa[NIA], xb[NIB];
-    float xaf[NIA], xbf[NIB];
-    bool oka[NIA], okb[NIB];
-    tile_issue<TK, TM, NIA, AR>(xa, xaf, oka, aoff_m, g.ak, 0, g.K, akf, g.a_f32, Ab, Af, tid);
-    tile_issue<TK, TN, NIB, AR>(xb, xbf, okb, boff_n, g.bk, 0, g.K, bkf, g.b_f32, Bb, Bf, tid);
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    static_assert(NIA <= 32 && NIB <= 32, "tile share exceeds the load mask");
+    unsigned long long xa[NIA], xb[NIB];
+    unsigned oka, okb;
+    int owa[NIA], owb[NIB];
+    int kka[NIA], kkb[NIB];
+    tile_map<TK, TM, NIA>(owa, kka, aoff_m, akf, tid);
+    tile_map<TK, TN, NIB>(owb, kkb, boff_n, bkf, tid);
+    stage_koff<TK>(koff[0][0], koff[0][1], g.ak, g.bk, 0, g.K, tid);
+    __syncthreads();
+    tile_issue<NIA>(xa, oka, owa, kka, koff[0][0], g.a_f32, Ab, Af);
+    tile_issue<NIB>(xb, okb, owb, kkb, koff[0][1], g.b_f32, Bb, Bf);
+    int stg = 0;
+    for (int k0 = 0; k0 < g.K; k0 += TK, ++stg) {
+        // the next stage's k offsets go to the other buffer, last read two stages ago
+        const int nb = (stg + 1) & 1;
+        if (k0 + TK < g.K) stage_koff<TK>(koff[nb][0], koff[nb][1], g.ak, g.bk, k0 + TK, g.K, tid);
         __syncthreads();
-        tile_store<TK, TM, NIA, AR>(As, xa, xaf, oka, akf, g.a_f32, tid);
-        tile_store<TK, TN, NIB, AR>(Bs, xb, xbf, okb, bkf, g.b_f32, tid);
+        tile_store<TK, TM, NIA, AR>(As, xa, oka, akf, g.a_f32, tid);
+        tile_store<TK, TN, NIB, AR>(Bs, xb, okb, bkf, g.b_f32, tid);
         __syncthreads();
         if (k0 + TK < g.K) {
-            tile_issue<TK, TM, NIA, AR>(xa, xaf, oka, aoff_m, g.ak, k0 + TK, g.K, akf, g.a_f32, Ab, Af, tid);
-            tile_issue<TK, TN, NIB, AR>(xb, xbf, okb, boff_n, g.bk, k0 + TK, g.K, bkf, g.b_f32, Bb, Bf, tid);
+            tile_issue<NIA>(xa, oka, owa, kka, koff[nb][0], g.a_f32, Ab, Af);
+            tile_issue<NIB>(xb, okb, owb, kkb, koff[nb][1], g.b_f32, Bb, Bf);
         }
 #pragma unroll
         for (int s = 0; s < TK / 4; ++s) {
@@ -219,25 +261,40 @@ hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
     return hipGetLastError();
 }
 
+// largest offset of a multi-index over [0, n) (strides must not be negative)
+long long idx_bound(const Idx2& x, int n) {
+    if (n <= 0) return 0;
+    if (x.s_outer < 0 || x.s_inner < 0 || x.inner <= 0) return -1;
+    const long long lo = std::min<long long>(n - 1, x.inner - 1);
+    return (long long)((n - 1) / x.inner) * x.s_outer + lo * x.s_inner;
+}
+
 }  // namespace
 
 // tiles 1..kMfmaTiles (TM x TN, k stage): 32x32, 64x16, 16x64, 64x64, 128x16, 16x128, 64x32, 32x64,
 // 128x64, 64x128, 128x32, 32x128 (k stage 16); 64x48, 128x48, 48x64, 48x128 (16); 64x48, 128x48,
-// 48x64, 64x64 (k stage 12: no padded stage when K is a multiple of 12, e.g. 36 or 216)
+// 48x64, 64x64 (k stage 12: no padded stage when K is a multiple of 12, e.g. 36 or 216);
+// 64x48, 128x48, 48x64, 64x64, 32x64 (k stage 36: a K of 36 in one stage, one barrier pair);
+// 64x64, 32x64 (k stage 32)
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    // the kernels hold the free-index offsets of A and B in 32 bits
+    const long long ma = idx_bound(g.am, g.M), nb = idx_bound(g.bn, g.N);
+    if (ma < 0 || nb < 0 || ma > 0x7fffffffLL || nb > 0x7fffffffLL) return hipErrorInvalidValue;
     if (tile <= 0 || tile > kMfmaTiles) {
         // heuristic: the smallest tile that covers small products, 48-wide where a leg of
-        // 36 or 48 would leave a 64-wide tile part-empty, else 64 x 64
-        const bool k12 = g.K % 12 == 0 && g.K % 16 != 0;
+        // 36 or 48 would leave a 64-wide tile part-empty, else 64 x 64; the k stage that
+        // divides K (36, 32, 12) before the padded 16
+        const bool k36 = g.K % 36 == 0, k32 = g.K % 32 == 0 && g.K % 16 == 0 && !k36;
+        const bool k12 = !k36 && g.K % 12 == 0 && g.K % 16 != 0;
         if (g.M <= 32 && g.N <= 32) tile = 1;
         else if (g.N <= 16) tile = g.M >= 128 ? 5 : 2;
         else if (g.M <= 16) tile = g.N >= 128 ? 6 : 3;
-        else if (g.N <= 48 && g.N > 32) tile = k12 ? 18 : 14;
-        else if (g.M <= 48 && g.M > 32) tile = k12 ? 19 : 15;
+        else if (g.N <= 48 && g.N > 32) tile = k36 ? 21 : k12 ? 18 : 14;
+        else if (g.M <= 48 && g.M > 32) tile = k36 ? 23 : k12 ? 19 : 15;
         else if (g.N <= 32) tile = 7;
-        else if (g.M <= 32) tile = 8;
-        else tile = k12 ? 20 : 4;
+        else if (g.M <= 32) tile = k36 ? 25 : k32 ? 27 : 8;
+        else tile = k36 ? 24 : k32 ? 26 : k12 ? 20 : 4;
     }
     switch (tile) {
         case 1: return launch_m<2, 2, 1, 1>(g, ar, st);
@@ -259,7 +316,14 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         case 17: return launch_m<4, 1, 1, 3, 12>(g, ar, st);
         case 18: return launch_m<4, 1, 2, 3, 12>(g, ar, st);
         case 19: return launch_m<1, 4, 3, 1, 12>(g, ar, st);
-        default: return launch_m<2, 2, 2, 2, 12>(g, ar, st);
+        case 20: return launch_m<2, 2, 2, 2, 12>(g, ar, st);
+        case 21: return launch_m<4, 1, 1, 3, 36>(g, ar, st);
+        case 22: return launch_m<4, 1, 2, 3, 36>(g, ar, st);
+        case 23: return launch_m<1, 4, 3, 1, 36>(g, ar, st);
+        case 24: return launch_m<2, 2, 2, 2, 36>(g, ar, st);
+        case 25: return launch_m<2, 2, 1, 2, 36>(g, ar, st);
+        case 26: return launch_m<2, 2, 2, 2, 32>(g, ar, st);
+        default: return launch_m<2, 2, 1, 2, 32>(g, ar, st);
     }
 }
 
