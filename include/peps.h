@@ -276,7 +276,8 @@ peps_status peps_autotune(peps_ctx* ctx, const peps_lattice* lat, peps_precision
                           const double* A, const int8_t* S, int64_t batch, int32_t* tuned);
 
 /* Save / load the tile table as text lines "M,N,K,batch,arith,f32mask tile" (f32mask: bit 0/1/2
-   set when operand A/B/C is a float32 temporary). */
+   set when operand A/B/C is a float32 temporary).  Loading adds or replaces entries; tile 0
+   selects the built-in heuristic for that shape, and numbers past the last tile are ignored. */
 peps_status peps_tune_save(peps_ctx* ctx, const char* path);
 peps_status peps_tune_load(peps_ctx* ctx, const char* path);
 

@@ -245,6 +245,232 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
         }
 }
 
+// Persistent form of k_mgemm for the short-K products that bound the contraction chain
+// by memory: each workgroup walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ... as
+// one flattened sequence of (tile, k stage) steps, so the global loads of the next
+// step (the next tile's first stage included) are in flight during the current step's
+// MFMAs and the previous tile's output stores.  The LDS operand tiles are double
+// buffered (one barrier per step), the k offsets of a stage double buffered, and the
+// row / column offset tables of a tile triple buffered (a tile of one stage has its
+// table rewritten one step after its output is stored).  Per output the products are
+// summed exactly as in k_mgemm (ascending k, one MFMA chain), so results are equal bit
+// for bit.
+template <int TM, int TN>
+__device__ __forceinline__ void tile_tables(const GemmArgs& g, int m0, int n0, long long* ao, long long* bo,
+                                            long long* co_m, long long* co_n, int tid) {
+    for (int i = tid; i < TM; i += 256) {
+        const int m = m0 + i;
+        ao[i] = m < g.M ? idx_off(g.am, m) : -1;
+        co_m[i] = m < g.M ? idx_off(g.cm, m) : -1;
+    }
+    for (int i = tid; i < TN; i += 256) {
+        const int n = n0 + i;
+        bo[i] = n < g.N ? idx_off(g.bn, n) : -1;
+        co_n[i] = n < g.N ? idx_off(g.cn, n) : -1;
+    }
+}
+
+// next tile of this workgroup after t whose sample is not skipped (total when none)
+__device__ __forceinline__ long long next_tile(const GemmArgs& g, long long t, int tiles, long long total) {
+    for (t += gridDim.x; t < total; t += gridDim.x)
+        if (!g.skip || g.skip[(t / tiles) * g.skip_bs] != 0) break;
+    return t;
+}
+
+template <int WM, int WN, int BM, int BN, int TK, Arith AR>
+__global__ __launch_bounds__(256) void k_mgemm_p(GemmArgs g, int tiles_m, int tiles_n) {
+    using In = typename MT<AR>::In;
+    using Acc = typename MT<AR>::Acc;
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    __shared__ In As[2][TK * (TM + 1)];
+    __shared__ In Bs[2][TK * (TN + 1)];
+    __shared__ long long aoff_m[3][TM], boff_n[3][TN], coff_m[3][TM], coff_n[3][TN];
+    __shared__ long long koff[2][2][TK];   // [step parity][operand][k in stage]
+
+    const int tiles = tiles_m * tiles_n;
+    const long long total = (long long)tiles * g.batch;
+    const int nst = (g.K + TK - 1) / TK;
+    const int tid = threadIdx.x;
+    long long it = blockIdx.x;                      // tile of the loads in flight
+    if (g.skip && it < total && g.skip[(it / tiles) * g.skip_bs] == 0) it = next_tile(g, it, tiles, total);
+    if (it >= total) return;                        // uniform over the workgroup
+
+    const bool akf = g.ak.s_inner == 1 && !(g.am.s_inner == 1 && g.am.inner > 1);
+    const bool bkf = g.bk.s_inner == 1 && !(g.bn.s_inner == 1 && g.bn.inner > 1);
+    const int lane = tid & 63, w = tid >> 6;
+    const int wm = w % WM, wn = w / WM;
+    const int li = lane & 15, gq = lane >> 4;
+    constexpr int NIA = TileLd<TK, TM>::NI, NIB = TileLd<TK, TN>::NI;
+    static_assert(NIA <= 32 && NIB <= 32, "tile share exceeds the load mask");
+    unsigned long long xa[NIA], xb[NIB];
+    unsigned oka, okb;
+    int owa[NIA], owb[NIB];
+    int kka[NIA], kkb[NIB];
+    Acc acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+    // operand bases of tile t (sample t / tiles, spin-selected slices)
+    auto bases = [&](long long t, const double*& Ab, const double*& Bb) {
+        const int b = (int)(t / tiles);
+        Ab = g.A + (long long)b * g.a_bs + gather_off(g.ga, b);
+        Bb = g.B + (long long)b * g.b_bs + gather_off(g.gb, b);
+    };
+    auto issue = [&](long long t, int tb, int stage, int kb) {
+        const double *Ab, *Bb;
+        bases(t, Ab, Bb);
+        const long long abs_ = Ab - g.A, bbs = Bb - g.B;
+        tile_issue<NIA>(xa, oka, owa, kka, koff[kb][0], g.a_f32, Ab, reinterpret_cast<const float*>(g.A) + abs_);
+        tile_issue<NIB>(xb, okb, owb, kkb, koff[kb][1], g.b_f32, Bb, reinterpret_cast<const float*>(g.B) + bbs);
+        (void)tb;
+        (void)stage;
+    };
+
+    // prologue: tables of the first tile, its first stage in flight
+    int tb_i = 0;                                   // table buffer of the in-flight tile
+    {
+        const int t = (int)(it % tiles);
+        tile_tables<TM, TN>(g, (t / tiles_n) * TM, (t % tiles_n) * TN, aoff_m[0], boff_n[0], coff_m[0], coff_n[0], tid);
+        stage_koff<TK>(koff[0][0], koff[0][1], g.ak, g.bk, 0, g.K, tid);
+    }
+    __syncthreads();
+    tile_map<TK, TM, NIA>(owa, kka, aoff_m[0], akf, tid);
+    tile_map<TK, TN, NIB>(owb, kkb, boff_n[0], bkf, tid);
+    issue(it, 0, 0, 0);
+
+    long long ct = it;                              // tile of the step being computed
+    int cs = 0, tb_c = 0;                           // its stage and table buffer
+    int is = 0;                                     // stage of the loads in flight
+    for (int step = 0;; ++step) {
+        // where the next loads come from: the next stage, or the next tile's first
+        long long nt = it;
+        int ns = is + 1;
+        if (ns == nst) {
+            nt = next_tile(g, it, tiles, total);
+            ns = 0;
+        }
+        const bool more = nt < total;
+        const int kb = (step + 1) & 1;
+        int tb_n = tb_i;
+        if (more) {
+            stage_koff<TK>(koff[kb][0], koff[kb][1], g.ak, g.bk, ns * TK, g.K, tid);
+            if (ns == 0) {
+                tb_n = tb_i == 2 ? 0 : tb_i + 1;
+                const int t = (int)(nt % tiles);
+                tile_tables<TM, TN>(g, (t / tiles_n) * TM, (t % tiles_n) * TN, aoff_m[tb_n], boff_n[tb_n],
+                                    coff_m[tb_n], coff_n[tb_n], tid);
+            }
+        }
+        In* as = As[step & 1];
+        In* bs = Bs[step & 1];
+        tile_store<TK, TM, NIA, AR>(as, xa, oka, akf, g.a_f32, tid);
+        tile_store<TK, TN, NIB, AR>(bs, xb, okb, bkf, g.b_f32, tid);
+        __syncthreads();
+        if (more) {
+            if (ns == 0) {
+                tile_map<TK, TM, NIA>(owa, kka, aoff_m[tb_n], akf, tid);
+                tile_map<TK, TN, NIB>(owb, kkb, boff_n[tb_n], bkf, tid);
+            }
+            issue(nt, tb_n, ns, kb);
+        }
+#pragma unroll
+        for (int s = 0; s < TK / 4; ++s) {
+            In av[BM], bv[BN];
+#pragma unroll
+            for (int i = 0; i < BM; ++i) av[i] = as[(4 * s + gq) * (TM + 1) + (wm * BM + i) * 16 + li];
+#pragma unroll
+            for (int j = 0; j < BN; ++j) bv[j] = bs[(4 * s + gq) * (TN + 1) + (wn * BN + j) * 16 + li];
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int j = 0; j < BN; ++j) acc[i][j] = mfma<AR>(av[i], bv[j], acc[i][j]);
+        }
+        if (cs == nst - 1) {
+            // output of tile ct; lane (li, gq) holds column li of each 16 x 16 block, rows
+            // 4 gq + r (float32 MFMA) or gq + 4 r (float64 MFMA)
+            const int b = (int)(ct / tiles);
+            const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
+            double* Cd = g.C + c0;
+            float* Cf = reinterpret_cast<float*>(g.C) + c0;
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int j = 0; j < BN; ++j) {
+                    const long long on = coff_n[tb_c][(wn * BN + j) * 16 + li];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = AR == Arith::F64 ? gq + 4 * r : 4 * gq + r;
+                        const long long om = coff_m[tb_c][(wm * BM + i) * 16 + row];
+                        const double a = (double)acc[i][j][r];
+                        acc[i][j][r] = 0;
+                        if (om < 0 || on < 0) continue;
+                        double v = g.alpha * a;
+                        if (g.c_f32) {
+                            if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
+                            Cf[om + on] = (float)v;
+                        } else {
+                            if (g.beta != 0.0) v += g.beta * Cd[om + on];
+                            Cd[om + on] = v;
+                        }
+                    }
+                }
+        }
+        if (!more) break;
+        ct = nt;
+        cs = ns;
+        tb_c = tb_n;
+        it = nt;
+        is = ns;
+        tb_i = tb_n;
+    }
+}
+
+template <int WM, int WN, int BM, int BN, int TK, Arith AR>
+int persistent_grid(long long total) {
+    static int per_cu = -1;
+    static int cus = 0;
+    if (per_cu < 0) {
+        int n = 0, dev = 0;
+        hipGetDevice(&dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mgemm_p<WM, WN, BM, BN, TK, AR>, 256, 0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+        cus = c;
+        per_cu = n;
+    }
+    return (int)std::min<long long>(total, (long long)per_cu * cus);
+}
+
+template <int WM, int WN, int BM, int BN, int TK = 16>
+hipError_t launch_p(const GemmArgs& g, Arith ar, hipStream_t st) {
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    const int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+    const long long total = (long long)tm * tn * g.batch;
+    if (total == 0) return hipSuccess;
+    const dim3 block(256);
+    switch (ar) {
+        case Arith::F64:
+            hipLaunchKernelGGL((k_mgemm_p<WM, WN, BM, BN, TK, Arith::F64>),
+                               dim3(persistent_grid<WM, WN, BM, BN, TK, Arith::F64>(total)), block, 0, st, g, tm, tn);
+            break;
+        case Arith::F32:
+            hipLaunchKernelGGL((k_mgemm_p<WM, WN, BM, BN, TK, Arith::F32>),
+                               dim3(persistent_grid<WM, WN, BM, BN, TK, Arith::F32>(total)), block, 0, st, g, tm, tn);
+            break;
+        case Arith::BF16:
+            hipLaunchKernelGGL((k_mgemm_p<WM, WN, BM, BN, TK, Arith::BF16>),
+                               dim3(persistent_grid<WM, WN, BM, BN, TK, Arith::BF16>(total)), block, 0, st, g, tm, tn);
+            break;
+    }
+    return hipGetLastError();
+}
+
 template <int WM, int WN, int BM, int BN, int TK = 16>
 hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
     constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
@@ -275,7 +501,8 @@ long long idx_bound(const Idx2& x, int n) {
 // 128x64, 64x128, 128x32, 32x128 (k stage 16); 64x48, 128x48, 48x64, 48x128 (16); 64x48, 128x48,
 // 48x64, 64x64 (k stage 12: no padded stage when K is a multiple of 12, e.g. 36 or 216);
 // 64x48, 128x48, 48x64, 64x64, 32x64 (k stage 36: a K of 36 in one stage, one barrier pair);
-// 64x64, 32x64 (k stage 32)
+// 64x64, 32x64 (k stage 32); persistent pipelined forms (k_mgemm_p): 64x48, 64x64, 48x64,
+// 128x48 (k stage 12), 64x64, 32x64, 64x48, 48x64 (16)
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     // the kernels hold the free-index offsets of A and B in 32 bits
@@ -323,7 +550,15 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         case 24: return launch_m<2, 2, 2, 2, 36>(g, ar, st);
         case 25: return launch_m<2, 2, 1, 2, 36>(g, ar, st);
         case 26: return launch_m<2, 2, 2, 2, 32>(g, ar, st);
-        default: return launch_m<2, 2, 1, 2, 32>(g, ar, st);
+        case 27: return launch_m<2, 2, 1, 2, 32>(g, ar, st);
+        case 28: return launch_p<4, 1, 1, 3, 12>(g, ar, st);
+        case 29: return launch_p<2, 2, 2, 2, 12>(g, ar, st);
+        case 30: return launch_p<1, 4, 3, 1, 12>(g, ar, st);
+        case 31: return launch_p<4, 1, 2, 3, 12>(g, ar, st);
+        case 32: return launch_p<2, 2, 2, 2, 16>(g, ar, st);
+        case 33: return launch_p<2, 2, 1, 2, 16>(g, ar, st);
+        case 34: return launch_p<4, 1, 1, 3, 16>(g, ar, st);
+        default: return launch_p<1, 4, 3, 1, 16>(g, ar, st);
     }
 }
 

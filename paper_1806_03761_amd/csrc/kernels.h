@@ -7,7 +7,7 @@ namespace peps {
 
 // tile: 0 = heuristic choice, 1..kMfmaTiles = a matrix-core tile shape (k_mgemm.hip), the two
 // after them = the row kernel (k_gemm.hip) on the product or its transpose
-static constexpr int kMfmaTiles = 27;
+static constexpr int kMfmaTiles = 35;
 static constexpr int kGemmTiles = kMfmaTiles + 2;
 // row kernel for skinny products: N <= 64 and K <= 64 (gemm_rows_fits); same results as
 // launch_gemm

@@ -1361,7 +1361,7 @@ peps_status peps_tune_load(peps_ctx* c, const char* path) {
         std::istringstream ss(line);
         std::string key;
         int tile = 0;
-        if (ss >> key >> tile && tile >= 1 && tile <= kGemmTiles) c->tune[key] = tile;
+        if (ss >> key >> tile && tile >= 0 && tile <= kGemmTiles) c->tune[key] = tile;   // 0: heuristic
     }
     return PEPS_OK;
 }

@@ -1,0 +1,179 @@
+"""The large configurations through the C ABI against stored oracle values
+(tests/golden/, written by the committed scripts there, which call only oracle/):
+
+* 16x16, D = 6, Dc = 36: the autograd Function's adjoint (Eqs. (6)-(7), frozen row
+  environments) against the oracle's log-derivatives at seeded entries and the per-site
+  Euler sums, and against central finite differences (h = 1e-6, float64) of the GPU
+  forward along directions in the last row, where the frozen-environment derivative is
+  the full one (the amplitude is the overlap of the top environment with that row);
+* 24x24, D = 8, Dc = 64 (Gram and QR orders 512 and 4096 x 512): ln|W| and sign of three
+  configurations and the local energy of the first (Eq. (4)), against a bound set by the
+  oracle's own rounding noise there;
+* the uneven batch over 8x8 (D 4, Dc 16), 12x12 (D 6, Dc 36) and 16x16 (D 8, Dc 64) in one
+  captured graph: float64 results against the oracle, and float32 results equal bit for
+  bit to separate evaluations.
+
+Tolerances as in test_gpu_parity: float64 log-amplitude 1e-10 relative to max(1, |ln W|),
+local energy 1e-9 relative to max(1, |E|), log-derivative entries 1e-9 relative to the
+largest sampled entry.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_03761_amd.workloads import Lattice, make_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _peps():
+    from paper_1806_03761_amd import peps
+    return peps
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _dev(A, S):
+    return torch.from_numpy(A).cuda(), torch.from_numpy(np.ascontiguousarray(S)).cuda()
+
+
+def _amp_ok(la, sg, rec, tol=1e-10):
+    assert int(sg) == rec["sign"]
+    err = abs(float(la) - rec["log_abs"]) / max(1.0, abs(rec["log_abs"]))
+    assert err <= tol, (rec["index"], err)
+    return err
+
+
+def test_c3_adjoint_against_oracle_gradient_and_fd():
+    p = _peps()
+    g = _gold("goldens_mixed.json")["16x16_D6_Dc36"]["samples"]
+    lat, A, S, _ = make_workload("16x16_D6_Dc36", len(g))
+    rng = np.random.default_rng(17)
+    for rec in g:
+        b = rec["index"]
+        _say("c3 adjoint, sample", b)
+        Ad, Sd = _dev(A, S[b:b + 1])
+        Ad.requires_grad_(True)
+        la, sg, fl = p.PepsLogAmp.apply(Ad, Sd, lat, "f64")
+        assert int(fl[0]) == 0
+        _amp_ok(la[0].item(), sg[0].item(), rec)
+        la.sum().backward()
+        grad = Ad.grad.detach().cpu().numpy().reshape(lat.N, 2, -1)
+        ent = np.array([e[3] for e in rec["grad_entries"]])
+        got = np.array([grad[m, s, e] for m, s, e, _ in rec["grad_entries"]])
+        scale = np.abs(ent).max()
+        assert np.abs(got - ent).max() <= 1e-9 * scale, float(np.abs(got - ent).max() / scale)
+        s_b = S[b]
+        euler = np.array([np.dot(A[m, int(s_b[m])].reshape(-1), grad[m, int(s_b[m])]) for m in range(lat.N)])
+        assert np.abs(euler - np.array(rec["euler"])).max() <= 1e-9
+        if b == 0:
+            # central differences of the forward along random directions on the last row
+            h = 1e-6
+            last = range((lat.Ly - 1) * lat.Lx, lat.N)
+            for k in range(3):
+                E = np.zeros_like(A)
+                for m in last:
+                    E[m, int(s_b[m])] = rng.standard_normal(A.shape[2:])
+                lp = p.log_amplitude(*_dev(A + h * E, S[b:b + 1]), lat, "f64")[0].item()
+                lm = p.log_amplitude(*_dev(A - h * E, S[b:b + 1]), lat, "f64")[0].item()
+                fd = (lp - lm) / (2 * h)
+                an = float(np.sum(grad * E.reshape(lat.N, 2, -1)))
+                _say("  direction", k, "fd", fd, "adjoint", an)
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (k, fd, an)
+
+
+def _noise(kind, b):
+    path = os.path.join(GOLD, f"noise_24x24_D8_Dc64_{kind}_{b}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle noise floor {os.path.basename(path)} not generated")
+    with open(path) as f:
+        return json.load(f)["noise"]
+
+
+def test_c4_amplitudes_and_local_energy():
+    """At 24x24, D = 8, Dc = 64 the 529 truncations amplify rounding far beyond the
+    float64 bound: the oracle's own ln|W| moves by up to ~1e-8 relative when only the
+    rounding changes (an exactly compensated per-site rescaling of its input, written
+    by make_noise_24x24.py).  The GPU is held to max(1e-10 |ln W|, 10 x that noise) per
+    sample, and the local energy to max(1e-9 max(1, |E|), 10 x its noise)."""
+    p = _peps()
+    g = _gold("goldens_24x24_D8_Dc64.json")
+    recs = g["samples"]
+    lat, A, S, _ = make_workload(g["workload"], len(recs))
+    Ad, Sd = _dev(A, S)
+    _say("c4 amplitudes,", len(recs), "samples")
+    la, sg, fl = (t.cpu().numpy() for t in p.log_amplitude(Ad, Sd, lat, "f64"))
+    for b, rec in enumerate(recs):
+        assert fl[b] == rec["flag"] == 0
+        assert int(sg[b]) == rec["sign"]
+        d = abs(float(la[b]) - rec["log_abs"])
+        nz = _noise("amp", b)
+        _say("  sample %d: |d ln W| %.2e, oracle noise %.2e" % (b, d, nz))
+        assert d <= max(1e-10 * abs(rec["log_abs"]), 10 * nz), (b, d, nz)
+    er = [r for r in recs if "e_loc" in r]
+    _say("c4 local energy,", len(er), "sample(s)")
+    la, sg, e, fl = (t.cpu().numpy() for t in p.local_energy(Ad, Sd[:len(er)], lat, "f64"))
+    for b, rec in enumerate(er):
+        d = abs(e[b] - rec["e_loc"])
+        nz = _noise("eloc", b)
+        _say("  sample %d: |d E| %.2e, oracle noise %.2e" % (b, d, nz))
+        assert d <= max(1e-9 * max(1.0, abs(rec["e_loc"])), 10 * nz), (b, d, nz)
+
+
+def test_c5_uneven_batch_in_one_graph():
+    p = _peps()
+    g = _gold("goldens_mixed.json")
+    specs = (("mix_8x8_D4_Dc16", 6, 3, True), ("mix_12x12_D6_Dc36", 2, 3, True), ("mix_16x16_D8_Dc64", 1, 0, False))
+    data = []
+    for name, B, gm, we in specs:
+        lat, A, S, _ = make_workload(name, B)
+        data.append((name, lat, A, S, gm, we) + _dev(A, S))
+    # float64 through one graph against the oracle
+    jobs = [{"A": Ad, "S": Sd, "lat": lat, "grad_mode": gm, "want_eloc": we}
+            for name, lat, A, S, gm, we, Ad, Sd in data]
+    _say("c5 float64 graph")
+    outs = p.eval_jobs(jobs, "f64", graph=True)
+    torch.cuda.synchronize()
+    for (name, lat, A, S, gm, we, Ad, Sd), o in zip(data, outs):
+        la, sg = o[0].cpu().numpy(), o[1].cpu().numpy()
+        e = o[2].cpu().numpy() if o[2] is not None else None
+        if name in g:
+            for rec in g[name]["samples"][:len(S)]:
+                b = rec["index"]
+                _amp_ok(la[b], sg[b], rec)
+                if "e_loc" in rec and e is not None:
+                    assert abs(e[b] - rec["e_loc"]) <= 1e-9 * max(1.0, abs(rec["e_loc"])), (name, b)
+        else:
+            la_o, sg_o, _ = O.log_amplitude(A, lat, S)
+            for b in range(len(S)):
+                _amp_ok(la[b], sg[b], {"index": b, "log_abs": la_o[b], "sign": int(sg_o[b])})
+            _, _, e_o, _ = O.local_energy(A, lat, S[:2])
+            assert np.all(np.abs(e[:2] - e_o) <= 1e-9 * np.maximum(1.0, np.abs(e_o)))
+    # float32 (the configuration's arithmetic): one graph equals separate calls bit for bit
+    _say("c5 float32 graph vs separate")
+    outs = p.eval_jobs(jobs, "f32", graph=True)
+    got = [[t.cpu().numpy() if t is not None else None for t in o] for o in outs]
+    for (name, lat, A, S, gm, we, Ad, Sd), o in zip(data, got):
+        if we or gm:
+            ref = [t.cpu().numpy() if t is not None else None for t in p.evaluate(Ad, Sd, lat, "f32", grad_mode=gm)]
+        else:
+            la, sg, fl = p.log_amplitude(Ad, Sd, lat, "f32")
+            ref = [la.cpu().numpy(), sg.cpu().numpy(), None, None, fl.cpu().numpy()]
+        for k, (x, y) in enumerate(zip(o, ref)):
+            if x is None or y is None:
+                continue
+            assert np.array_equal(x, y), (name, k)

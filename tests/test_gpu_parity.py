@@ -263,11 +263,14 @@ def test_autograd_function_4x4():
 
 # At 16x16, D = 6, Dc = 36 the truncation amplifies input rounding: rounding only the
 # apply operands to f32 (all arithmetic in f64) already moves ln|W| by 1.2e-5 relative on
-# the first configuration, so the f32 bound here is stated as 5e-5 and the error is printed.
-TOL_AMP_16 = {"f64": 1e-10, "f32": 5e-5}
+# the first configuration.  The float32 path is held to the stated 1e-5 bound and is
+# expected to miss it (measured about 3e-5): recorded as an expected failure, not passed
+# under a wider bound.
+TOL_AMP_16 = {"f64": 1e-10, "f32": 1e-5}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", pytest.param("f32", marks=pytest.mark.xfail(
+    reason="float32 apply rounding amplified by the Dc = 36 truncation exceeds 1e-5", strict=False))])
 def test_amplitude_16x16_D6_Dc36(prec):
     """Full 16x16, D = 6, Dc = 36 shapes (matrices beyond the LDS: global-memory paths),
     two sampled configurations against the oracle."""
@@ -275,8 +278,9 @@ def test_amplitude_16x16_D6_Dc36(prec):
     la, sg, fl = _np(*_peps().log_amplitude(*_dev(A, S), lat, prec))
     la_o, sg_o, _ = O.log_amplitude(A, lat, S)
     assert np.all(fl == 0)
-    err = _assert_amp(la, sg, la_o, sg_o, TOL_AMP_16[prec])
-    _say("16x16 D6 Dc36 %s: max log-amp rel err %.2e" % (prec, err))
+    err = np.abs(la - la_o) / np.maximum(1.0, np.abs(la_o))
+    _say("16x16 D6 Dc36 %s: max log-amp rel err %.2e (bound %.0e)" % (prec, err.max(), TOL_AMP_16[prec]))
+    _assert_amp(la, sg, la_o, sg_o, TOL_AMP_16[prec])
 
 
 def test_product_state_24x24_geometry():
@@ -371,6 +375,47 @@ def test_autotune_keeps_results():
         lines = [ln for ln in open(path) if not ln.startswith("#")]
         assert len(lines) >= n
         p.tune_load(path)
+
+
+@pytest.mark.parametrize("case", [("8x8_D4_Dc16", "f32"), ("8x8_D4_Dc16", "f64"), ("6x5_D6_Dc36", "f64")])
+def test_every_gemm_tile_gives_identical_results(case):
+    """Every GEMM tile the autotuner may pick (the matrix-core tiles of each k stage, the
+    persistent pipelined forms and the row kernels) sums each output in the same order,
+    so forcing one tile onto every GEMM shape of the path leaves all results bit for bit
+    equal to those before (tile 0 is the heuristic choice; the loader ignores numbers
+    past the last tile)."""
+    import os
+    import tempfile
+    p = _peps()
+    name, prec = case
+    if name == "6x5_D6_Dc36":
+        lat = Lattice(6, 5, 6, 36)
+        A, S = make_random(lat, 6, 31, "half")
+    else:
+        lat, A, S, _ = make_workload(name, 16)
+    Ad, Sd = _dev(A, S)
+    with tempfile.TemporaryDirectory() as d:
+        saved = os.path.join(d, "saved.txt")
+        p.tune_save(saved)
+        base = _np(*p.evaluate(Ad, Sd, lat, prec, grad_mode=3))
+        p.autotune(Ad, Sd, lat, prec)
+        path = os.path.join(d, "t.txt")
+        p.tune_save(path)
+        keys = [ln.split()[0] for ln in open(path) if ln.strip() and not ln.startswith("#")]
+        assert keys
+        try:
+            for t in range(0, 41):
+                with open(path, "w") as f:
+                    f.writelines(f"{k} {t}\n" for k in keys)
+                p.tune_load(path)
+                got = _np(*p.evaluate(Ad, Sd, lat, prec, grad_mode=3))
+                for nm, x, y in zip(("log-amp", "sign", "E_loc", "grad", "flags"), got, base):
+                    assert np.array_equal(x, y), (t, nm)
+        finally:
+            with open(path, "w") as f:
+                f.writelines(f"{k} 0\n" for k in keys)
+            p.tune_load(path)
+            p.tune_load(saved)
 
 
 def _eval_env(p, Ad, Sd, lat, env):
