@@ -17,37 +17,11 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "mfma_ops.h"
 
 namespace peps {
 
 namespace {
-
-typedef double mf64x4 __attribute__((ext_vector_type(4)));
-typedef float mf32x4 __attribute__((ext_vector_type(4)));
-
-template <Arith AR> struct MT;
-template <> struct MT<Arith::F64> { using In = double; using Acc = mf64x4; };
-template <> struct MT<Arith::F32> { using In = float; using Acc = mf32x4; };
-template <> struct MT<Arith::BF16> { using In = float; using Acc = mf32x4; };
-
-template <Arith AR>
-__device__ __forceinline__ typename MT<AR>::In to_mt(double x) {
-    if constexpr (AR == Arith::F64) {
-        return x;
-    } else if constexpr (AR == Arith::F32) {
-        return (float)x;
-    } else {
-        // operands rounded to bfloat16 (nearest-even); their products are exact in float32
-        return __bfloat162float(__float2bfloat16((float)x));
-    }
-}
-
-template <Arith AR>
-__device__ __forceinline__ typename MT<AR>::Acc mfma(typename MT<AR>::In a, typename MT<AR>::In b,
-                                                     typename MT<AR>::Acc c) {
-    if constexpr (AR == Arith::F64) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // Per-thread share of one operand tile (TK x TW entries): NI loads.  Entry e of the tile
 // maps to (k, w) either w-fastest (consecutive threads walk the free index) or k-fastest,

@@ -434,9 +434,8 @@ def _eval_env(p, Ad, Sd, lat, env):
 
 def test_fused_pair_step_matches_gemm_path():
     """The fused sandwich steps accumulate every product in the order of the unfused
-    GEMMs (float32 operands, fma, k ascending), so amplitudes, local energies and
-    log-derivatives equal those of the GEMM path exactly: the vector form of the
-    two-row step directly, the matrix-core form because each 16x16x4 MFMA sums its four
+    GEMMs (float32 operands, k ascending), so amplitudes, local energies and
+    log-derivatives equal those of the GEMM path exactly: each 16x16x4 MFMA sums its four
     products in k order with one rounding per product and the operands are laid out so
     that consecutive MFMAs take consecutive k."""
     p = _peps()
