@@ -82,11 +82,13 @@ def finish_cpu_baseline(h, name):
                       f"steps; wall {dt:.1f} s"}
 
 
-# HBM traffic per launch of the dominant kernel class, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE) over one evaluation of the headline workload, scaled by the
-# same counters on a 256 MiB device copy (profiles/); valid only for the kernel sources
-# they were measured on (hash below), otherwise reported as null.
-TRAFFIC = {"sources": None, "workload": "16x16_D6_Dc36", "bytes_per_launch": {}}
+# HBM traffic per launch of the contraction GEMMs, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) over one evaluation, each scaled by what the
+# same counter reads for a 256 MiB device copy (FETCH_SIZE reads half of the copied bytes:
+# factor 2.0; WRITE_SIZE all: 1.0).  Valid only for the kernel sources they were measured
+# on (hash below) and the workload, arithmetic and batch named; otherwise null.
+TRAFFIC = {"sources": "bf7db4f2a91ebdbf",
+           "bytes_per_launch": {("8x8_D4_Dc16", "f64", 4096, "gemm"): 168.7e6}}
 
 
 def _sources_hash() -> str:
@@ -232,7 +234,10 @@ def main():
         torch.cuda.synchronize()
         _log(f"warm-up step {k + 1}")
     kern = _read(peps, CLASSES)
-    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    # the roofline kernel: the contraction kernel family with the most time (the MFMA GEMMs,
+    # or the fused sandwich steps where those replace them); the factorisation classes are
+    # reported beside it
+    dom = "gemm" if kern["gemm"]["ms_total"] >= kern["fused"]["ms_total"] else "fused"
     cpu = finish_cpu_baseline(cpu_h, name) if cpu_h else None
     _log("cpu baseline done" if cpu else "no cpu baseline")
     # progress lines in the timed region only for slow steps (the host runs ahead of the
@@ -275,13 +280,14 @@ def main():
                    "gemm_precision": args.prec, "factorisation_precision": "f64",
                    "autotuned_gemm_shapes": tuned},
     }
-    peak = MI355X_PEAK["f64"] if dom in ("svd", "qr") else MI355X_PEAK[args.prec if args.prec != "bf16" else "f32"]
+    peak = MI355X_PEAK[args.prec if args.prec != "bf16" else "f32"]
     traffic = None
-    if TRAFFIC["sources"] == _sources_hash() and TRAFFIC["workload"] == name and B == WORKLOADS[name].batch:
-        traffic = TRAFFIC["bytes_per_launch"].get(dom)
+    if TRAFFIC["sources"] == _sources_hash():
+        traffic = TRAFFIC["bytes_per_launch"].get((name, args.prec, B, dom))
     res["roofline"] = {"kernel": CLASS_NAMES[dom], "class": dom, "bound": "mfma", "achieved": timed["tflops"],
                        "peak": peak, "unit": "TFLOP/s", "frac": timed["tflops"] / peak,
-                       "traffic": traffic, "avg_launch_us": timed["avg_us"], "launches": timed["launches"]}
+                       "traffic": traffic, "avg_launch_us": timed["avg_us"], "launches": timed["launches"],
+                       "share_of_kernel_time": kern[dom]["ms_total"] / max(sum(v["ms_total"] for v in kern.values()), 1e-9)}
     # every class against the dtype's matrix-core peak (the factorisations against fp64)
     res["kernels_warmup"] = {k: dict(v, frac_of_peak=v["tflops"] / (MI355X_PEAK["f64"] if k in ("svd", "qr") else peak))
                              for k, v in kern.items()}
