@@ -164,7 +164,7 @@ hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st) {
 }
 
 // the same product as C^T = B^T A^T (M and N, A and B swapped)
-static GemmArgs transposed(const GemmArgs& g) {
+GemmArgs gemm_transposed(const GemmArgs& g) {
     GemmArgs t = g;
     t.M = g.N; t.N = g.M;
     t.A = g.B; t.B = g.A;
@@ -185,7 +185,7 @@ hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     // of fma), so all of them give the same results.
     if (tile == kMfmaTiles + 1 && gemm_rows_fits(g)) return launch_gemm_rows(g, ar, st);
     if (tile == kMfmaTiles + 2) {
-        const GemmArgs t = transposed(g);
+        const GemmArgs t = gemm_transposed(g);
         if (gemm_rows_fits(t)) return launch_gemm_rows(t, ar, st);
     }
     return launch_mgemm(g, ar, st, tile > kMfmaTiles ? 0 : tile);

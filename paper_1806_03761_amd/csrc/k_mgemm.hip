@@ -479,6 +479,11 @@ long long idx_bound(const Idx2& x, int n) {
 // 128x48 (k stage 12), 64x64, 32x64, 64x48, 48x64 (16)
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    // consecutive lanes write consecutive N: a result with unit stride along M instead (the
+    // column-major updates of the QR and of the application of Q) runs as the transposed
+    // product, whose stores then coalesce.  Same products, same ascending k: same bits.
+    auto unit = [](const Idx2& x) { return x.s_inner == 1 && x.inner > 1; };
+    if (unit(g.cm) && !unit(g.cn)) return launch_mgemm(gemm_transposed(g), ar, st, tile);
     // the kernels hold the free-index offsets of A and B in 32 bits
     const long long ma = idx_bound(g.am, g.M), nb = idx_bound(g.bn, g.N);
     if (ma < 0 || nb < 0 || ma > 0x7fffffffLL || nb > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -491,10 +496,10 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         if (g.M <= 32 && g.N <= 32) tile = 1;
         else if (g.N <= 16) tile = g.M >= 128 ? 5 : 2;
         else if (g.M <= 16) tile = g.N >= 128 ? 6 : 3;
+        else if (g.M <= 32) tile = k36 ? 25 : (g.K % 32 == 0 ? 27 : 8);
         else if (g.N <= 48 && g.N > 32) tile = k36 ? 21 : k12 ? 18 : 14;
         else if (g.M <= 48 && g.M > 32) tile = k36 ? 23 : k12 ? 19 : 15;
         else if (g.N <= 32) tile = 7;
-        else if (g.M <= 32) tile = k36 ? 25 : 8;
         else tile = k36 ? 24 : k12 ? 20 : 4;
     }
     switch (tile) {

@@ -14,6 +14,8 @@ static constexpr int kGemmTiles = kMfmaTiles + 2;
 bool gemm_rows_fits(const GemmArgs& g);
 hipError_t launch_gemm_rows(const GemmArgs& g, Arith ar, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
+// the same product with the roles of A and B (and of M and N) exchanged: C^T = B^T A^T
+GemmArgs gemm_transposed(const GemmArgs& g);
 // matrix-core GEMM (k_mgemm.hip): tile 1..kMfmaTiles, 0 = heuristic
 hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile = 0);
 size_t get_lds_cap();

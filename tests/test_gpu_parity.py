@@ -283,6 +283,31 @@ def test_amplitude_16x16_D6_Dc36(prec):
     _assert_amp(la, sg, la_o, sg_o, TOL_AMP_16[prec])
 
 
+@pytest.mark.xfail(reason="float32 environments move the exchange ratios of about 14% of these "
+                          "configurations by more than 1e-4 (the log-amplitudes stay within 1e-5)",
+                   strict=False)
+def test_float32_local_energy_tail_over_512_samples():
+    """Local energies of the first 512 configurations of the 8x8, D = 4, Dc = 16 batch
+    in float32 against the float64 path (which matches the oracle to 1e-9 on the tested
+    samples), held to the stated 1e-4 bound on every sample, with median / p99 / max
+    printed.  The log-amplitudes meet the float32 bound of 1e-5 and the signs agree.
+    Running only the sandwich and environment GEMMs in float64 (float32 apply) leaves
+    the same tail, so it comes from the float32 environments, not the sandwiches."""
+    p = _peps()
+    lat, A, S, _ = make_workload("8x8_D4_Dc16", 512)
+    Ad, Sd = _dev(A, S)
+    la0, sg0, e0, fl0 = _np(*p.local_energy(Ad, Sd, lat, "f64"))
+    la, sg, e, fl = _np(*p.local_energy(Ad, Sd, lat, "f32"))
+    assert ((fl == 0) & (fl0 == 0)).all()
+    err = np.abs(e - e0) / np.maximum(1.0, np.abs(e0))
+    ea = np.abs(la - la0) / np.maximum(1.0, np.abs(la0))
+    _say("8x8 f32 over 512: E_loc err median %.2e p99 %.2e max %.2e (%d above 1e-4); log-amp max %.2e"
+         % (np.median(err), np.quantile(err, 0.99), err.max(), int((err > 1e-4).sum()), ea.max()))
+    assert np.array_equal(sg, sg0)
+    assert ea.max() <= 1e-5
+    assert err.max() <= 1e-4
+
+
 def test_product_state_24x24_geometry():
     """24x24 open lattice (the largest lattice of the paper's runs) with a random product
     state embedded at D = 2 (Dc = 4, gauge-dressed): closed-form ln|W| and E(S) at any size."""
