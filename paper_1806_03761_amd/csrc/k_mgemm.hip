@@ -101,7 +101,58 @@ __device__ __forceinline__ void tile_store(typename MT<AR>::In* dst, const unsig
     }
 }
 
-template <int WM, int WN, int BM, int BN, int TK, Arith AR>
+// Output of one wave's blocks: C = alpha acc (+ beta C).  Lane (li, gq) holds column li of
+// each 16 x 16 block, rows 4 gq + r (float32 MFMA) or gq + 4 r (float64 MFMA).  With
+// beta != 0 and GATHER (the float64 factorisation updates), all of the lane's old values are
+// loaded before any is used (read without a branch, p[ok ? o : 0]), so their latencies
+// overlap instead of adding up; the other launches keep those registers free.
+template <int BM, int BN, Arith AR, bool GATHER, class Acc>
+__device__ __forceinline__ void tile_out(const Acc (&acc)[BM][BN], const GemmArgs& g, long long c0,
+                                         const long long* coff_m, const long long* coff_n, int wm, int wn, int li,
+                                         int gq) {
+    double* Cd = g.C + c0;
+    float* Cf = reinterpret_cast<float*>(g.C) + c0;
+    auto off = [&](int i, int j, int r) -> long long {
+        const int row = AR == Arith::F64 ? gq + 4 * r : 4 * gq + r;
+        const long long om = coff_m[(wm * BM + i) * 16 + row], on = coff_n[(wn * BN + j) * 16 + li];
+        return (om < 0 || on < 0) ? -1 : om + on;
+    };
+    double old[GATHER ? BM : 1][GATHER ? BN : 1][4];
+#pragma unroll
+    for (int i = 0; i < (GATHER ? BM : 1); ++i)
+#pragma unroll
+        for (int j = 0; j < (GATHER ? BN : 1); ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) old[i][j][r] = 0.0;
+    if (GATHER && g.beta != 0.0) {
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+            for (int j = 0; j < BN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long long o = off(i, j, r);
+                    const long long oo = o >= 0 ? o : 0;
+                    old[GATHER ? i : 0][GATHER ? j : 0][r] = g.c_f32 ? (double)Cf[oo] : Cd[oo];
+                }
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long o = off(i, j, r);
+                if (o < 0) continue;
+                double v = g.alpha * (double)acc[i][j][r];
+                if (g.beta != 0.0)
+                    v += g.beta * (GATHER ? old[GATHER ? i : 0][GATHER ? j : 0][r] : (g.c_f32 ? (double)Cf[o] : Cd[o]));
+                if (g.c_f32) Cf[o] = (float)v;
+                else Cd[o] = v;
+            }
+}
+
+template <int WM, int WN, int BM, int BN, int TK, Arith AR, bool GATHER = false>
 __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tiles_n) {
     using In = typename MT<AR>::In;
     using Acc = typename MT<AR>::Acc;
@@ -193,30 +244,7 @@ __global__ __launch_bounds__(256) void k_mgemm(GemmArgs g, int tiles_m, int tile
                 for (int j = 0; j < BN; ++j) acc[i][j] = mfma<AR>(av[i], bv[j], acc[i][j]);
         }
     }
-    // lane (li, gq) holds column li of each 16 x 16 block, rows 4 gq + r (float32 MFMA) or
-    // gq + 4 r (float64 MFMA)
-    double* Cd = g.C + c0;
-    float* Cf = reinterpret_cast<float*>(g.C) + c0;
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-        for (int j = 0; j < BN; ++j) {
-            const long long on = coff_n[(wn * BN + j) * 16 + li];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = AR == Arith::F64 ? gq + 4 * r : 4 * gq + r;
-                const long long om = coff_m[(wm * BM + i) * 16 + row];
-                if (om < 0 || on < 0) continue;
-                double v = g.alpha * (double)acc[i][j][r];
-                if (g.c_f32) {
-                    if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
-                    Cf[om + on] = (float)v;
-                } else {
-                    if (g.beta != 0.0) v += g.beta * Cd[om + on];
-                    Cd[om + on] = v;
-                }
-            }
-        }
+    tile_out<BM, BN, AR, GATHER>(acc, g, c0, coff_m, coff_n, wm, wn, li, gq);
 }
 
 // Persistent form of k_mgemm for the short-K products that bound the contraction chain
@@ -364,34 +392,16 @@ __global__ __launch_bounds__(256) void k_mgemm_p(GemmArgs g, int tiles_m, int ti
                 for (int j = 0; j < BN; ++j) acc[i][j] = mfma<AR>(av[i], bv[j], acc[i][j]);
         }
         if (cs == nst - 1) {
-            // output of tile ct; lane (li, gq) holds column li of each 16 x 16 block, rows
-            // 4 gq + r (float32 MFMA) or gq + 4 r (float64 MFMA)
+            // output of tile ct, then the accumulators restart for the next tile
             const int b = (int)(ct / tiles);
             const long long c0 = (long long)b * g.c_bs + gather_off(g.gc, b);
-            double* Cd = g.C + c0;
-            float* Cf = reinterpret_cast<float*>(g.C) + c0;
+            tile_out<BM, BN, AR, false>(acc, g, c0, coff_m[tb_c], coff_n[tb_c], wm, wn, li, gq);
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll
-                for (int j = 0; j < BN; ++j) {
-                    const long long on = coff_n[tb_c][(wn * BN + j) * 16 + li];
+                for (int j = 0; j < BN; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = AR == Arith::F64 ? gq + 4 * r : 4 * gq + r;
-                        const long long om = coff_m[tb_c][(wm * BM + i) * 16 + row];
-                        const double a = (double)acc[i][j][r];
-                        acc[i][j][r] = 0;
-                        if (om < 0 || on < 0) continue;
-                        double v = g.alpha * a;
-                        if (g.c_f32) {
-                            if (g.beta != 0.0) v += g.beta * (double)Cf[om + on];
-                            Cf[om + on] = (float)v;
-                        } else {
-                            if (g.beta != 0.0) v += g.beta * Cd[om + on];
-                            Cd[om + on] = v;
-                        }
-                    }
-                }
+                    for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
         }
         if (!more) break;
         ct = nt;
@@ -454,7 +464,13 @@ hipError_t launch_m(const GemmArgs& g, Arith ar, hipStream_t st) {
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(256);
     switch (ar) {
-        case Arith::F64: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F64>), grid, block, 0, st, g, tm, tn); break;
+        case Arith::F64:
+            // the factorisation updates (beta != 0) read their old values all at once
+            if (g.beta != 0.0)
+                hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F64, true>), grid, block, 0, st, g, tm, tn);
+            else
+                hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F64>), grid, block, 0, st, g, tm, tn);
+            break;
         case Arith::F32: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::F32>), grid, block, 0, st, g, tm, tn); break;
         case Arith::BF16: hipLaunchKernelGGL((k_mgemm<WM, WN, BM, BN, TK, Arith::BF16>), grid, block, 0, st, g, tm, tn); break;
     }

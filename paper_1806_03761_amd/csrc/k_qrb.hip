@@ -59,8 +59,8 @@ __device__ __forceinline__ void block_sums(const double (&x)[NV], double (&out)[
 // for the tallest matrices so the panel stays in registers).  The WY blocks are always
 // stored as 16 x 16 T matrices (zero beyond the panel's reflectors), T of panel p at p*256.
 template <int RPT, int WG, int PW>
-__global__ __launch_bounds__(WG) void k_qrb_panel(double* X, long long xs, int m, int n, int k0, double* tau,
-                                                  long long ts, double* Tw, long long tws) {
+__device__ __forceinline__ void qrb_panel(double* X, long long xs, int m, int n, int k0, double* tau, long long ts,
+                                          double* Tw, long long tws) {
     __shared__ double red[(WG / 64) * PW];
     __shared__ double vtv[4 * 256];
     __shared__ double Ts[NB * NB];
@@ -200,6 +200,12 @@ __global__ __launch_bounds__(WG) void k_qrb_panel(double* X, long long xs, int m
     __syncthreads();
     if (tid < 256) Tw[(long long)b * tws + (long long)(k0 / PW) * NB * NB + tid] = Ts[tid];
     if (tid < nref) tau[(long long)b * ts + k0 + tid] = tvs[tid];
+}
+
+template <int RPT, int WG, int PW>
+__global__ __launch_bounds__(WG) void k_qrb_panel(double* X, long long xs, int m, int n, int k0, double* tau,
+                                                  long long ts, double* Tw, long long tws) {
+    qrb_panel<RPT, WG, PW>(X, xs, m, n, k0, tau, ts, Tw, tws);
 }
 
 // A <- op(Q_b)^T-style update of columns [c0, c0 + 16) of A over rows [k0, m):

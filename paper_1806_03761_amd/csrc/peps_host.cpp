@@ -374,13 +374,17 @@ public:
         if (it != ctx->tune.end()) {
             tile = it->second;
         } else if (ctx->tune_mode) {
-            // time every tile once on this very launch (all tiles give identical results)
+            // time every tile on this very launch (all tiles give identical results, and the
+            // product has beta = 0, so repeating it changes nothing): one untimed launch
+            // first, so a kernel's first-use cost does not count against it
             hipEvent_t ev[2];
             if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
                 return hipErrorUnknown;
             float best = 1e30f;
             int best_t = 0;
             for (int t = 1; t <= kGemmTiles; ++t) {
+                hipError_t e0 = launch_gemm(g, arith, st_, t);
+                if (e0 != hipSuccess) return e0;
                 hipEventRecord(ev[0], st_);
                 hipError_t e = launch_gemm(g, arith, st_, t);
                 hipEventRecord(ev[1], st_);
