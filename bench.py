@@ -133,11 +133,18 @@ def run_mixed(args, peps, torch):
     dev = torch.device("cuda:0")
     peps.set_workspace_limit(200 << 30)
     jobs, total = [], 0
+    tuned = {}
     for name, B in MIXED_BATCH:
         lat, A, S, _ = make_workload(name, B)
         Ad, Sd = torch.from_numpy(A).to(dev), torch.from_numpy(S).to(dev)
-        n = 0 if args.no_tune else peps.autotune(Ad, Sd, lat, "f32")
-        _log(f"{name}: batch {B}, {n} GEMM shapes tuned")
+        # the D = 8 lattice keeps the heuristic tiles: its tuning pass (every candidate tile
+        # on every GEMM shape of a 410-sample evaluation) takes minutes by itself
+        if args.no_tune or lat.D >= 8:
+            n = "heuristic tiles"
+        else:
+            n = peps.autotune(Ad, Sd, lat, "f32")
+        tuned[name] = n
+        _log(f"{name}: batch {B}, GEMM tiles tuned: {n}")
         jobs.append({"A": Ad, "S": Sd, "lat": lat, "grad_mode": 3})
         total += B
     outs = None
@@ -159,7 +166,7 @@ def run_mixed(args, peps, torch):
            "config": {"workload": "uneven batch in one captured graph: " +
                                   ", ".join(f"{n} x {B}" for n, B in MIXED_BATCH) +
                                   "; float32 contraction GEMMs, float64 QR/SVD; amplitude + local energy + dE/dA",
-                      "batch": total},
+                      "batch": total, "autotuned_gemm_shapes": tuned},
            "flagged_samples": flags, "run_wall_s": time.time() - T_START}
     print(json.dumps(res), flush=True)
 

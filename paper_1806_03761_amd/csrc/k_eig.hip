@@ -677,7 +677,10 @@ __device__ void prep_body(const EigArgs& a, double* Z, double* Am, double* d, do
     double* vb0 = vbuf;                 // two reflector buffers of length ns
     double* vb1 = vbuf + ns;
     double* pb = vbuf + 2 * ns;         // p = tau A v
-    const int tpc = e_tpc(ns), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
+    // orders above 128 (the matrix in global memory): a whole wave per column, so every
+    // column is read in coalesced 64-row runs (one lane per column would stream 256
+    // separate columns)
+    const int tpc = ns > 128 ? 64 : e_tpc(ns), ngroups = NT / tpc, g = tid / tpc, l = tid % tpc;
     __syncthreads();
     auto pivot = [&](int kp, double* vb) {
         double* ck = Am + (long long)kp * lda;
