@@ -505,9 +505,9 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
     if (ma < 0 || nb < 0 || ma > 0x7fffffffLL || nb > 0x7fffffffLL) return hipErrorInvalidValue;
     if (tile <= 0 || tile > kMfmaTiles) {
         // heuristic: the smallest tile that covers small products, 48-wide where a leg of
-        // 36 or 48 would leave a 64-wide tile part-empty, else 64 x 64; a k stage of 36 or
-        // 12 where it divides K, else 16
-        const bool k36 = g.K % 36 == 0;
+        // 36 or 48 would leave a 64-wide tile part-empty, else 64 x 64 (64 x 48 with a
+        // 12-deep stage); a k stage of 36 for K = 36 or 72, of 12 where it divides K, else 16
+        const bool k36 = g.K % 36 == 0 && g.K <= 72;   // longer K: the 36-deep tiles hold too many registers
         const bool k12 = !k36 && g.K % 12 == 0 && g.K % 16 != 0;
         if (g.M <= 32 && g.N <= 32) tile = 1;
         else if (g.N <= 16) tile = g.M >= 128 ? 5 : 2;
@@ -516,7 +516,7 @@ hipError_t launch_mgemm(const GemmArgs& g, Arith ar, hipStream_t st, int tile) {
         else if (g.N <= 48 && g.N > 32) tile = k36 ? 21 : k12 ? 18 : 14;
         else if (g.M <= 48 && g.M > 32) tile = k36 ? 23 : k12 ? 19 : 15;
         else if (g.N <= 32) tile = 7;
-        else tile = k36 ? 24 : k12 ? 20 : 4;
+        else tile = k36 ? 24 : k12 ? 17 : 4;
     }
     switch (tile) {
         case 1: return launch_m<2, 2, 1, 1>(g, ar, st);
