@@ -82,6 +82,13 @@ peps_status peps_destroy(peps_ctx* ctx);
 /* Stream on which all later work is enqueued (a hipStream_t; NULL = default stream). */
 peps_status peps_set_stream(peps_ctx* ctx, void* hip_stream);
 
+/* Fused float32 sandwich steps (enable != 0, the default): the single- and two-row steps
+ * of the float32 and bfloat16 modes with legs <= 4 and boundary bonds <= 16 run as one
+ * kernel each, summing every product in the order of the GEMM form, so their results
+ * equal the GEMM form's bit for bit.  enable = 0 keeps the GEMM form (a comparison
+ * switch; slower). */
+peps_status peps_set_fused_steps(peps_ctx* ctx, int32_t enable);
+
 /* Cap the device workspace in bytes (0 = default: 1/4 of free device memory at
  * first use).  Larger batches are processed in chunks that fit; a single sample
  * that does not fit returns PEPS_ERR_OOM. */

@@ -52,6 +52,7 @@ struct peps_ctx {
     size_t ws_limit = 0;
     double* ones = nullptr;   // 4096 ones
     char* scratch = nullptr;  // device address of this device's fixed scratch array
+    bool fused_steps = true;  // fused float32 sandwich steps where they fit (else the GEMM form)
     char* mc = nullptr;       // sampling buffers (peps_metropolis_step, peps_vmc_step)
     size_t mc_bytes = 0;
     char* corr = nullptr;     // exchanged configurations and their amplitudes (peps_pair_correlations)
@@ -138,9 +139,9 @@ public:
         // environment-tensor GEMMs then run in f32 (f32 and f64 use one type throughout)
         ar = prec == PEPS_PREC_F64 ? Arith::F64 : (prec == PEPS_PREC_F32 ? Arith::F32 : Arith::BF16);
         ar_sw = prec == PEPS_PREC_F64 ? Arith::F64 : Arith::F32;
-        // fused single- and two-row sandwich steps in float32 (PEPS_FUSE=0 keeps the GEMM form)
-        const char* fz = getenv("PEPS_FUSE");
-        fuse_pairs = ar_sw == Arith::F32 && D <= 4 && !(fz && strcmp(fz, "0") == 0);
+        // fused single- and two-row sandwich steps in float32 (peps_set_fused_steps(ctx, 0)
+        // keeps the GEMM form, with the same results)
+        fuse_pairs = ar_sw == Arith::F32 && D <= 4 && c->fused_steps;
         Dh.assign(Lx + 1, D); Dh[0] = Dh[Lx] = 1;
         Dv.assign(Ly + 1, D); Dv[0] = Dv[Ly] = 1;
         chiU.assign(Ly, std::vector<int>(Lx + 1, 1));
@@ -1054,6 +1055,12 @@ peps_status peps_set_stream(peps_ctx* c, void* s) {
     return PEPS_OK;
 }
 
+peps_status peps_set_fused_steps(peps_ctx* c, int32_t enable) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    c->fused_steps = enable != 0;
+    return PEPS_OK;
+}
+
 peps_status peps_set_workspace_limit(peps_ctx* c, size_t bytes) {
     if (!c) return PEPS_ERR_INVALID_ARG;
     c->ws_limit = bytes;
@@ -1208,11 +1215,13 @@ static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision 
 // ---------------------------------------------------------------------------
 // heterogeneous batches: several lattices in one graph launch
 // ---------------------------------------------------------------------------
-static std::string jobs_key(const peps_job* jobs, int njobs, peps_precision prec, const void* ws) {
+static std::string jobs_key(const peps_job* jobs, int njobs, peps_precision prec, const void* ws,
+                            bool fused) {
     std::string k;
     auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
     add(&prec, sizeof prec);
     add(&ws, sizeof ws);
+    add(&fused, sizeof fused);  // the captured kernels differ with the step form
     for (int i = 0; i < njobs; ++i) add(&jobs[i], sizeof(peps_job));
     return k;
 }
@@ -1250,7 +1259,7 @@ peps_status peps_eval_jobs(peps_ctx* c, const peps_job* jobs, int32_t njobs, pep
     peps_status st = ensure_ws(c, total);
     if (st != PEPS_OK) return st;
     const bool use_graph = (flags & PEPS_JOBS_GRAPH) != 0;
-    const std::string key = jobs_key(jobs, njobs, prec, c->ws);
+    const std::string key = jobs_key(jobs, njobs, prec, c->ws, c->fused_steps);
     if (use_graph) {
         for (auto& g : c->graphs)
             if (g.key == key) {

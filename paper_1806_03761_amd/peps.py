@@ -46,6 +46,7 @@ _SIGS = {
     "peps_destroy": [_P],
     "peps_set_stream": [_P, _P],
     "peps_set_workspace_limit": [_P, ctypes.c_size_t],
+    "peps_set_fused_steps": [_P, ctypes.c_int32],
     "peps_workspace_query": [_P, ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int,
                              ctypes.POINTER(ctypes.c_size_t)],
     "peps_log_amplitude": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
@@ -201,6 +202,12 @@ def tune_save(path: str, device: int = 0):
 def tune_load(path: str, device: int = 0):
     lib, ctx = _context(device)
     _check(lib, ctx, lib.peps_tune_load(ctx, path.encode()), "peps_tune_load")
+
+
+def set_fused_steps(enable: bool, device: int = 0):
+    """Fused float32 sandwich steps on (default) or the GEMM form (same results)."""
+    lib, ctx = _context(device)
+    _check(lib, ctx, lib.peps_set_fused_steps(ctx, 1 if enable else 0), "peps_set_fused_steps")
 
 
 def noalloc_scratch_bytes() -> int:

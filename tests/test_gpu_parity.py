@@ -443,18 +443,12 @@ def test_every_gemm_tile_gives_identical_results(case):
             p.tune_load(saved)
 
 
-def _eval_env(p, Ad, Sd, lat, env):
-    import os
-    saved = {k: os.environ.get(k) for k in env}
-    os.environ.update(env)
+def _eval_form(p, Ad, Sd, lat, fused):
+    p.set_fused_steps(fused)
     try:
         return _np(*p.evaluate(Ad, Sd, lat, "f32", grad_mode=1))
     finally:
-        for k, v in saved.items():
-            if v is None:
-                del os.environ[k]
-            else:
-                os.environ[k] = v
+        p.set_fused_steps(True)
 
 
 def test_fused_pair_step_matches_gemm_path():
@@ -483,10 +477,10 @@ def _fused_forms_equal_plain(p, lat, A, S):
     Ad, Sd = _dev(A, S)
     p.profile_enable(("fused",))   # counts fused-step launches, so a fallback cannot pass
     try:
-        plain = _eval_env(p, Ad, Sd, lat, {"PEPS_FUSE": "0"})
+        plain = _eval_form(p, Ad, Sd, lat, False)
         assert p.profile_read("fused")[1] == 0
         n0 = p.profile_read("fused")[1]
-        fused = _eval_env(p, Ad, Sd, lat, {})
+        fused = _eval_form(p, Ad, Sd, lat, True)
         assert p.profile_read("fused")[1] > n0, "fused steps did not run"
         for name, x, y in zip(("log-amp", "sign", "E_loc", "grad", "flags"), fused, plain):
             d = np.abs(np.asarray(x, np.float64) - np.asarray(y, np.float64))
