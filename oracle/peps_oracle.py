@@ -28,6 +28,9 @@ Readings of points the paper leaves open (each one is listed in the design notes
     left-canonical form, then a right-to-left SVD sweep keeping
     t = min(Dc, rows, cols) singular vectors (zero ones included), then the
     norm is pulled out of the first site and kept as a log;
+  * the variational alternative (sweeps >= 1; Sec. II-A's O(D^4 Dc^2) cost): one-site
+    alternating least squares started from the incoming boundary, used where that
+    boundary already has the dims of the result, the SVD truncation elsewhere;
   * the bottom-up sweep uses the same column orientation as the top-down one;
   * the reported amplitude is the top-down one (final overlap with the last row);
   * spin-flip ratios use the sandwich that holds both sites: the single-row
@@ -193,11 +196,122 @@ def truncate(mps, Dc):
     return mps, math.log(nu)
 
 
-def boundary_envs(A, lat, S):
+# --------------------------------------------------------------------------
+# variational boundary compression (the GEMM-dominated alternative to the SVD
+# truncation; cost O(D^4 Dc^2) per site and sweep, Sec. II-A)
+# --------------------------------------------------------------------------
+def truncated_bonds(mps, Dc):
+    """Bond dims [1, t_1, ..., t_{n-1}, 1] that truncate(mps, Dc) produces, from the
+    shapes alone: the QR sweep leaves r_{j+1} = min(r_j p_j, b_{j+1}), the SVD sweep
+    keeps t_j = min(Dc, r_j, p_j t_{j+1})."""
+    n = len(mps)
+    r = [1] * (n + 1)
+    for j in range(n - 1):
+        _, p, b = mps[j].shape
+        r[j + 1] = min(r[j] * p, b)
+    t = [1] * (n + 1)
+    for j in range(n - 1, 0, -1):
+        t[j] = min(Dc, r[j], mps[j].shape[1] * t[j + 1])
+    return t
+
+
+def _qr_pos(M):
+    """Thin QR of a tall matrix with the diagonal of R made non-negative, so that Q is
+    unique when M has full column rank (numpy's LAPACK QR as the library step)."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    s = np.where(np.diag(R) < 0.0, -1.0, 1.0)
+    return Q * s, R * s[:, None]
+
+
+def compress_variational(P, G, sweeps):
+    """Variational compression of the MPS P onto the bond dims of the guess G.
+
+    The approximation C minimises ||P - C|| one tensor at a time (one-site
+    alternating least squares).  With every other tensor of C an isometry towards
+    the site being updated, the optimal tensor is the contraction of P with the rest
+    of C: M_j[c,d,c'] = sum L_j[c,k] P_j[k,d,k'] R_{j+1}[c',k'], where L_j (R_{j+1})
+    is the overlap of C's and P's sites left of j (right of j).  Steps:
+      1. bring G to right-canonical form: from the last site down to site 1, an LQ
+         factorisation of each tensor (as a matrix bond x (phys bond)) keeps the
+         orthonormal rows and pushes the triangular factor into the left neighbour;
+      2. a sweep: sites 0..n-2 left to right (update, thin QR, keep Q, extend L),
+         then sites n-1..1 right to left (update, LQ, keep the rows, extend R),
+         then the update of site 0, which carries the norm;
+      3. after the last sweep the norm nu of site 0 is pulled out.
+    Every QR/LQ factor is sign-fixed (non-negative diagonal).  Returns (C, ln nu);
+    ln nu = -inf for the zero state.
+    """
+    if sweeps < 1:
+        raise ValueError("at least one sweep")
+    n = len(P)
+    C = [g.copy() for g in G]
+    for j in range(n - 1, 0, -1):
+        a, p, b = C[j].shape
+        Q, R = _qr_pos(C[j].reshape(a, p * b).T)          # C_j = R^T Q^T
+        C[j] = Q.T.reshape(a, p, b)
+        C[j - 1] = _c("xpa,ka->xpk", C[j - 1], R)
+
+    def update(j):
+        X = _c("kdf,ef->kde", P[j], Renv[j + 1])            # contract P's right bond
+        return _c("ck,kde->cde", Lenv[j], X)
+
+    def left_step(j):
+        X = _c("ck,cde->kde", Lenv[j], C[j])
+        return _c("kde,kdf->ef", X, P[j])
+
+    def right_step(j):
+        X = _c("cde,ef->cdf", C[j], Renv[j + 1])
+        return _c("cdf,kdf->ck", X, P[j])
+
+    Lenv = [None] * (n + 1)
+    Renv = [None] * (n + 1)
+    Lenv[0] = np.ones((1, 1))
+    Renv[n] = np.ones((1, 1))
+    for j in range(n - 1, 0, -1):
+        Renv[j] = right_step(j)
+    for _ in range(sweeps):
+        for j in range(n - 1):
+            M = update(j)
+            a, p, b = M.shape
+            Q, _ = _qr_pos(M.reshape(a * p, b))
+            C[j] = Q.reshape(a, p, b)
+            Lenv[j + 1] = left_step(j)
+        for j in range(n - 1, 0, -1):
+            M = update(j)
+            a, p, b = M.shape
+            Q, _ = _qr_pos(M.reshape(a, p * b).T)
+            C[j] = Q.T.reshape(a, p, b)
+            Renv[j] = right_step(j)
+        C[0] = update(0)
+    nu = float(np.linalg.norm(C[0]))
+    if nu == 0.0:
+        return C, -math.inf
+    C[0] = C[0] / nu
+    return C, math.log(nu)
+
+
+def next_boundary(E, P, Dc, sweeps=0):
+    """The truncated boundary Trunc(P) of the applied MPS P = Apply(E, row).
+
+    sweeps = 0: canonical SVD truncation.  sweeps >= 1: variational compression with
+    the incoming boundary E as the guess, wherever E already has the bond and
+    physical dims of the result (the bond has stopped growing); elsewhere the SVD
+    truncation, which then also fixes those dims.
+    """
+    if sweeps > 0:
+        t = truncated_bonds(P, Dc)
+        if ([e.shape[0] for e in E] + [1] == t
+                and all(e.shape[1] == q.shape[1] for e, q in zip(E, P))):
+            return compress_variational(P, E, sweeps)
+    return truncate(P, Dc)
+
+
+def boundary_envs(A, lat, S, sweeps=0):
     """Upper envs U_0..U_{Ly-1} and lower envs L_0..L_{Ly-1} with their log scales.
 
     U_0 and L_{Ly-1} are trivial; U_{i+1} = Trunc(Apply(U_i, row i)) and
-    L_{i-1} = Trunc(Apply_up(L_i, row i)).  True env = exp(log) * stored MPS.
+    L_{i-1} = Trunc(Apply_up(L_i, row i)), Trunc as in next_boundary.  True env =
+    exp(log) * stored MPS.
     """
     Ly = lat.Ly
     U = [None] * Ly
@@ -206,11 +320,11 @@ def boundary_envs(A, lat, S):
     logL = [0.0] * Ly
     U[0] = trivial_mps(lat.Lx)
     for i in range(Ly - 1):
-        U[i + 1], ln = truncate(apply_row_down(U[i], row_tensors(A, lat, S, i)), lat.Dc)
+        U[i + 1], ln = next_boundary(U[i], apply_row_down(U[i], row_tensors(A, lat, S, i)), lat.Dc, sweeps)
         logU[i + 1] = logU[i] + ln
     L[Ly - 1] = trivial_mps(lat.Lx)
     for i in range(Ly - 1, 0, -1):
-        L[i - 1], ln = truncate(apply_row_up(L[i], row_tensors(A, lat, S, i)), lat.Dc)
+        L[i - 1], ln = next_boundary(L[i], apply_row_up(L[i], row_tensors(A, lat, S, i)), lat.Dc, sweeps)
         logL[i - 1] = logL[i] + ln
     return U, L, logU, logL
 
@@ -263,14 +377,15 @@ def _check_config(lat, S):
     return S.shape == (lat.N,) and bool(np.all((S == 0) | (S == 1)))
 
 
-def log_amplitude_one(A, lat, S):
-    """(ln|W(S)|, sign W(S), flag) from the top-down boundary-MPS contraction."""
+def log_amplitude_one(A, lat, S, sweeps=0):
+    """(ln|W(S)|, sign W(S), flag) from the top-down boundary-MPS contraction
+    (sweeps: the truncation of next_boundary)."""
     if not _check_config(lat, S):
         return math.nan, 0, FLAG_BAD_CONFIG
     U = trivial_mps(lat.Lx)
     logscale = 0.0
     for i in range(lat.Ly - 1):
-        U, ln = truncate(apply_row_down(U, row_tensors(A, lat, S, i)), lat.Dc)
+        U, ln = next_boundary(U, apply_row_down(U, row_tensors(A, lat, S, i)), lat.Dc, sweeps)
         logscale += ln
     w = final_overlap(U, row_tensors(A, lat, S, lat.Ly - 1))
     if w == 0.0 or not math.isfinite(logscale):
@@ -281,7 +396,7 @@ def log_amplitude_one(A, lat, S):
     return out, int(np.sign(w)), FLAG_OK
 
 
-def local_energy_one(A, lat, S, envs=None):
+def local_energy_one(A, lat, S, envs=None, sweeps=0):
     """E(S) of Eq. (4) for H = J1 sum_<ij> S_i.S_j + J2 sum_<<ij>> S_i.S_j.
 
     Off-diagonal terms: 1/2 * W(S')/W(S) for every anti-parallel bond, where S'
@@ -291,7 +406,7 @@ def local_energy_one(A, lat, S, envs=None):
     S = np.asarray(S)
     if not _check_config(lat, S):
         return math.nan
-    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S)
+    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S, sweeps)
     sig = 1 - 2 * S.astype(np.int64)
     Lx = lat.Lx
 
@@ -326,7 +441,7 @@ def local_energy_one(A, lat, S, envs=None):
     return E
 
 
-def log_derivative_one(A, lat, S, envs=None):
+def log_derivative_one(A, lat, S, envs=None, sweeps=0):
     """Delta[m][s][l][u][r][d] = (1/W_i) dW_i/dA_m^{s}, Eqs. (6)-(7), frozen environments.
 
     B_m is the row-i sandwich with site m removed: left partial P_j (columns < j),
@@ -339,7 +454,7 @@ def log_derivative_one(A, lat, S, envs=None):
     if not _check_config(lat, S):
         out[:] = np.nan
         return out
-    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S)
+    U, L, _, _ = envs if envs is not None else boundary_envs(A, lat, S, sweeps)
     for i in range(Ly):
         row = row_tensors(A, lat, S, i)
         left = [(np.ones((1, 1, 1)), 0.0)]
@@ -371,30 +486,30 @@ def log_derivative_one(A, lat, S, envs=None):
 # --------------------------------------------------------------------------
 # batched front ends (plain loops over samples)
 # --------------------------------------------------------------------------
-def log_amplitude(A, lat, S):
+def log_amplitude(A, lat, S, sweeps=0):
     B = S.shape[0]
     la = np.empty(B)
     sg = np.empty(B, dtype=np.int8)
     fl = np.empty(B, dtype=np.int8)
     for b in range(B):
-        la[b], sg[b], fl[b] = log_amplitude_one(A, lat, S[b])
+        la[b], sg[b], fl[b] = log_amplitude_one(A, lat, S[b], sweeps)
     return la, sg, fl
 
 
-def local_energy(A, lat, S):
+def local_energy(A, lat, S, sweeps=0):
     """(log_abs, sign, e_loc, flags) per sample."""
     B = S.shape[0]
-    la, sg, fl = log_amplitude(A, lat, S)
+    la, sg, fl = log_amplitude(A, lat, S, sweeps)
     e = np.full(B, np.nan)
     for b in range(B):
         if fl[b] == FLAG_OK:
-            e[b] = local_energy_one(A, lat, S[b])
+            e[b] = local_energy_one(A, lat, S[b], sweeps=sweeps)
             if not math.isfinite(e[b]):
                 fl[b] = FLAG_NONFINITE
     return la, sg, e, fl
 
 
-def log_derivative(A, lat, S, weights=None):
+def log_derivative(A, lat, S, weights=None, sweeps=0):
     """Per-sample Delta [B][N][2][D^4] or, with weights, sum_b weights[b] * Delta_b
     accumulated in sample order (the per-sample term of Eq. (5))."""
     B = S.shape[0]
@@ -402,20 +517,20 @@ def log_derivative(A, lat, S, weights=None):
     if weights is None:
         out = np.zeros((B, lat.N, 2, D4))
         for b in range(B):
-            out[b] = log_derivative_one(A, lat, S[b]).reshape(lat.N, 2, D4)
+            out[b] = log_derivative_one(A, lat, S[b], sweeps=sweeps).reshape(lat.N, 2, D4)
         return out
     g = np.zeros((lat.N, 2, D4))
     for b in range(B):
-        g += weights[b] * log_derivative_one(A, lat, S[b]).reshape(lat.N, 2, D4)
+        g += weights[b] * log_derivative_one(A, lat, S[b], sweeps=sweeps).reshape(lat.N, 2, D4)
     return g
 
 
-def full_path_one(A, lat, S):
+def full_path_one(A, lat, S, sweeps=0):
     """Amplitude, local energy and log-derivative of one sample from one set of envs."""
-    la, sg, fl = log_amplitude_one(A, lat, S)
+    la, sg, fl = log_amplitude_one(A, lat, S, sweeps)
     if fl != FLAG_OK:
         return la, sg, math.nan, np.zeros((lat.N, 2, lat.D ** 4)), fl
-    envs = boundary_envs(A, lat, S)
+    envs = boundary_envs(A, lat, S, sweeps)
     e = local_energy_one(A, lat, S, envs)
     d = log_derivative_one(A, lat, S, envs).reshape(lat.N, 2, -1)
     return la, sg, e, d, fl
