@@ -82,6 +82,21 @@ peps_status peps_destroy(peps_ctx* ctx);
 /* Stream on which all later work is enqueued (a hipStream_t; NULL = default stream). */
 peps_status peps_set_stream(peps_ctx* ctx, void* hip_stream);
 
+/* Boundary truncation of every contraction on this context (Sec. II-A: the bond of a
+ * boundary MPS is cut to Dc after each row is applied).  sweeps = 0 (default): the
+ * canonical SVD truncation.  sweeps = 1..16: variational compression wherever the
+ * incoming boundary already has the bond and physical dims of the outgoing one (the
+ * bond has stopped growing; the SVD truncation still fixes the dims before that):
+ * the outgoing boundary is fitted to the applied row by one-site alternating least
+ * squares started from the incoming boundary, `sweeps` left-to-right plus
+ * right-to-left passes, every factor sign-fixed (non-negative diagonal of R), the norm
+ * kept as a log.  Its contractions are float64 batched GEMMs of O(D^4 Dc^2) per site
+ * and pass, whatever the precision argument of a call; the result is a different
+ * approximation of W than the SVD truncation's.  Evaluations fail with
+ * PEPS_ERR_UNSUPPORTED when a site factorisation (Dc D x Dc) does not fit in one
+ * workgroup's LDS.  PEPS_ERR_INVALID_ARG for sweeps outside [0, 16]. */
+peps_status peps_set_truncation(peps_ctx* ctx, int32_t sweeps);
+
 /* Fused float32 sandwich steps (enable != 0, the default): the single- and two-row steps
  * of the float32 and bfloat16 modes with legs <= 4 and boundary bonds <= 16 run as one
  * kernel each, summing every product in the order of the GEMM form, so their results
@@ -294,9 +309,11 @@ enum { PEPS_KC_GEMM = 0, PEPS_KC_QR = 1, PEPS_KC_SVD = 2, PEPS_KC_FUSED = 3 };
 /* Start timing the launches of the kernel classes in `class_mask` (bit 1 << PEPS_KC_*):
  * each such launch is bracketed by two HIP events on the context's stream, together
  * with its algorithmic flop count (GEMM 2MNK; fused single-/two-row sandwich step: the
- * 2MNK of the three / four GEMMs it replaces; QR 2 r^2 (max(m,n) - r/3); truncation
- * step: implicit-Q apply 4 t (mz r - r^2/2) plus a thin SVD 4 a b^2 + 8 b^3 plus
- * U_t Sigma_t 2 m n t).  Clears earlier records; 0 turns timing off. */
+ * 2MNK of the three / four GEMMs it replaces; QR 2 r^2 (max(m,n) - r/3), and for the
+ * thin QR of the variational compression 4 m n^2 - 4 n^3 / 3 (factor and explicit Q);
+ * truncation step: implicit-Q apply 4 t (mz r - r^2/2) plus a thin SVD
+ * min(14 a b^2 + 8 b^3, 6 a b^2 + 20 b^3) plus U_t Sigma_t 2 m n t).  Clears earlier
+ * records; 0 turns timing off. */
 peps_status peps_profile_enable(peps_ctx* ctx, uint32_t class_mask);
 
 /* Synchronise the context's stream and report, for one kernel class, the summed
@@ -307,11 +324,12 @@ peps_status peps_profile_read(peps_ctx* ctx, int32_t kernel_class, double* total
 
 /* Diagnostic, no device work: lay out the workspace of one chunk of `batch` samples
  * and walk the whole launch sequence of an evaluation (want_eloc, grad_mode as in
- * peps_evaluate) without launching anything, checking on the host that every
- * operand offset stays inside its buffer.  Returns PEPS_OK and the chunk's
- * workspace bytes, or PEPS_ERR_INVALID_ARG if a check fails.  Needs no GPU. */
+ * peps_evaluate; sweeps as in peps_set_truncation) without launching anything,
+ * checking on the host that every operand offset stays inside its buffer.  Returns
+ * PEPS_OK and the chunk's workspace bytes, PEPS_ERR_INVALID_ARG if a check fails, or
+ * PEPS_ERR_UNSUPPORTED as peps_set_truncation's evaluations would.  Needs no GPU. */
 peps_status peps_plan_check(const peps_lattice* lat, int64_t batch, int32_t grad_mode,
-                            int32_t want_eloc, size_t* bytes);
+                            int32_t want_eloc, int32_t sweeps, size_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpeps_hip.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k_gemm.hip", "k_mgemm.hip", "k_qrb.hip", "k_qr_svd.hip", "k_eig.hip", "k_misc.hip", "k_pair.hip", "k_corr.hip", "peps_host.cpp"]
+SOURCES = ["k_gemm.hip", "k_mgemm.hip", "k_qrb.hip", "k_qr_svd.hip", "k_eig.hip", "k_misc.hip", "k_pair.hip", "k_corr.hip", "k_vc.hip", "peps_host.cpp"]
 ARCH = os.environ.get("PEPS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -35,6 +35,8 @@ struct CachedGraph {
     hipGraphExec_t exec;
 };
 
+static constexpr int kMaxSweeps = 16;
+
 struct peps_ctx {
     int device = 0;
     std::vector<CachedGraph> graphs;          // captured job lists (peps_eval_jobs)
@@ -53,6 +55,7 @@ struct peps_ctx {
     double* ones = nullptr;   // 4096 ones
     char* scratch = nullptr;  // device address of this device's fixed scratch array
     bool fused_steps = true;  // fused float32 sandwich steps where they fit (else the GEMM form)
+    int vc_sweeps = 0;        // 0: SVD truncation; n > 0: variational compression, n sweeps
     char* mc = nullptr;       // sampling buffers (peps_metropolis_step, peps_vmc_step)
     size_t mc_bytes = 0;
     char* corr = nullptr;     // exchanged configurations and their amplitudes (peps_pair_correlations)
@@ -156,6 +159,41 @@ public:
             tL[i] = make_trunc(chiL[i], Dv[i + 1], Dv[i]);
             chiL[i - 1] = tL[i].tau;
         }
+        sweeps = c->vc_sweeps;
+        vcU.assign(Ly, 0);
+        vcL.assign(Ly, 0);
+        for (int i = 0; i + 1 < Ly; ++i) vcU[i] = use_vc(tU[i]);
+        for (int i = Ly - 1; i >= 1; --i) vcL[i] = use_vc(tL[i]);
+    }
+
+    // Variational compression replaces the SVD truncation of a boundary wherever the
+    // incoming boundary (its guess) already has the bond and physical dims of the result.
+    bool use_vc(const Trunc& t) const { return sweeps > 0 && t.pin == t.p && t.chi == t.tau; }
+    // the reason a planned variational step cannot run ("" when every one can)
+    std::string vc_unsupported() const {
+        auto check = [&](const Trunc& t) -> std::string {
+            for (int j = 0; j < Lx; ++j) {
+                const int a = t.chi[j], b = t.chi[j + 1];
+                if (!thinq_fits(a * t.p, b) || !thinq_fits(t.p * b, a)) {
+                    char m[160];
+                    snprintf(m, sizeof m, "variational compression: the %d x %d site factorisation does not "
+                             "fit in LDS", std::max(a * t.p, t.p * b), std::max(a, b));
+                    return m;
+                }
+            }
+            return "";
+        };
+        for (int i = 0; i + 1 < Ly; ++i)
+            if (vcU[i]) {
+                std::string m = check(tU[i]);
+                if (!m.empty()) return m;
+            }
+        for (int i = Ly - 1; i >= 1; --i)
+            if (vcL[i]) {
+                std::string m = check(tL[i]);
+                if (!m.empty()) return m;
+            }
+        return "";
     }
 
     Trunc make_trunc(const std::vector<int>& chi, int pin, int p) const {
@@ -225,9 +263,43 @@ public:
                 if (j == 0 && sc * sizeof(double) > lds_cap_bytes()) s_svd = std::max<long long>(s_svd, sc);
             }
         };
-        for (int i = 0; i + 1 < Ly; ++i) visit(tU[i]);
+        for (int i = 0; i + 1 < Ly; ++i)
+            if (!vcU[i]) visit(tU[i]);
         if (need_L)
-            for (int i = Ly - 1; i >= 1; --i) visit(tL[i]);
+            for (int i = Ly - 1; i >= 1; --i)
+                if (!vcL[i]) visit(tL[i]);
+        // variational compression: overlap environments L_c and R_c per cut c ([c][a][l],
+        // bond x bond x horizontal leg), two contraction temporaries, the updated site
+        // tensor and the triangular factor of the guess's canonicalisation
+        vc_eoff.assign(Lx + 2, 0);
+        {
+            std::vector<long long> e(Lx + 1, 0);
+            s_vZ1 = s_vZ2 = s_vM = s_vRf = 0;
+            auto visit_vc = [&](const Trunc& t) {
+                for (int c = 0; c <= Lx; ++c) e[c] = std::max<long long>(e[c], (long long)t.chi[c] * t.chi[c] * Dh[c]);
+                for (int j = 0; j < Lx; ++j) {
+                    const long long a = t.chi[j], b = t.chi[j + 1], hl = Dh[j], hr = Dh[j + 1], p = t.p;
+                    s_vZ1 = std::max({s_vZ1, a * hl * p * b, b * hr * a * p});
+                    s_vZ2 = std::max({s_vZ2, a * b * hr * p, b * a * hl * p});
+                    s_vM = std::max(s_vM, a * p * b);
+                    s_vRf = std::max({s_vRf, a * a, b * b});
+                }
+            };
+            bool any = false;
+            for (int i = 0; i + 1 < Ly; ++i)
+                if (vcU[i]) { visit_vc(tU[i]); any = true; }
+            if (need_L)
+                for (int i = Ly - 1; i >= 1; --i)
+                    if (vcL[i]) { visit_vc(tL[i]); any = true; }
+            for (int c = 0; c <= Lx; ++c) vc_eoff[c + 1] = vc_eoff[c] + e[c];
+            s_vE = vc_eoff[Lx + 1];
+            o_vL = any ? L.alloc(s_vE) : 0;
+            o_vR = any ? L.alloc(s_vE) : 0;
+            o_vZ1 = any ? L.alloc(s_vZ1) : 0;
+            o_vZ2 = any ? L.alloc(s_vZ2) : 0;
+            o_vM = any ? L.alloc(s_vM) : 0;
+            o_vRf = any ? L.alloc(s_vRf) : 0;
+        }
         o_X.resize(Lx); o_tau.resize(Lx); o_wy.assign(Lx, 0);
         for (int j = 0; j < Lx; ++j) {
             o_X[j] = L.alloc(s_X[j]);
@@ -247,9 +319,11 @@ public:
                 s_eig = std::max<long long>(s_eig, (long long)eig_scratch_doubles(mz, tin, t.p, Dc));
             }
         };
-        for (int i = 0; i + 1 < Ly; ++i) visit_eig(tU[i]);
+        for (int i = 0; i + 1 < Ly; ++i)
+            if (!vcU[i]) visit_eig(tU[i]);
         if (need_L)
-            for (int i = Ly - 1; i >= 1; --i) visit_eig(tL[i]);
+            for (int i = Ly - 1; i >= 1; --i)
+                if (!vcL[i]) visit_eig(tL[i]);
         o_eig = L.alloc(s_eig);
         // single-row partials
         s_P.assign(Lx + 1, 1);
@@ -534,6 +608,118 @@ public:
         return hipSuccess;
     }
 
+    // One variational compression: new env = the one-site least-squares fit of
+    // Apply(env, row) started from env itself (same bond and physical dims), in `sweeps`
+    // sweeps, never forming the applied MPS.  Indices of site j: a = bond at cut j,
+    // b = bond at cut j+1 (incoming and outgoing boundaries alike), l / r = the row's
+    // horizontal legs (Dh), u / d = its incoming / outgoing physical leg (p each).
+    // Overlap environments: L_j[c][a][l] = <C| rows |E> left of cut j, R_j the same right
+    // of it.  Every contraction is a float64 GEMM; every QR is k_thinq.
+    hipError_t vc_step(bool down, int row) {
+        const Trunc& t = down ? tU[row] : tL[row];
+        const long long s_in = down ? D2 : 1, s_out = down ? 1 : D2;
+        const int p = t.p;
+        const Arith F = Arith::F64;
+        auto Ein = [&](int j) { return down ? envU(row, j) : envL(row, j); };
+        auto Cout = [&](int j) { return down ? envU(row + 1, j) : envL(row - 1, j); };
+        auto Lenv = [&](int c) { return c == 0 ? ones() : op(o_vL, s_vE).at(vc_eoff[c]); };
+        auto Renv = [&](int c) { return c == Lx ? ones() : op(o_vR, s_vE).at(vc_eoff[c]); };
+        const Op Z1 = op(o_vZ1, s_vZ1), Z2 = op(o_vZ2, s_vZ2), Mb = op(o_vM, s_vM), Rf = op(o_vRf, s_vRf);
+        const Op lin = down ? logU(row) : logL(row), lout = down ? logU(row + 1) : logL(row - 1);
+        // thin QR of an m x n column-major matrix at X into Q (rows q_row, columns q_col apart)
+        auto thinq = [&](const Op& X, int m, int n, const Op& Q, long long q_row, long long q_col,
+                         bool with_r) -> hipError_t {
+            if (!bounds_ok("vc qr in", X, (long long)m * n - 1, 0) ||
+                !bounds_ok("vc qr out", Q, (long long)(m - 1) * q_row + (long long)(n - 1) * q_col, 0) ||
+                (with_r && !bounds_ok("vc qr R", Rf, (long long)n * n - 1, 0)))
+                return hipErrorInvalidValue;
+            const double fl = (4.0 * m * n * n - 4.0 / 3.0 * n * n * n) * Bcur;
+            KL(timed(PEPS_KC_QR, fl, [&] {
+                return launch_thinq(X.p, X.bs, m, n, Q.p, Q.bs, q_row, q_col, with_r ? Rf.p : nullptr, Rf.bs,
+                                    Bcur, st_);
+            }));
+            return hipSuccess;
+        };
+        // W2[c'][a][l][d] = sum_{a',r,u} R_{j+1}[c',a',r] E_j[a,u,a'] T_j[l,u,r,d] (in Z2)
+        auto right_part = [&](int j) -> hipError_t {
+            const int a = t.chi[j], b = t.chi[j + 1], hl = Dh[j], hr = Dh[j + 1];
+            CK(gemm_a(F, b * hr, a * p, b, Renv(j + 1), I2(hr, (long long)b * hr, 1), I1(hr), Gather{},
+                      Ein(j), I1(1), I1(b), Gather{}, Z1, I1((long long)a * p), I1(1)));
+            CK(gemm_a(F, b * a, hl * p, hr * p, Z1, I2(a, (long long)hr * a * p, p), I2(p, (long long)a * p, 1),
+                      Gather{}, site_op(row, j), I2(p, D, s_in), I2(p, D3, s_out), site_gather(row, j, 0),
+                      Z2, I1((long long)hl * p), I1(1)));
+            return hipSuccess;
+        };
+        // R_j[c][a][l] = sum_{d,c'} C_j[c,d,c'] W2[c',a,l,d]
+        auto right_env = [&](int j) -> hipError_t {
+            const int a = t.chi[j], b = t.chi[j + 1], hl = Dh[j];
+            CK(gemm_a(F, a, a * hl, p * b, Cout(j), I1((long long)p * b), I1(1), Gather{}, Z2,
+                      I2(b, 1, (long long)a * hl * p), I1(p), Gather{}, Renv(j), I1((long long)a * hl), I1(1)));
+            return hipSuccess;
+        };
+        // C_j (row layout [c][d][c']) = sum_{a,l} L_j[c,a,l] W2[c',a,l,d]: the update seen from the right
+        auto update_right = [&](int j) -> hipError_t {
+            const int a = t.chi[j], b = t.chi[j + 1], hl = Dh[j];
+            CK(gemm_a(F, a, p * b, a * hl, Lenv(j), I1((long long)a * hl), I1(1), Gather{}, Z2, I1(p),
+                      I2(b, 1, (long long)a * hl * p), Gather{}, Cout(j), I1((long long)p * b), I1(1)));
+            return hipSuccess;
+        };
+
+        // 1. the guess in right-canonical form: LQ of every site from the right (a QR of its
+        //    transpose, which is the row layout read column-major), the factor pushed left
+        for (int j = Lx - 1; j >= 1; --j) {
+            const int a = t.chi[j], b = t.chi[j + 1];
+            Op src = Ein(j);
+            if (j < Lx - 1) {
+                // C_j[(a,u)][k] = sum_a' E_j[(a,u), a'] R[k][a']
+                CK(gemm_a(F, a * p, b, b, Ein(j), I1(b), I1(1), Gather{}, Rf, I1(1), I1(b), Gather{}, Cout(j),
+                          I1(b), I1(1)));
+                src = Cout(j);
+            }
+            CK(thinq(src, p * b, a, Cout(j), 1, (long long)p * b, true));
+        }
+        for (int j = Lx - 1; j >= 1; --j) {
+            CK(right_part(j));
+            CK(right_env(j));
+        }
+        // 2. the sweeps
+        for (int s = 0; s < sweeps; ++s) {
+            for (int j = 0; j + 1 < Lx; ++j) {
+                const int a = t.chi[j], b = t.chi[j + 1], hl = Dh[j], hr = Dh[j + 1];
+                // Z1[c][l][u][a'] = sum_a L_j[c,a,l] E_j[a,u,a']
+                CK(gemm_a(F, a * hl, p * b, a, Lenv(j), I2(hl, (long long)a * hl, 1), I1(hl), Gather{}, Ein(j),
+                          I1((long long)p * b), I1(1), Gather{}, Z1, I1((long long)p * b), I1(1)));
+                // Z2[c][a'][r][d] = sum_{l,u} Z1[c,l,u,a'] T_j[l,u,r,d]
+                CK(gemm_a(F, a * b, hr * p, hl * p, Z1, I2(b, (long long)hl * p * b, 1), I1(b), Gather{},
+                          site_op(row, j), I2(p, D3, s_in), I2(p, D, s_out), site_gather(row, j, 0), Z2,
+                          I1((long long)hr * p), I1(1)));
+                // M[(c,d)][c'] (column-major) = sum_{a',r} Z2[c,a',r,d] R_{j+1}[c',a',r]
+                CK(gemm_a(F, a * p, b, b * hr, Z2, I2(p, (long long)b * hr * p, 1), I1(p), Gather{}, Renv(j + 1),
+                          I1(1), I1((long long)b * hr), Gather{}, Mb, I1(1), I1((long long)a * p)));
+                CK(thinq(Mb, a * p, b, Cout(j), b, 1, false));
+                // L_{j+1}[c'][a'][r] = sum_{c,d} C_j[c,d,c'] Z2[c,a',r,d]
+                CK(gemm_a(F, b, b * hr, a * p, Cout(j), I1(1), I1(b), Gather{}, Z2,
+                          I2(p, (long long)b * hr * p, 1), I1(p), Gather{}, Lenv(j + 1), I1((long long)b * hr),
+                          I1(1)));
+            }
+            for (int j = Lx - 1; j >= 1; --j) {
+                const int a = t.chi[j], b = t.chi[j + 1];
+                CK(right_part(j));
+                CK(update_right(j));
+                CK(thinq(Cout(j), p * b, a, Cout(j), 1, (long long)p * b, false));
+                CK(right_env(j));
+            }
+        }
+        // 3. the last update of site 0 carries the norm
+        CK(right_part(0));
+        CK(update_right(0));
+        const Op C0 = Cout(0);
+        const int n0 = p * t.chi[1];
+        if (!bounds_ok("vc norm", C0, n0 - 1, 0)) return hipErrorInvalidValue;
+        KL(launch_vc_norm(C0.p, C0.bs, n0, lin.p, lout.p, Bcur, st_));
+        return hipSuccess;
+    }
+
     // the single-row step as one fused kernel when it fits (done = false: use the GEMMs)
     hipError_t row_fused(int i, int j, Op X, int flip, Op Y, bool fwd, bool& done, const double* lin,
                          double* lout) {
@@ -788,11 +974,11 @@ public:
         KL(launch_fill(buf(o_zero), Bn, 0.0, st));
         if (fuse_pairs) KL(launch_site_tables(Ad, reinterpret_cast<float*>(buf(o_site32)), Lx, Ly, D, st));
         KL(launch_fill(buf(o_logU[0]), Bn, 0.0, st));
-        for (int i = 0; i + 1 < Ly; ++i) CK(trunc_step(true, i));
+        for (int i = 0; i + 1 < Ly; ++i) CK(vcU[i] ? vc_step(true, i) : trunc_step(true, i));
         const bool need_L = want_eloc || want_grad;
         if (need_L) {
             KL(launch_fill(buf(o_logL[Ly - 1]), Bn, 0.0, st));
-            for (int i = Ly - 1; i >= 1; --i) CK(trunc_step(false, i));
+            for (int i = Ly - 1; i >= 1; --i) CK(vcL[i] ? vc_step(false, i) : trunc_step(false, i));
         }
         if (want_grad) KL(launch_fill(buf(o_delta), (long long)Bn * N * D4, 0.0, st));
         const int nH = Ly * (Lx - 1), nV = (Ly - 1) * Lx, nD = (Ly - 1) * (Lx - 1);
@@ -962,6 +1148,11 @@ public:
     long long s_R, s_Y, s_G, s_svd, s_T, s_F, s_eig = 1;
     size_t o_eig = 0;
     bool fuse_pairs = false;
+    int sweeps = 0;                         // variational compression sweeps (0: SVD truncation)
+    std::vector<char> vcU, vcL;             // which truncations are variational
+    std::vector<long long> vc_eoff;         // offset of cut c's overlap environment
+    size_t o_vL = 0, o_vR = 0, o_vZ1 = 0, o_vZ2 = 0, o_vM = 0, o_vRf = 0;
+    long long s_vE = 0, s_vZ1 = 0, s_vZ2 = 0, s_vM = 0, s_vRf = 0;
     bool step_rescaled = false;   // the last sandwich step also applied the max-abs rescale
 };
 
@@ -1055,6 +1246,13 @@ peps_status peps_set_stream(peps_ctx* c, void* s) {
     return PEPS_OK;
 }
 
+peps_status peps_set_truncation(peps_ctx* c, int32_t sweeps) {
+    if (!c) return PEPS_ERR_INVALID_ARG;
+    if (sweeps < 0 || sweeps > kMaxSweeps) return fail(c, PEPS_ERR_INVALID_ARG, "sweeps must be in [0, %d]", kMaxSweeps);
+    c->vc_sweeps = sweeps;
+    return PEPS_OK;
+}
+
 peps_status peps_set_fused_steps(peps_ctx* c, int32_t enable) {
     if (!c) return PEPS_ERR_INVALID_ARG;
     c->fused_steps = enable != 0;
@@ -1082,6 +1280,8 @@ peps_status peps_workspace_query(peps_ctx* c, const peps_lattice* lat, int64_t b
     peps_status s = check_lat(c, lat);
     if (s != PEPS_OK) return s;
     Runner r(c, *lat, prec);
+    const std::string vm = r.vc_unsupported();
+    if (!vm.empty()) return fail(c, PEPS_ERR_UNSUPPORTED, "%s", vm.c_str());
     r.layout((int)std::max<int64_t>(batch, 1), true, true);
     *bytes = r.L.bytes;
     return PEPS_OK;
@@ -1178,6 +1378,8 @@ static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision 
     if (st != PEPS_OK || batch == 0) return st;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, PEPS_ERR_HIP, "hipSetDevice failed");
     Runner r(c, *lat, prec);
+    const std::string vm = r.vc_unsupported();
+    if (!vm.empty()) return fail(c, PEPS_ERR_UNSUPPORTED, "%s", vm.c_str());
     size_t per, fixed;
     job_sizes(r, j, &per, &fixed);
     const size_t limit = noalloc ? kScratchBytes : default_limit(c);
@@ -1216,12 +1418,13 @@ static peps_status run_all(peps_ctx* c, const peps_lattice* lat, peps_precision 
 // heterogeneous batches: several lattices in one graph launch
 // ---------------------------------------------------------------------------
 static std::string jobs_key(const peps_job* jobs, int njobs, peps_precision prec, const void* ws,
-                            bool fused) {
+                            bool fused, int sweeps) {
     std::string k;
     auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
     add(&prec, sizeof prec);
     add(&ws, sizeof ws);
-    add(&fused, sizeof fused);  // the captured kernels differ with the step form
+    add(&fused, sizeof fused);    // the captured kernels differ with the step form
+    add(&sweeps, sizeof sweeps);  // and with the truncation
     for (int i = 0; i < njobs; ++i) add(&jobs[i], sizeof(peps_job));
     return k;
 }
@@ -1250,6 +1453,8 @@ peps_status peps_eval_jobs(peps_ctx* c, const peps_job* jobs, int32_t njobs, pep
     size_t total = 0;
     for (auto& j : js) {
         rs.emplace_back(c, j.lat, prec);
+        const std::string vm = rs.back().vc_unsupported();
+        if (!vm.empty()) return fail(c, PEPS_ERR_UNSUPPORTED, "%s", vm.c_str());
         rs.back().layout((int)std::min<int64_t>(j.batch, 1 << 20), j.want_e, j.grad_mode != 0);
         offs.push_back(total);
         total += (rs.back().L.bytes + 255) / 256 * 256;
@@ -1259,7 +1464,7 @@ peps_status peps_eval_jobs(peps_ctx* c, const peps_job* jobs, int32_t njobs, pep
     peps_status st = ensure_ws(c, total);
     if (st != PEPS_OK) return st;
     const bool use_graph = (flags & PEPS_JOBS_GRAPH) != 0;
-    const std::string key = jobs_key(jobs, njobs, prec, c->ws, c->fused_steps);
+    const std::string key = jobs_key(jobs, njobs, prec, c->ws, c->fused_steps, c->vc_sweeps);
     if (use_graph) {
         for (auto& g : c->graphs)
             if (g.key == key) {
@@ -1412,12 +1617,15 @@ peps_status peps_profile_read(peps_ctx* c, int32_t kernel_class, double* total_m
 }
 
 peps_status peps_plan_check(const peps_lattice* lat, int64_t batch, int32_t grad_mode,
-                            int32_t want_eloc, size_t* bytes) {
+                            int32_t want_eloc, int32_t sweeps, size_t* bytes) {
     peps_status st = check_lat(nullptr, lat);
     if (st != PEPS_OK) return st;
-    if (batch < 1 || grad_mode < 0 || grad_mode > 3) return PEPS_ERR_INVALID_ARG;
+    if (batch < 1 || grad_mode < 0 || grad_mode > 3 || sweeps < 0 || sweeps > kMaxSweeps)
+        return PEPS_ERR_INVALID_ARG;
     peps_ctx dummy;
+    dummy.vc_sweeps = sweeps;
     Runner r(&dummy, *lat, PEPS_PREC_F64);
+    if (!r.vc_unsupported().empty()) return PEPS_ERR_UNSUPPORTED;
     r.dry = true;
     const bool want_e = want_eloc || grad_mode == 3;
     r.layout((int)std::min<int64_t>(batch, 1 << 20), want_e, grad_mode != 0);

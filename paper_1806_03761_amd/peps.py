@@ -47,6 +47,7 @@ _SIGS = {
     "peps_set_stream": [_P, _P],
     "peps_set_workspace_limit": [_P, ctypes.c_size_t],
     "peps_set_fused_steps": [_P, ctypes.c_int32],
+    "peps_set_truncation": [_P, ctypes.c_int32],
     "peps_workspace_query": [_P, ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int,
                              ctypes.POINTER(ctypes.c_size_t)],
     "peps_log_amplitude": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
@@ -56,7 +57,7 @@ _SIGS = {
     "peps_log_derivative": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                             _P, _P, _P, _P, _P],
     "peps_plan_check": [ctypes.POINTER(_Lattice), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
-                        ctypes.POINTER(ctypes.c_size_t)],
+                        ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "peps_profile_enable": [_P, ctypes.c_uint32],
     "peps_profile_read": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
@@ -150,13 +151,13 @@ def _prep(A, S, lat):
     return lib, ctx, A, S
 
 
-def plan_check(lat, batch: int, grad_mode: int = 3, want_eloc: bool = True) -> int:
+def plan_check(lat, batch: int, grad_mode: int = 3, want_eloc: bool = True, sweeps: int = 0) -> int:
     """Host-only dry run of the launch sequence with bounds checks (no GPU needed).
     Returns the workspace bytes of one chunk; raises if a bounds check fails."""
     lib = load_library()
     out = ctypes.c_size_t()
     st = lib.peps_plan_check(ctypes.byref(_lat(lat)), int(batch), int(grad_mode), int(bool(want_eloc)),
-                             ctypes.byref(out))
+                             int(sweeps), ctypes.byref(out))
     if st != 0:
         raise PepsError(f"peps_plan_check failed: {STATUS.get(st, st)}")
     return int(out.value)
@@ -202,6 +203,13 @@ def tune_save(path: str, device: int = 0):
 def tune_load(path: str, device: int = 0):
     lib, ctx = _context(device)
     _check(lib, ctx, lib.peps_tune_load(ctx, path.encode()), "peps_tune_load")
+
+
+def set_truncation(sweeps: int, device: int = 0):
+    """Boundary truncation of this device's context: 0 = canonical SVD (default),
+    1..16 = variational compression with that many sweeps (see peps_set_truncation)."""
+    lib, ctx = _context(device)
+    _check(lib, ctx, lib.peps_set_truncation(ctx, int(sweeps)), "peps_set_truncation")
 
 
 def set_fused_steps(enable: bool, device: int = 0):

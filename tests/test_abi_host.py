@@ -40,6 +40,30 @@ def test_plan_bounds(lat, batch):
             assert peps.plan_check(lat, batch, grad_mode, want_e) > 0
 
 
+@pytest.mark.parametrize("lat,batch", [
+    (Lattice(4, 4, 2, 4), 16), (Lattice(6, 6, 2, 3), 5), (Lattice(5, 5, 3, 4), 3), (Lattice(8, 8, 4, 16), 64),
+    (Lattice(16, 16, 6, 36), 2), (Lattice(12, 12, 6, 36), 3), (Lattice(4, 4, 16, 32), 2),
+    (Lattice(16, 16, 16, 32), 1), (Lattice(7, 2, 5, 9), 2), (Lattice(3, 7, 2, 1), 5)])
+def test_plan_bounds_variational(lat, batch):
+    """The launch sequence with variational compression (1 and 2 sweeps) stays in bounds."""
+    peps = _peps()
+    for sweeps in (1, 2):
+        for grad_mode, want_e in ((0, False), (0, True), (3, True)):
+            assert peps.plan_check(lat, batch, grad_mode, want_e, sweeps) > 0
+
+
+def test_plan_variational_limits():
+    """A site factorisation beyond one workgroup's LDS (Dc D x Dc = 512 x 64) is refused;
+    sweep counts outside [0, 16] are invalid."""
+    peps = _peps()
+    with pytest.raises(peps.PepsError, match="unsupported"):
+        peps.plan_check(Lattice(24, 24, 8, 64), 1, 0, False, 1)
+    assert peps.plan_check(Lattice(24, 24, 8, 64), 1, 0, False, 0) > 0
+    for sw in (-1, 17):
+        with pytest.raises(peps.PepsError):
+            peps.plan_check(Lattice(4, 4, 2, 4), 1, 0, False, sw)
+
+
 def test_plan_rejects_bad_lattice():
     peps = _peps()
     for lat in (Lattice(1, 4, 2, 2), Lattice(4, 4, 0, 2), Lattice(4, 4, 2, 0)):

@@ -1,0 +1,172 @@
+"""Variational boundary compression on the GPU (through the C ABI) against the FP64
+oracle with the same sweep count, element by element.
+
+Tolerances as for the SVD truncation in float64 (the compression runs in float64 in
+every precision mode): log-amplitude |d| <= 1e-10 max(1, |ln W|) with equal signs,
+local energy 1e-9 relative to max(1, |E|), per-sample log-derivative relative l2 1e-9.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_03761_amd.workloads import Lattice, make_random, make_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_AMP, TOL_E, TOL_G = 1e-10, 1e-9, 1e-9
+
+
+def _peps():
+    from paper_1806_03761_amd import peps
+    return peps
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _dev(A, S):
+    return torch.from_numpy(A).cuda(), torch.from_numpy(np.ascontiguousarray(S)).cuda()
+
+
+def _np(*ts):
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in ts]
+
+
+@pytest.fixture
+def truncation():
+    p = _peps()
+
+    def set_(sweeps):
+        p.set_truncation(sweeps)
+
+    yield set_
+    p.set_truncation(0)
+
+
+def _eval(A, S, lat, grad_mode=1):
+    la, sg, e, g, fl = _peps().evaluate(*_dev(A, S), lat, "f64", grad_mode=grad_mode)
+    if grad_mode:
+        return _np(la, sg, e, g, fl)
+    la, sg, e, fl = _np(la, sg, e, fl)
+    return la, sg, e, None, fl
+
+
+def _check(lat, A, S, sweeps, with_e=True, with_g=True):
+    la, sg, e, g, fl = _eval(A, S, lat, 1 if with_g else 0)
+    assert np.all(fl == 0), fl
+    worst = [0.0, 0.0, 0.0]
+    for b in range(len(S)):
+        if with_e or with_g:
+            la_o, sg_o, e_o, d_o, fl_o = O.full_path_one(A, lat, S[b], sweeps)
+        else:
+            la_o, sg_o, fl_o = O.log_amplitude_one(A, lat, S[b], sweeps)
+        assert fl_o == 0
+        assert int(sg[b]) == int(sg_o), (b, sg[b], sg_o)
+        ea = abs(la[b] - la_o) / max(1.0, abs(la_o))
+        worst[0] = max(worst[0], ea)
+        assert ea <= TOL_AMP, f"sample {b}: log-amp error {ea:.3e}"
+        if with_e:
+            ee = abs(e[b] - e_o) / max(1.0, abs(e_o))
+            worst[1] = max(worst[1], ee)
+            assert ee <= TOL_E, f"sample {b}: E_loc error {ee:.3e}"
+        if with_g:
+            eg = np.linalg.norm(g[b] - d_o) / max(np.linalg.norm(d_o), 1e-300)
+            worst[2] = max(worst[2], eg)
+            assert eg <= TOL_G, f"sample {b}: log-derivative error {eg:.3e}"
+    _say(f"  worst errors: amp {worst[0]:.2e} E {worst[1]:.2e} grad {worst[2]:.2e}")
+    return la
+
+
+@pytest.mark.parametrize("lat,seed,scaling", [
+    (Lattice(4, 4, 2, 4), 21, "half"), (Lattice(6, 6, 2, 3), 22, "half"), (Lattice(5, 5, 3, 4), 23, "half"),
+    (Lattice(7, 4, 3, 5), 24, "frobenius"), (Lattice(4, 6, 2, 2), 25, "half")])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_variational_small_lattices(lat, seed, scaling, sweeps, truncation):
+    A, S = make_random(lat, 5, seed, scaling)
+    _say("variational", lat, "sweeps", sweeps)
+    truncation(sweeps)
+    _check(lat, A, S, sweeps)
+
+
+def test_variational_changes_w_only_where_truncating(truncation):
+    """The SVD and variational truncations agree in the exact regime (4x4, D2, Dc4) and
+    differ in the truncated one (6x6, D2, Dc3)."""
+    for lat, differ in ((Lattice(4, 4, 2, 4), False), (Lattice(6, 6, 2, 3), True)):
+        A, S = make_random(lat, 6, 26, "half")
+        truncation(0)
+        l0 = _eval(A, S, lat, 0)[0]
+        truncation(1)
+        l1 = _eval(A, S, lat, 0)[0]
+        d = np.max(np.abs(l1 - l0))
+        _say("variational vs svd", lat, f"{d:.2e}")
+        assert (d > 1e-6) if differ else (d < 1e-10)
+
+
+def test_variational_8x8_D4_Dc16(truncation):
+    lat, A, S, _ = make_workload("8x8_D4_Dc16", 6)
+    _say("variational 8x8 D4 Dc16")
+    truncation(1)
+    _check(lat, A, S, 1)
+
+
+def _oracle_noise(A, lat, s, sweeps, la, seeds=(1, 2)):
+    """The oracle's own rounding noise on ln|W|: W is linear in every site tensor (the
+    compression is homogeneous in the applied row), so scaling site m by 1 + d_m
+    (|d_m| <= 2^-30) moves ln|W| by exactly sum ln(1 + d_m); whatever else moves is
+    rounding.  Relative to max(1, |ln W|), the largest over the seeds."""
+    worst = 0.0
+    for k in seeds:
+        d = np.random.default_rng(7100 + k).uniform(-1.0, 1.0, size=lat.N) * 2.0 ** -30
+        la2 = O.log_amplitude_one(A * (1.0 + d)[:, None, None, None, None, None], lat, s, sweeps)[0]
+        worst = max(worst, abs(la2 - float(np.sum(np.log1p(d))) - la) / max(1.0, abs(la)))
+    return worst
+
+
+def test_variational_16x16_D6_Dc36_amplitude(truncation):
+    """At 16x16, D = 6, Dc = 36 one sweep passes rounding on from row to row (each
+    boundary is linear in its guess, the previous boundary), so the oracle's own noise
+    on ln|W| reaches ~1e-10 (1e-12 with the SVD truncation): the bound is 10x that noise,
+    measured on the oracle alone, and never below 1e-10."""
+    lat, A, S, _ = make_workload("16x16_D6_Dc36", 2)
+    _say("variational 16x16 D6 Dc36 amplitude")
+    truncation(1)
+    la, sg, _, _, fl = _eval(A, S, lat, 0)
+    assert np.all(fl == 0)
+    for b in range(len(S)):
+        la_o, sg_o, fl_o = O.log_amplitude_one(A, lat, S[b], 1)
+        assert fl_o == 0 and int(sg[b]) == int(sg_o)
+        noise = _oracle_noise(A, lat, S[b], 1, la_o)
+        err = abs(la[b] - la_o) / max(1.0, abs(la_o))
+        _say(f"  sample {b}: error {err:.2e}, oracle noise {noise:.2e}")
+        assert err <= max(TOL_AMP, 10.0 * noise)
+
+
+def test_variational_D16_Dc32(truncation):
+    """The Dc = 2D regime at D = 16 (4x4 lattice): amplitude, local energy and
+    log-derivative."""
+    lat = Lattice(4, 4, 16, 32)
+    A, S = make_random(lat, 2, 27)
+    _say("variational 4x4 D16 Dc32")
+    truncation(1)
+    _check(lat, A, S, 1)
+
+
+def test_variational_chunked_equals_single_chunk(truncation):
+    """A workspace limit that splits the batch into chunks gives the same bits."""
+    p = _peps()
+    lat = Lattice(6, 6, 3, 5)
+    A, S = make_random(lat, 40, 28)
+    truncation(2)
+    ref = _eval(A, S, lat)
+    try:
+        p.set_workspace_limit(p.workspace_bytes(lat, 7))
+        got = _eval(A, S, lat)
+    finally:
+        p.set_workspace_limit(0)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
