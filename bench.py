@@ -301,10 +301,72 @@ def main():
     if not args.no_legs:
         la0, sg0, e0, g0, fl0 = (t.detach().cpu().numpy() for t in res_f64)
         legs = {}
+        step_s = ms / 1e3
+        # variational boundary compression (one sweep) in place of the SVD truncation on
+        # the same batch: throughput, the class breakdown (the flops move from the float64
+        # factorisations onto the GEMMs) and how far its results are from the SVD ones
+        # (two different approximations of W, so a difference, not an error)
+        vname = f"{name}_variational_1sweep"
+        if _fits(4.0 * step_s + 20.0):
+            _log(f"leg {vname}")
+            peps.set_truncation(1)
+            try:
+                gv = torch.empty_like(grad)
+                if not args.no_tune:
+                    peps.autotune(Ad, Sd, lat, args.prec)
+                step(out=gv)
+                torch.cuda.synchronize()
+                peps.profile_enable(CLASSES)
+                t1 = time.perf_counter()
+                rv = step(out=gv)
+                torch.cuda.synchronize()
+                dv = time.perf_counter() - t1
+                kv = _read(peps, CLASSES)
+                peps.profile_enable(())
+            finally:
+                peps.set_truncation(0)
+            lav, sgv, ev, ggv, flv = (t.detach().cpu().numpy() for t in rv)
+            ok = (fl0 == 0) & (flv == 0)
+            legs[vname] = {"samples_per_s": B / dv, "ms_per_step": dv * 1e3, "sweeps": 1,
+                           "kernels": {k: {"ms_total": v["ms_total"], "tflops": v["tflops"]} for k, v in kv.items()},
+                           "gemm_frac_of_f64_peak": kv["gemm"]["tflops"] / MI355X_PEAK["f64"],
+                           "diff_log_amp_vs_svd": _rel_errors(lav[ok], la0[ok]),
+                           "diff_e_loc_vs_svd": _rel_errors(ev[ok], e0[ok]),
+                           "sign_differences_vs_svd": int((sgv[ok] != sg0[ok]).sum())}
+        else:
+            legs[vname] = {"skipped": "time budget of the run"}
+        # the Dc ∝ D regime (D = 16, Dc = 32) on 16x16, variational compression, 64 samples
+        if _fits(60.0):
+            _log("leg 16x16_D16_Dc32_variational_1sweep")
+            from paper_1806_03761_amd.workloads import Lattice, make_random
+            lat5 = Lattice(16, 16, 16, 32)
+            A5, S5 = make_random(lat5, 64, 93)
+            A5d, S5d = torch.from_numpy(A5).to(dev), torch.from_numpy(S5).to(dev)
+            g5 = torch.empty((lat5.N, 2, lat5.D ** 4), dtype=torch.float64, device=dev)
+            peps.set_truncation(1)
+            try:
+                step("f64", A5d, S5d, lat5, g5)
+                torch.cuda.synchronize()
+                peps.profile_enable(CLASSES)
+                t1 = time.perf_counter()
+                r5 = step("f64", A5d, S5d, lat5, g5)
+                torch.cuda.synchronize()
+                d5 = time.perf_counter() - t1
+                k5 = _read(peps, CLASSES)
+                peps.profile_enable(())
+            finally:
+                peps.set_truncation(0)
+            legs["16x16_D16_Dc32_variational_1sweep"] = {
+                "samples_per_s": S5.shape[0] / d5, "ms_per_step": d5 * 1e3, "batch": int(S5.shape[0]),
+                "flagged": int((r5[4] != 0).sum().item()),
+                "kernels": {k: {"ms_total": v["ms_total"], "tflops": v["tflops"]} for k, v in k5.items()},
+                "sample": "64 seeded configurations, Frobenius-normalised Gaussian tensors, f64, heuristic GEMM tiles"}
+            del A5d, S5d, g5, r5
+        else:
+            legs["16x16_D16_Dc32_variational_1sweep"] = {"skipped": "time budget of the run"}
         # the same workload with narrower contraction arithmetic: throughput and the error
         # of every result against the float64 results above (which match the oracle to
         # 1e-10 on the tested subsets)
-        step_s = ms / 1e3
         for pr in ("f32", "bf16"):
             if pr == args.prec:
                 continue
