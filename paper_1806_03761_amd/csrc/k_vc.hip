@@ -7,32 +7,58 @@
 
 namespace peps {
 
-static constexpr int VT = 256;           // threads per matrix
+static constexpr int VT = 256;           // threads of the small kernels
 static constexpr int kThinqMaxN = 128;   // columns
 
 __device__ inline double vq_wsum(double v) { return lane_group_sum(v, 64); }
 
+template <int NT>
 __device__ inline double vq_bsum(double v, double* red) {
     v = vq_wsum(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < VT / 64; ++i) s += red[i];
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
     return s;
 }
 
-// One wave applies H = I - tk v v^T (v_k = 1, v_i = vk[i] below row k) to column aj,
-// rows k..m-1.
-__device__ inline void vq_reflect(const double* vk, double* aj, int k, int m, double tk, int lane) {
-    double d = lane == 0 ? aj[k] : 0.0;
-    for (int i = k + 1 + lane; i < m; i += 64) d += vk[i] * aj[i];
-    d = vq_wsum(d) * tk;
-    if (lane == 0) aj[k] -= d;
-    for (int i = k + 1 + lane; i < m; i += 64) aj[i] -= d * vk[i];
+// One wave applies H = I - tk v v^T (v_k = 1, v_i = a[k m + i] below row k) to the up to
+// G columns j0..j0+G-1 (< n) of a, rows k..m-1: the G dot products share every load of v
+// and are reduced together.
+template <int G>
+__device__ inline void vq_reflect(double* a, int m, int n, int k, int j0, double tk, int lane) {
+    const double* vk = a + (long long)k * m;
+    double* c0 = a + (long long)j0 * m;
+    const int nc = min(G, n - j0);
+    double d[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) d[c] = (lane == 0 && c < nc) ? c0[(long long)c * m + k] : 0.0;
+    for (int i = k + 1 + lane; i < m; i += 64) {
+        const double v = vk[i];
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (c < nc) d[c] += v * c0[(long long)c * m + i];
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) d[c] = vq_wsum(d[c]) * tk;
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (c < nc) c0[(long long)c * m + k] -= d[c];
+    }
+    for (int i = k + 1 + lane; i < m; i += 64) {
+        const double v = vk[i];
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+            if (c < nc) c0[(long long)c * m + i] -= d[c] * v;
+    }
 }
 
-// Thin Householder QR of one m x n matrix (m >= n) per workgroup, in LDS:
+// Thin Householder QR of one m x n matrix (m >= n) per workgroup of NT threads, held in
+// LDS (IN_LDS) or in the workgroup's slice of a global scratch buffer (W + b ws, m n
+// doubles; the waves of a workgroup share one CU, so its barriers order those accesses as
+// they do LDS ones):
 //   X: column-major, leading dimension m, stride xs per matrix (may equal Q: every
 //      element is read before any is written);
 //   Q: the m x n factor with the signs fixed so that diag(R) >= 0, element (i, k) at
@@ -40,29 +66,33 @@ __device__ inline void vq_reflect(const double* vk, double* aj, int k, int m, do
 //   R: when not null, the n x n factor (row-major, zeros below the diagonal), stride rs.
 // Reflectors follow the usual convention (beta = -sign(alpha) ||x||, tau = (beta -
 // alpha) / beta); a column with nothing below the diagonal gives tau = 0.  Q is formed
-// in place by applying the reflectors backwards to the leading n columns of I.
-__global__ __launch_bounds__(VT) void k_thinq(const double* X, long long xs, int m, int n, double* Q,
+// in place by applying the reflectors backwards to the leading n columns of I.  Each
+// wave updates groups of G trailing columns.
+template <int NT, bool IN_LDS, int G>
+__global__ __launch_bounds__(NT) void k_thinq(const double* X, long long xs, int m, int n, double* Q,
                                               long long qs, long long q_row, long long q_col, double* R,
-                                              long long rs) {
-    extern __shared__ double a[];
-    __shared__ double tau[kThinqMaxN], sg[kThinqMaxN], red[VT / 64];
+                                              long long rs, double* W, long long ws) {
+    constexpr int NW = NT / 64;
+    extern __shared__ double lds[];
+    __shared__ double tau[kThinqMaxN], sg[kThinqMaxN], red[NW];
     const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    double* a = IN_LDS ? lds : W + (long long)b * ws;
     const double* Xb = X + (long long)b * xs;
     const int mn = m * n;
-    for (int i = t; i < mn; i += VT) a[i] = Xb[i];
+    for (int i = t; i < mn; i += NT) a[i] = Xb[i];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
         double* ak = a + (long long)k * m;
         double s = 0.0;
-        for (int i = k + 1 + t; i < m; i += VT) s += ak[i] * ak[i];
-        s = vq_bsum(s, red);
+        for (int i = k + 1 + t; i < m; i += NT) s += ak[i] * ak[i];
+        s = vq_bsum<NT>(s, red);
         const double alpha = ak[k];
         double tk = 0.0, beta = alpha;
         if (s > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + s), alpha);
             tk = (beta - alpha) / beta;
             const double sc = 1.0 / (alpha - beta);
-            for (int i = k + 1 + t; i < m; i += VT) ak[i] *= sc;
+            for (int i = k + 1 + t; i < m; i += NT) ak[i] *= sc;
         }
         __syncthreads();
         if (t == 0) {
@@ -70,14 +100,14 @@ __global__ __launch_bounds__(VT) void k_thinq(const double* X, long long xs, int
             tau[k] = tk;
         }
         if (tk != 0.0)
-            for (int j = k + 1 + w; j < n; j += VT / 64) vq_reflect(ak, a + (long long)j * m, k, m, tk, lane);
+            for (int j0 = k + 1 + G * w; j0 < n; j0 += G * NW) vq_reflect<G>(a, m, n, k, j0, tk, lane);
         __syncthreads();
     }
-    for (int k = t; k < n; k += VT) sg[k] = a[k + (long long)k * m] < 0.0 ? -1.0 : 1.0;
+    for (int k = t; k < n; k += NT) sg[k] = a[k + (long long)k * m] < 0.0 ? -1.0 : 1.0;
     __syncthreads();
     if (R) {
         double* Rb = R + (long long)b * rs;
-        for (int idx = t; idx < n * n; idx += VT) {
+        for (int idx = t; idx < n * n; idx += NT) {
             const int k = idx / n, j = idx - k * n;
             Rb[idx] = j >= k ? sg[k] * a[k + (long long)j * m] : 0.0;
         }
@@ -87,35 +117,46 @@ __global__ __launch_bounds__(VT) void k_thinq(const double* X, long long xs, int
         double* ak = a + (long long)k * m;
         const double tk = tau[k];
         if (tk != 0.0)
-            for (int j = k + 1 + w; j < n; j += VT / 64) vq_reflect(ak, a + (long long)j * m, k, m, tk, lane);
+            for (int j0 = k + 1 + G * w; j0 < n; j0 += G * NW) vq_reflect<G>(a, m, n, k, j0, tk, lane);
         __syncthreads();
-        for (int i = t; i < m; i += VT) ak[i] = i < k ? 0.0 : (i == k ? 1.0 - tk : -tk * ak[i]);
+        for (int i = t; i < m; i += NT) ak[i] = i < k ? 0.0 : (i == k ? 1.0 - tk : -tk * ak[i]);
         __syncthreads();
     }
     double* Qb = Q + (long long)b * qs;
     if (q_row == 1) {
-        for (int idx = t; idx < mn; idx += VT) {
+        for (int idx = t; idx < mn; idx += NT) {
             const int k = idx / m, i = idx - k * m;
             Qb[i + (long long)k * q_col] = sg[k] * a[idx];
         }
     } else {
-        for (int idx = t; idx < mn; idx += VT) {
+        for (int idx = t; idx < mn; idx += NT) {
             const int i = idx / n, k = idx - i * n;
             Qb[(long long)i * q_row + (long long)k * q_col] = sg[k] * a[i + (long long)k * m];
         }
     }
 }
 
+bool thinq_shape_ok(int m, int n) { return n >= 1 && m >= n && n <= kThinqMaxN; }
 bool thinq_fits(int m, int n) {
-    return n >= 1 && m >= n && n <= kThinqMaxN && (size_t)m * n * sizeof(double) + 4096 <= get_lds_cap();
+    return thinq_shape_ok(m, n) && (size_t)m * n * sizeof(double) + 4096 <= get_lds_cap();
 }
 
+// LDS: 256 threads (two workgroups per CU at the largest matrices), one column per wave at
+// a time; global scratch: 1024 threads and four columns per wave, so that every trailing
+// column group of a step has a wave of its own and each load of v serves four columns
 hipError_t launch_thinq(const double* X, long long xs, int m, int n, double* Q, long long qs, long long q_row,
-                        long long q_col, double* R, long long rs, int batch, hipStream_t st) {
+                        long long q_col, double* R, long long rs, double* W, long long ws, int batch,
+                        hipStream_t st) {
     if (batch <= 0) return hipSuccess;
-    if (!thinq_fits(m, n)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_thinq, dim3(batch), dim3(VT), (size_t)m * n * sizeof(double), st, X, xs, m, n, Q, qs,
-                       q_row, q_col, R, rs);
+    if (!thinq_shape_ok(m, n)) return hipErrorInvalidValue;
+    if (thinq_fits(m, n)) {
+        hipLaunchKernelGGL((k_thinq<256, true, 1>), dim3(batch), dim3(256), (size_t)m * n * sizeof(double), st, X, xs,
+                           m, n, Q, qs, q_row, q_col, R, rs, nullptr, 0LL);
+    } else {
+        if (!W || ws < (long long)m * n) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_thinq<1024, false, 4>), dim3(batch), dim3(1024), 0, st, X, xs, m, n, Q, qs, q_row,
+                           q_col, R, rs, W, ws);
+    }
     return hipGetLastError();
 }
 
@@ -127,7 +168,7 @@ __global__ __launch_bounds__(VT) void k_vc_norm(double* x, long long xs, int n, 
     double* xb = x + (long long)b * xs;
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += VT) s += xb[i] * xb[i];
-    s = vq_bsum(s, red);
+    s = vq_bsum<VT>(s, red);
     const double nu = sqrt(s);
     if (nu > 0.0) {
         const double inv = 1.0 / nu;

@@ -79,12 +79,15 @@ hipError_t launch_applyq_blocked(const double* V, long long vs, int mz, int nref
                                  long long zs, int ldz, double* Wq, long long wqs, int batch, hipStream_t st);
 
 // variational compression (k_vc.hip)
-// thin QR of m x n matrices (m >= n, column-major, one per sample) into the sign-fixed
-// Q (element (i, k) at Q + b qs + i q_row + k q_col) and, when R != nullptr, the n x n
-// factor (row-major); X may equal Q.  thinq_fits: the matrix fits in LDS.
+// thin QR of m x n matrices (m >= n, n <= 128, column-major, one per sample) into the
+// sign-fixed Q (element (i, k) at Q + b qs + i q_row + k q_col) and, when R != nullptr,
+// the n x n factor (row-major); X may equal Q.  Matrices that do not fit in LDS
+// (thinq_fits false) are worked on in W (m n doubles per sample, stride ws).
+bool thinq_shape_ok(int m, int n);
 bool thinq_fits(int m, int n);
 hipError_t launch_thinq(const double* X, long long xs, int m, int n, double* Q, long long qs, long long q_row,
-                        long long q_col, double* R, long long rs, int batch, hipStream_t st);
+                        long long q_col, double* R, long long rs, double* W, long long ws, int batch,
+                        hipStream_t st);
 // x /= ||x||, lout = lin + ln ||x|| (lout = -inf for a zero x)
 hipError_t launch_vc_norm(double* x, long long xs, int n, const double* lin, double* lout, int batch,
                           hipStream_t st);

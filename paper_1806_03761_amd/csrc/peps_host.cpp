@@ -174,10 +174,10 @@ public:
         auto check = [&](const Trunc& t) -> std::string {
             for (int j = 0; j < Lx; ++j) {
                 const int a = t.chi[j], b = t.chi[j + 1];
-                if (!thinq_fits(a * t.p, b) || !thinq_fits(t.p * b, a)) {
+                if (!thinq_shape_ok(a * t.p, b) || !thinq_shape_ok(t.p * b, a)) {
                     char m[160];
-                    snprintf(m, sizeof m, "variational compression: the %d x %d site factorisation does not "
-                             "fit in LDS", std::max(a * t.p, t.p * b), std::max(a, b));
+                    snprintf(m, sizeof m, "variational compression: bond %d exceeds the 128 columns of the "
+                             "site factorisation", std::max(a, b));
                     return m;
                 }
             }
@@ -274,7 +274,7 @@ public:
         vc_eoff.assign(Lx + 2, 0);
         {
             std::vector<long long> e(Lx + 1, 0);
-            s_vZ1 = s_vZ2 = s_vM = s_vRf = 0;
+            s_vZ1 = s_vZ2 = s_vM = s_vRf = s_vW = 0;
             auto visit_vc = [&](const Trunc& t) {
                 for (int c = 0; c <= Lx; ++c) e[c] = std::max<long long>(e[c], (long long)t.chi[c] * t.chi[c] * Dh[c]);
                 for (int j = 0; j < Lx; ++j) {
@@ -283,6 +283,8 @@ public:
                     s_vZ2 = std::max({s_vZ2, a * b * hr * p, b * a * hl * p});
                     s_vM = std::max(s_vM, a * p * b);
                     s_vRf = std::max({s_vRf, a * a, b * b});
+                    if (!thinq_fits((int)(a * p), (int)b) || !thinq_fits((int)(p * b), (int)a))
+                        s_vW = std::max(s_vW, a * p * b);
                 }
             };
             bool any = false;
@@ -299,6 +301,7 @@ public:
             o_vZ2 = any ? L.alloc(s_vZ2) : 0;
             o_vM = any ? L.alloc(s_vM) : 0;
             o_vRf = any ? L.alloc(s_vRf) : 0;
+            o_vW = s_vW > 0 ? L.alloc(s_vW) : 0;   // factorisations beyond LDS
         }
         o_X.resize(Lx); o_tau.resize(Lx); o_wy.assign(Lx, 0);
         for (int j = 0; j < Lx; ++j) {
@@ -629,14 +632,17 @@ public:
         // thin QR of an m x n column-major matrix at X into Q (rows q_row, columns q_col apart)
         auto thinq = [&](const Op& X, int m, int n, const Op& Q, long long q_row, long long q_col,
                          bool with_r) -> hipError_t {
+            const bool in_lds = thinq_fits(m, n);
+            const Op Wq = op(o_vW, s_vW);
             if (!bounds_ok("vc qr in", X, (long long)m * n - 1, 0) ||
                 !bounds_ok("vc qr out", Q, (long long)(m - 1) * q_row + (long long)(n - 1) * q_col, 0) ||
-                (with_r && !bounds_ok("vc qr R", Rf, (long long)n * n - 1, 0)))
+                (with_r && !bounds_ok("vc qr R", Rf, (long long)n * n - 1, 0)) ||
+                (!in_lds && (s_vW < (long long)m * n || !bounds_ok("vc qr scratch", Wq, (long long)m * n - 1, 0))))
                 return hipErrorInvalidValue;
             const double fl = (4.0 * m * n * n - 4.0 / 3.0 * n * n * n) * Bcur;
             KL(timed(PEPS_KC_QR, fl, [&] {
                 return launch_thinq(X.p, X.bs, m, n, Q.p, Q.bs, q_row, q_col, with_r ? Rf.p : nullptr, Rf.bs,
-                                    Bcur, st_);
+                                    in_lds ? nullptr : Wq.p, in_lds ? 0 : Wq.bs, Bcur, st_);
             }));
             return hipSuccess;
         };
@@ -1151,8 +1157,8 @@ public:
     int sweeps = 0;                         // variational compression sweeps (0: SVD truncation)
     std::vector<char> vcU, vcL;             // which truncations are variational
     std::vector<long long> vc_eoff;         // offset of cut c's overlap environment
-    size_t o_vL = 0, o_vR = 0, o_vZ1 = 0, o_vZ2 = 0, o_vM = 0, o_vRf = 0;
-    long long s_vE = 0, s_vZ1 = 0, s_vZ2 = 0, s_vM = 0, s_vRf = 0;
+    size_t o_vL = 0, o_vR = 0, o_vZ1 = 0, o_vZ2 = 0, o_vM = 0, o_vRf = 0, o_vW = 0;
+    long long s_vE = 0, s_vZ1 = 0, s_vZ2 = 0, s_vM = 0, s_vRf = 0, s_vW = 0;
     bool step_rescaled = false;   // the last sandwich step also applied the max-abs rescale
 };
 

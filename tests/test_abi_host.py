@@ -53,12 +53,14 @@ def test_plan_bounds_variational(lat, batch):
 
 
 def test_plan_variational_limits():
-    """A site factorisation beyond one workgroup's LDS (Dc D x Dc = 512 x 64) is refused;
-    sweep counts outside [0, 16] are invalid."""
+    """Site factorisations beyond LDS (Dc D x Dc = 512 x 64) run from a global scratch
+    buffer; a bond above 128 columns is refused; sweep counts outside [0, 16] are invalid."""
     peps = _peps()
+    for lat in (Lattice(24, 24, 8, 64), Lattice(16, 16, 8, 64)):
+        assert peps.plan_check(lat, 2, 3, True, 1) > 0
     with pytest.raises(peps.PepsError, match="unsupported"):
-        peps.plan_check(Lattice(24, 24, 8, 64), 1, 0, False, 1)
-    assert peps.plan_check(Lattice(24, 24, 8, 64), 1, 0, False, 0) > 0
+        peps.plan_check(Lattice(10, 10, 4, 150), 1, 0, False, 1)
+    assert peps.plan_check(Lattice(10, 10, 4, 150), 1, 0, False, 0) > 0
     for sw in (-1, 17):
         with pytest.raises(peps.PepsError):
             peps.plan_check(Lattice(4, 4, 2, 4), 1, 0, False, sw)

@@ -227,3 +227,18 @@ def test_variational_differs_from_svd_and_approaches_it():
     l4 = O.log_amplitude(A, lat, S, sweeps=4)[0]
     assert np.max(np.abs(l1 - l0)) > 1e-6
     assert np.max(np.abs(l4 - l0)) < 0.2
+
+
+def test_variational_accuracy_weakly_entangled():
+    """Against the exact W (the same lattice contracted with Dc at the full boundary rank),
+    one sweep is as accurate as the SVD truncation on a weakly entangled state (a product
+    state plus half a Gaussian PEPS): both within 1e-6 of ln|W|."""
+    lat, latx = Lattice(8, 6, 2, 4), Lattice(8, 6, 2, 16)
+    A, S = make_random(lat, 8, 31)
+    a = np.random.default_rng(0).uniform(0.5, 1.5, size=(lat.N, 2))
+    A2 = 0.5 * A / np.max(np.abs(A))
+    A2[:, :, 0, 0, 0, 0] += a
+    ex = O.log_amplitude(A2, latx, S)[0]
+    for sweeps in (0, 1):
+        d = np.abs(O.log_amplitude(A2, lat, S, sweeps)[0] - ex)
+        assert d.max() < 1e-6, (sweeps, d.max())
