@@ -48,23 +48,23 @@ def _oracle_worker(args):
 
     import oracle as O
     from paper_1806_03761_amd.workloads import make_workload
-    name, lo, hi = args
+    name, lo, hi, sweeps = args
     with threadpool_limits(limits=1):
         lat, A, S, _ = make_workload(name, hi)
         for b in range(lo, hi):
-            O.full_path_one(A, lat, S[b])
+            O.full_path_one(A, lat, S[b], sweeps)
     return hi - lo
 
 
-def start_cpu_baseline(name: str, per_proc: int):
+def start_cpu_baseline(name: str, per_proc: int, sweeps: int = 0):
     """Start the FP64 oracle (amplitude + local energy + log-derivatives, one sample at a
     time per process, numpy single-threaded) on up to 16 host cores over the first samples
     of the workload; returns a handle for finish_cpu_baseline."""
     import multiprocessing as mp
     procs = max(1, min(16, os.cpu_count() or 1))
-    tasks = [(name, k * per_proc, (k + 1) * per_proc) for k in range(procs)]
+    tasks = [(name, k * per_proc, (k + 1) * per_proc, sweeps) for k in range(procs)]
     pool = mp.get_context("spawn").Pool(procs)
-    pool.map(_oracle_worker, [(name, 0, 0)] * procs)           # imports warmed up
+    pool.map(_oracle_worker, [(name, 0, 0, sweeps)] * procs)   # imports warmed up
     t0 = time.perf_counter()
     res = pool.map_async(_oracle_worker, tasks)
     return pool, res, t0, procs, per_proc
@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the GEMM tile autotuner")
+    ap.add_argument("--truncation-sweeps", type=int, default=0,
+                    help="boundary truncation of the timed workload: 0 = canonical SVD (the default "
+                         "path), n > 0 = variational compression with n sweeps")
     ap.add_argument("--mixed", action="store_true",
                     help="only the uneven batch: 2048 samples over 8x8 (D 4, Dc 16), 12x12 (D 6, Dc 36) "
                          "and 16x16 (D 8, Dc 64) at 50/30/20, float32 contractions, one captured graph")
@@ -222,6 +225,7 @@ def main():
     Sd = torch.from_numpy(S).to(dev)
     N, D4 = lat.N, lat.D ** 4
     grad = torch.empty((N, 2, D4), dtype=torch.float64, device=dev)
+    peps.set_truncation(args.truncation_sweeps)
 
     def step(prec=args.prec, Ax=Ad, Sx=Sd, latx=lat, out=grad):
         return peps.evaluate(Ax, Sx, latx, prec, grad_mode=3, out=out)
@@ -232,7 +236,7 @@ def main():
     _log(f"{name}: batch {B}, {tuned} GEMM shapes tuned")
     cpu_h = None
     if not args.no_cpu_baseline:
-        cpu_h = start_cpu_baseline(name, 1)
+        cpu_h = start_cpu_baseline(name, 1, args.truncation_sweeps)
     # warm-up steps with every kernel class bracketed by HIP events: the per-class
     # breakdown, and which class dominates
     peps.profile_enable(CLASSES)
@@ -285,6 +289,8 @@ def main():
                                f"local energy + dE/dA",
                    "lattice": [lat.Lx, lat.Ly], "D": lat.D, "Dc": lat.Dc, "batch": B,
                    "gemm_precision": args.prec, "factorisation_precision": "f64",
+                   "truncation": ("canonical SVD" if args.truncation_sweeps == 0 else
+                                  f"variational, {args.truncation_sweeps} sweeps"),
                    "autotuned_gemm_shapes": tuned},
     }
     peak = MI355X_PEAK["f64" if args.prec == "f64" else "f32"]
@@ -298,7 +304,7 @@ def main():
     # every class against the dtype's matrix-core peak (the factorisations against fp64)
     res["kernels_warmup"] = {k: dict(v, frac_of_peak=v["tflops"] / (MI355X_PEAK["f64"] if k in ("svd", "qr") else peak))
                              for k, v in kern.items()}
-    if not args.no_legs:
+    if not args.no_legs and args.truncation_sweeps == 0:
         la0, sg0, e0, g0, fl0 = (t.detach().cpu().numpy() for t in res_f64)
         legs = {}
         step_s = ms / 1e3
@@ -335,6 +341,34 @@ def main():
                            "sign_differences_vs_svd": int((sgv[ok] != sg0[ok]).sum())}
         else:
             legs[vname] = {"skipped": "time budget of the run"}
+        # 24x24, D = 8, Dc = 64 with variational compression: 128 of its 512 samples
+        if _fits(60.0):
+            _log("leg 24x24_D8_Dc64_variational_1sweep")
+            lat6, A6, S6, _ = make_workload("24x24_D8_Dc64", 128)
+            A6d, S6d = torch.from_numpy(A6).to(dev), torch.from_numpy(S6).to(dev)
+            g6 = torch.empty((lat6.N, 2, lat6.D ** 4), dtype=torch.float64, device=dev)
+            peps.set_truncation(1)
+            try:
+                step("f64", A6d, S6d, lat6, g6)
+                torch.cuda.synchronize()
+                peps.profile_enable(CLASSES)
+                t1 = time.perf_counter()
+                r6 = step("f64", A6d, S6d, lat6, g6)
+                torch.cuda.synchronize()
+                d6 = time.perf_counter() - t1
+                k6 = _read(peps, CLASSES)
+                peps.profile_enable(())
+            finally:
+                peps.set_truncation(0)
+            legs["24x24_D8_Dc64_variational_1sweep"] = {
+                "samples_per_s": S6.shape[0] / d6, "ms_per_step": d6 * 1e3, "batch": int(S6.shape[0]),
+                "flagged": int((r6[4] != 0).sum().item()),
+                "kernels": {k: {"ms_total": v["ms_total"], "tflops": v["tflops"]} for k, v in k6.items()},
+                "sample": "the first 128 of the 512 configurations, f64, heuristic GEMM tiles; amplitude + "
+                          "local energy + dE/dA"}
+            del A6d, S6d, g6, r6
+        else:
+            legs["24x24_D8_Dc64_variational_1sweep"] = {"skipped": "time budget of the run"}
         # the Dc ∝ D regime (D = 16, Dc = 32) on 16x16, variational compression, 64 samples
         if _fits(60.0):
             _log("leg 16x16_D16_Dc32_variational_1sweep")
