@@ -87,7 +87,7 @@ def finish_cpu_baseline(h, name):
 # same counter reads for a 256 MiB device copy (FETCH_SIZE reads half of the copied bytes:
 # factor 2.0; WRITE_SIZE all: 1.0).  Valid only for the kernel sources they were measured
 # on (hash below) and the workload, arithmetic and batch named; otherwise null.
-TRAFFIC = {"sources": "e261c0f71b867d58",
+TRAFFIC = {"sources": "6c7d262cbc03cc88",
            "bytes_per_launch": {("8x8_D4_Dc16", "f64", 4096, "gemm"): 166.4e6}}
 
 
@@ -114,9 +114,30 @@ def _read(peps, classes):
     out = {}
     for cls in classes:
         kms, n, fl = peps.profile_read(cls)
+        by = peps.profile_bytes(cls)
         out[cls] = {"ms_total": kms, "launches": n, "avg_us": 1e3 * kms / max(n, 1),
-                    "tflops": fl / max(kms, 1e-12) / 1e9}
+                    "tflops": fl / max(kms, 1e-12) / 1e9, "flops": fl, "bytes": by,
+                    "gbps": by / max(kms, 1e-12) / 1e6}
     return out
+
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def _roofline(timed, peak_tflops):
+    """The binding roof of a kernel class from its algorithmic flops and bytes: HBM when the
+    arithmetic intensity is below the ridge point peak_flops / peak_bandwidth, else the
+    matrix cores; both views are kept."""
+    ridge = peak_tflops * 1e12 / (HBM_PEAK_GBPS * 1e9)
+    ai = timed["flops"] / timed["bytes"] if timed["bytes"] > 0 else float("inf")
+    mfma = {"achieved": timed["tflops"], "peak": peak_tflops, "unit": "TFLOP/s",
+            "frac": timed["tflops"] / peak_tflops}
+    hbm = {"achieved": timed["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": timed["gbps"] / HBM_PEAK_GBPS} if timed["bytes"] > 0 else None
+    if hbm is not None and ai < ridge:
+        return dict(bound="hbm", **hbm, arithmetic_intensity=ai, ridge=ridge, mfma_view=mfma,
+                    algorithmic_bytes_per_launch=timed["bytes"] / max(timed["launches"], 1))
+    return dict(bound="mfma", **mfma, arithmetic_intensity=ai, ridge=ridge, hbm_view=hbm)
 
 
 def _rel_errors(x, ref, floor=1.0):
@@ -297,10 +318,9 @@ def main():
     traffic = None
     if TRAFFIC["sources"] == _sources_hash():
         traffic = TRAFFIC["bytes_per_launch"].get((name, args.prec, B, dom))
-    res["roofline"] = {"kernel": CLASS_NAMES[dom], "class": dom, "bound": "mfma", "achieved": timed["tflops"],
-                       "peak": peak, "unit": "TFLOP/s", "frac": timed["tflops"] / peak,
-                       "traffic": traffic, "avg_launch_us": timed["avg_us"], "launches": timed["launches"],
-                       "share_of_kernel_time": kern[dom]["ms_total"] / max(sum(v["ms_total"] for v in kern.values()), 1e-9)}
+    res["roofline"] = dict({"kernel": CLASS_NAMES[dom], "class": dom}, **_roofline(timed, peak),
+                           traffic=traffic, avg_launch_us=timed["avg_us"], launches=timed["launches"],
+                           share_of_kernel_time=kern[dom]["ms_total"] / max(sum(v["ms_total"] for v in kern.values()), 1e-9))
     # every class against the dtype's matrix-core peak (the factorisations against fp64)
     res["kernels_warmup"] = {k: dict(v, frac_of_peak=v["tflops"] / (MI355X_PEAK["f64"] if k in ("svd", "qr") else peak))
                              for k, v in kern.items()}

@@ -322,6 +322,14 @@ peps_status peps_profile_enable(peps_ctx* ctx, uint32_t class_mask);
 peps_status peps_profile_read(peps_ctx* ctx, int32_t kernel_class, double* total_ms,
                               int64_t* launches, double* flops);
 
+/* The summed algorithmic HBM bytes of one kernel class's timed launches since the last
+ * peps_profile_enable (call after peps_profile_read, which synchronises).  Counted for the
+ * GEMM class only (0 for the others): per launch, every operand read once and the result
+ * written once for each active sample, in its storage type; an operand shared by all
+ * samples (the site tensors, the ones vector) once per launch, both spin slices of a
+ * gathered one.  The minimum traffic of the product, for a bandwidth roofline. */
+peps_status peps_profile_read_bytes(peps_ctx* ctx, int32_t kernel_class, double* bytes);
+
 /* Diagnostic, no device work: lay out the workspace of one chunk of `batch` samples
  * and walk the whole launch sequence of an evaluation (want_eloc, grad_mode as in
  * peps_evaluate; sweeps as in peps_set_truncation) without launching anything,

@@ -26,6 +26,7 @@ struct ProfRec {
     hipEvent_t a, b;
     int cls;
     double flops;
+    double bytes;   // algorithmic HBM bytes (GEMMs: operands read once, result written once)
 };
 
 // a captured job list of peps_eval_jobs, replayed when the same list comes again
@@ -434,7 +435,17 @@ public:
             return hipErrorInvalidValue;
         if (dry) return hipSuccess;
         GemmArgs g;
-        const double fl = 2.0 * M * Nn * K * (double)active_samples();
+        const double ns = (double)active_samples();
+        const double fl = 2.0 * M * Nn * K * ns;
+        // algorithmic bytes: each operand read once and the result written once per active
+        // sample; an operand shared by all samples (batch stride 0) once per launch, both
+        // spin slices of a gathered one
+        auto obytes = [&](const Op& o, double elems, const Gather& gt) {
+            const double w = o.f32 ? 4.0 : 8.0;
+            return o.bs == 0 ? elems * w * (gt.sel ? 2.0 : 1.0) : elems * w * ns;
+        };
+        const double by = obytes(A, (double)M * K, ga) + obytes(B, (double)K * Nn, gb) +
+                          obytes(C, (double)M * Nn, Gather{});
         g.M = M; g.N = Nn; g.K = K; g.batch = Bcur;
         g.am = am; g.ak = ak; g.bk = bk; g.bn = bn; g.cm = cm; g.cn = cn;
         g.a_bs = A.bs; g.b_bs = B.bs; g.c_bs = C.bs;
@@ -481,7 +492,7 @@ public:
             ctx->tuned_now++;
             return hipSuccess;
         }
-        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, arith, st_, tile); });
+        return timed(PEPS_KC_GEMM, fl, [&] { return launch_gemm(g, arith, st_, tile); }, by);
     }
     Gather site_gather(int i, int j, int flip) const {
         return Gather{Scur + (long long)i * Lx + j, (long long)N, flip, (long long)D4};
@@ -928,7 +939,7 @@ public:
 
     // launch `f` between two events when its kernel class is being profiled
     template <class F>
-    hipError_t timed(int cls, double flops, F f) {
+    hipError_t timed(int cls, double flops, F f, double bytes = 0.0) {
         if (dry || quiet || !(ctx->prof_mask & (1u << cls))) return f();
         hipEvent_t ev[2];
         for (int k = 0; k < 2; ++k) {
@@ -943,7 +954,7 @@ public:
         hipError_t e = hipEventRecord(ev[0], st_);
         if (e == hipSuccess) e = f();
         if (e == hipSuccess) e = hipEventRecord(ev[1], st_);
-        ctx->prof.push_back(ProfRec{ev[0], ev[1], cls, flops});
+        ctx->prof.push_back(ProfRec{ev[0], ev[1], cls, flops, bytes});
         return e;
     }
     // algorithmic flop models (documented in the design notes)
@@ -1619,6 +1630,15 @@ peps_status peps_profile_read(peps_ctx* c, int32_t kernel_class, double* total_m
     if (total_ms) *total_ms = ms;
     if (launches) *launches = n;
     if (flops) *flops = fl;
+    return PEPS_OK;
+}
+
+peps_status peps_profile_read_bytes(peps_ctx* c, int32_t kernel_class, double* bytes) {
+    if (!c || !bytes || kernel_class < 0 || kernel_class >= 32) return PEPS_ERR_INVALID_ARG;
+    double by = 0.0;
+    for (auto& r : c->prof)
+        if (r.cls == kernel_class) by += r.bytes;
+    *bytes = by;
     return PEPS_OK;
 }
 

@@ -61,6 +61,7 @@ _SIGS = {
     "peps_profile_enable": [_P, ctypes.c_uint32],
     "peps_profile_read": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "peps_profile_read_bytes": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "peps_eval_jobs": [_P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32],
     "peps_autotune": [_P, ctypes.POINTER(_Lattice), ctypes.c_int, _P, _P, ctypes.c_int64,
                       ctypes.POINTER(ctypes.c_int32)],
@@ -183,6 +184,16 @@ def profile_read(cls: str, device: int = 0):
     st = lib.peps_profile_read(ctx, KERNEL_CLASS[cls], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl))
     _check(lib, ctx, st, "peps_profile_read")
     return ms.value, n.value, fl.value
+
+
+def profile_bytes(cls: str, device: int = 0) -> float:
+    """Algorithmic HBM bytes of one kernel class's timed launches since enable (GEMM class;
+    call after profile_read)."""
+    lib, ctx = _context(device)
+    by = ctypes.c_double()
+    _check(lib, ctx, lib.peps_profile_read_bytes(ctx, KERNEL_CLASS[cls], ctypes.byref(by)),
+           "peps_profile_read_bytes")
+    return by.value
 
 
 def autotune(A, S, lat, prec: str = "f32") -> int:
