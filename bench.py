@@ -153,6 +153,7 @@ def run_mixed(args, peps, torch):
     from paper_1806_03761_amd.workloads import MIXED_BATCH, make_workload
     dev = torch.device("cuda:0")
     peps.set_workspace_limit(200 << 30)
+    peps.set_truncation(args.truncation_sweeps)
     jobs, total = [], 0
     tuned = {}
     for name, B in MIXED_BATCH:
@@ -187,7 +188,9 @@ def run_mixed(args, peps, torch):
            "config": {"workload": "uneven batch in one captured graph: " +
                                   ", ".join(f"{n} x {B}" for n, B in MIXED_BATCH) +
                                   "; float32 contraction GEMMs, float64 QR/SVD; amplitude + local energy + dE/dA",
-                      "batch": total, "autotuned_gemm_shapes": tuned},
+                      "batch": total, "autotuned_gemm_shapes": tuned,
+                      "truncation": ("canonical SVD" if args.truncation_sweeps == 0 else
+                                     f"variational, {args.truncation_sweeps} sweeps (float64)")},
            "flagged_samples": flags, "run_wall_s": time.time() - T_START}
     print(json.dumps(res), flush=True)
 

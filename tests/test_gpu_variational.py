@@ -213,3 +213,37 @@ def test_variational_D8_Dc64_against_goldens(name, truncation):
         err = abs(e[0] - ge["e_loc"])
         _say(f"  sample 0: |d E| {err:.2e}, oracle noise {ge['noise']:.2e}")
         assert err <= max(TOL_E * max(1.0, abs(ge["e_loc"])), 10.0 * ge["noise"])
+
+
+def test_variational_in_a_captured_graph(truncation):
+    """Two lattices with variational compression in one captured HIP graph: each job's
+    outputs equal a separate evaluation bit for bit, over three replays with eager work in
+    between; switching the truncation back captures a new graph (the cached one is keyed
+    on it) whose results equal the SVD truncation's."""
+    p = _peps()
+    specs = [(Lattice(6, 6, 2, 3), 9, 41), (Lattice(5, 7, 3, 4), 6, 42)]
+    truncation(1)
+    jobs, ref = [], []
+    for lat, B, seed in specs:
+        A, S = make_random(lat, B, seed, "half")
+        Ad, Sd = _dev(A, S)
+        jobs.append({"A": Ad, "S": Sd, "lat": lat, "grad_mode": 1})
+        ref.append(_np(*p.evaluate(Ad, Sd, lat, "f64", grad_mode=1)))
+    outs = p.eval_jobs(jobs, "f64", graph=True)
+    for rep in range(3):
+        for k, o in enumerate(outs):
+            for x, y in zip(_np(*o), ref[k]):
+                assert np.array_equal(x, y, equal_nan=True), (rep, k)
+        for o in outs:
+            for t in o:
+                t.zero_()
+        torch.cuda.synchronize()
+        _ = p.log_amplitude(jobs[0]["A"], jobs[0]["S"], jobs[0]["lat"], "f64")
+        torch.cuda.synchronize()
+        outs = p.eval_jobs(jobs, "f64", graph=True, outputs=outs)
+    truncation(0)
+    svd = _np(*p.evaluate(jobs[0]["A"], jobs[0]["S"], jobs[0]["lat"], "f64", grad_mode=1))
+    outs = p.eval_jobs(jobs, "f64", graph=True, outputs=outs)
+    for x, y in zip(_np(*outs[0]), svd):
+        assert np.array_equal(x, y, equal_nan=True)
+    assert not np.array_equal(svd[0], ref[0][0])
