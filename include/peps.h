@@ -92,9 +92,10 @@ peps_status peps_set_stream(peps_ctx* ctx, void* hip_stream);
  * right-to-left passes, every factor sign-fixed (non-negative diagonal of R), the norm
  * kept as a log.  Its contractions are float64 batched GEMMs of O(D^4 Dc^2) per site
  * and pass, whatever the precision argument of a call; the result is a different
- * approximation of W than the SVD truncation's.  Evaluations fail with
- * PEPS_ERR_UNSUPPORTED when a site factorisation (Dc D x Dc) does not fit in one
- * workgroup's LDS.  PEPS_ERR_INVALID_ARG for sweeps outside [0, 16]. */
+ * approximation of W than the SVD truncation's.  Site factorisations (Dc D x Dc) run in
+ * LDS where they fit and from workspace memory otherwise; evaluations fail with
+ * PEPS_ERR_UNSUPPORTED when a bond of a variational step exceeds 128.
+ * PEPS_ERR_INVALID_ARG for sweeps outside [0, 16]. */
 peps_status peps_set_truncation(peps_ctx* ctx, int32_t sweeps);
 
 /* Fused float32 sandwich steps (enable != 0, the default): the single- and two-row steps
