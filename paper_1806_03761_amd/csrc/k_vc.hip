@@ -136,20 +136,192 @@ __global__ __launch_bounds__(NT) void k_thinq(const double* X, long long xs, int
     }
 }
 
+// The same factorisation with the matrix in registers: column j belongs to wave j % NW
+// (slot j / NW), its rows i = lane + 64 r (r < RPL) to that wave's lanes, so m <= 64 RPL
+// and n <= NW * SL.  Only the current reflector v_k is shared, through a double-buffered
+// LDS vector (one barrier per step): the owner of column k forms it with wave reductions,
+// every wave applies it to its own trailing columns.  Q is formed in the registers the same
+// way, backwards, and stored with the signs that make diag(R) >= 0.
+template <int NW, int SL, int RPL>
+__global__ __launch_bounds__(NW * 64) void k_thinq_reg(const double* X, long long xs, int m, int n, double* Q,
+                                                       long long qs, long long q_row, long long q_col, double* R,
+                                                       long long rs) {
+    __shared__ double vbuf[2][64 * RPL];
+    __shared__ double tau[NW * SL], sg[NW * SL];
+    const int b = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double* Xb = X + (long long)b * xs;
+    double a[SL][RPL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int j = s * NW + w;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            a[s][r] = (j < n && i < m) ? Xb[i + (long long)j * m] : 0.0;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        double* v = vbuf[k & 1];
+        if (w == k % NW) {
+            const int sk = k / NW;
+            double x[RPL];
+#pragma unroll
+            for (int s = 0; s < SL; ++s)
+                if (s == sk) {
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) x[r] = a[s][r];
+                }
+            double ss = 0.0, al = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i > k && i < m) ss += x[r] * x[r];
+                if (i == k) al = x[r];
+            }
+            ss = vq_wsum(ss);
+            al = vq_wsum(al);
+            double tk = 0.0, beta = al, sc = 0.0;
+            if (ss > 0.0) {
+                beta = -copysign(sqrt(al * al + ss), al);
+                tk = (beta - al) / beta;
+                sc = 1.0 / (al - beta);
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                double vi = 0.0;
+                if (i == k) {
+                    vi = 1.0;
+                    x[r] = beta;
+                } else if (i > k && i < m) {
+                    vi = ss > 0.0 ? x[r] * sc : 0.0;
+                    x[r] = vi;
+                }
+                v[i] = vi;
+            }
+#pragma unroll
+            for (int s = 0; s < SL; ++s)
+                if (s == sk) {
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) a[s][r] = x[r];
+                }
+            if (lane == 0) tau[k] = tk;
+        }
+        __syncthreads();
+        const double tk = tau[k];
+        if (tk != 0.0) {
+            double vr[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) vr[r] = v[lane + 64 * r];
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const int j = s * NW + w;
+                if (j > k && j < n) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) d += vr[r] * a[s][r];
+                    d = vq_wsum(d) * tk;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) a[s][r] -= d * vr[r];
+                }
+            }
+        }
+    }
+    // signs of diag(R) and R itself
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int j = s * NW + w;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+            if (j < n && lane + 64 * r == j) sg[j] = a[s][r] < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    if (R) {
+        double* Rb = R + (long long)b * rs;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int j = s * NW + w;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (j < n && i < n) Rb[(long long)i * n + j] = i <= j ? sg[i] * a[s][r] : 0.0;
+            }
+        }
+    }
+    // Q, backwards: H_k applied to the columns right of k, then column k becomes e_k - tau_k v_k
+    for (int k = n - 1; k >= 0; --k) {
+        double* v = vbuf[k & 1];
+        const double tk = tau[k];
+        if (w == k % NW) {
+            const int sk = k / NW;
+#pragma unroll
+            for (int s = 0; s < SL; ++s)
+                if (s == sk) {
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const int i = lane + 64 * r;
+                        const double vi = i == k ? 1.0 : (i > k && i < m ? a[s][r] : 0.0);
+                        v[i] = vi;
+                        a[s][r] = i < k ? 0.0 : (i == k ? 1.0 - tk : -tk * vi);
+                    }
+                }
+        }
+        __syncthreads();
+        if (tk != 0.0) {
+            double vr[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) vr[r] = v[lane + 64 * r];
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const int j = s * NW + w;
+                if (j > k && j < n) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) d += vr[r] * a[s][r];
+                    d = vq_wsum(d) * tk;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) a[s][r] -= d * vr[r];
+                }
+            }
+        }
+    }
+    double* Qb = Q + (long long)b * qs;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int j = s * NW + w;
+        if (j >= n) continue;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            if (i < m) Qb[(long long)i * q_row + (long long)j * q_col] = sg[j] * a[s][r];
+        }
+    }
+}
+
 bool thinq_shape_ok(int m, int n) { return n >= 1 && m >= n && n <= kThinqMaxN; }
 bool thinq_fits(int m, int n) {
     return thinq_shape_ok(m, n) && (size_t)m * n * sizeof(double) + 4096 <= get_lds_cap();
 }
+bool thinq_needs_scratch(int m, int n) {
+    return !(m <= 256 && n <= 40) && !(m <= 512 && n <= 64) && !thinq_fits(m, n);
+}
 
-// LDS: 256 threads (two workgroups per CU at the largest matrices), one column per wave at
-// a time; global scratch: 1024 threads and four columns per wave, so that every trailing
-// column group of a step has a wave of its own and each load of v serves four columns
+// Up to 256 x 40 and 512 x 64: in registers (512 and 1024 threads); beyond, in LDS where
+// it fits (256 threads, one column per wave at a time), else in global scratch (1024
+// threads and four columns per wave, so that every trailing column group of a step has a
+// wave of its own and each load of v serves four columns)
 hipError_t launch_thinq(const double* X, long long xs, int m, int n, double* Q, long long qs, long long q_row,
                         long long q_col, double* R, long long rs, double* W, long long ws, int batch,
                         hipStream_t st) {
     if (batch <= 0) return hipSuccess;
     if (!thinq_shape_ok(m, n)) return hipErrorInvalidValue;
-    if (thinq_fits(m, n)) {
+    if (m <= 256 && n <= 40) {
+        hipLaunchKernelGGL((k_thinq_reg<8, 5, 4>), dim3(batch), dim3(512), 0, st, X, xs, m, n, Q, qs, q_row, q_col,
+                           R, rs);
+    } else if (m <= 512 && n <= 64) {
+        hipLaunchKernelGGL((k_thinq_reg<16, 4, 8>), dim3(batch), dim3(1024), 0, st, X, xs, m, n, Q, qs, q_row, q_col,
+                           R, rs);
+    } else if (thinq_fits(m, n)) {
         hipLaunchKernelGGL((k_thinq<256, true, 1>), dim3(batch), dim3(256), (size_t)m * n * sizeof(double), st, X, xs,
                            m, n, Q, qs, q_row, q_col, R, rs, nullptr, 0LL);
     } else {

@@ -81,10 +81,12 @@ hipError_t launch_applyq_blocked(const double* V, long long vs, int mz, int nref
 // variational compression (k_vc.hip)
 // thin QR of m x n matrices (m >= n, n <= 128, column-major, one per sample) into the
 // sign-fixed Q (element (i, k) at Q + b qs + i q_row + k q_col) and, when R != nullptr,
-// the n x n factor (row-major); X may equal Q.  Matrices that do not fit in LDS
-// (thinq_fits false) are worked on in W (m n doubles per sample, stride ws).
+// the n x n factor (row-major); X may equal Q.  Matrices up to 512 x 64 are held in
+// registers, larger ones in LDS where they fit (thinq_fits), the rest in W (m n doubles
+// per sample, stride ws; thinq_needs_scratch).
 bool thinq_shape_ok(int m, int n);
 bool thinq_fits(int m, int n);
+bool thinq_needs_scratch(int m, int n);   // W is read only for these shapes
 hipError_t launch_thinq(const double* X, long long xs, int m, int n, double* Q, long long qs, long long q_row,
                         long long q_col, double* R, long long rs, double* W, long long ws, int batch,
                         hipStream_t st);

@@ -284,7 +284,7 @@ public:
                     s_vZ2 = std::max({s_vZ2, a * b * hr * p, b * a * hl * p});
                     s_vM = std::max(s_vM, a * p * b);
                     s_vRf = std::max({s_vRf, a * a, b * b});
-                    if (!thinq_fits((int)(a * p), (int)b) || !thinq_fits((int)(p * b), (int)a))
+                    if (thinq_needs_scratch((int)(a * p), (int)b) || thinq_needs_scratch((int)(p * b), (int)a))
                         s_vW = std::max(s_vW, a * p * b);
                 }
             };
@@ -643,7 +643,7 @@ public:
         // thin QR of an m x n column-major matrix at X into Q (rows q_row, columns q_col apart)
         auto thinq = [&](const Op& X, int m, int n, const Op& Q, long long q_row, long long q_col,
                          bool with_r) -> hipError_t {
-            const bool in_lds = thinq_fits(m, n);
+            const bool in_lds = !thinq_needs_scratch(m, n);   // registers or LDS: no scratch
             const Op Wq = op(o_vW, s_vW);
             if (!bounds_ok("vc qr in", X, (long long)m * n - 1, 0) ||
                 !bounds_ok("vc qr out", Q, (long long)(m - 1) * q_row + (long long)(n - 1) * q_col, 0) ||

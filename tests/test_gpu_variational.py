@@ -247,3 +247,14 @@ def test_variational_in_a_captured_graph(truncation):
     for x, y in zip(_np(*outs[0]), svd):
         assert np.array_equal(x, y, equal_nan=True)
     assert not np.array_equal(svd[0], ref[0][0])
+
+
+def test_variational_register_factorisation_ragged(truncation):
+    """6x6, D = 7, Dc = 60: the middle sites factorise 343 x 60 and 420 x 49 matrices, too
+    large for LDS and not multiples of the wave width, so they take the register-resident
+    thin QR: amplitudes, local energies and log-derivatives against the oracle."""
+    lat = Lattice(6, 6, 7, 60)
+    A, S = make_random(lat, 2, 43)
+    _say("variational 6x6 D7 Dc60 (register factorisation)")
+    truncation(1)
+    _check(lat, A, S, 1)
