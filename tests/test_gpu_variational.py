@@ -84,7 +84,8 @@ def _check(lat, A, S, sweeps, with_e=True, with_g=True):
 
 @pytest.mark.parametrize("lat,seed,scaling", [
     (Lattice(4, 4, 2, 4), 21, "half"), (Lattice(6, 6, 2, 3), 22, "half"), (Lattice(5, 5, 3, 4), 23, "half"),
-    (Lattice(7, 4, 3, 5), 24, "frobenius"), (Lattice(4, 6, 2, 2), 25, "half")])
+    (Lattice(7, 4, 3, 5), 24, "frobenius"), (Lattice(4, 6, 2, 2), 25, "half"),
+    (Lattice(2, 6, 3, 2), 29, "half"), (Lattice(3, 5, 2, 3), 30, "half")])
 @pytest.mark.parametrize("sweeps", [1, 2])
 def test_variational_small_lattices(lat, seed, scaling, sweeps, truncation):
     A, S = make_random(lat, 5, seed, scaling)
