@@ -259,3 +259,24 @@ def test_variational_register_factorisation_ragged(truncation):
     _say("variational 6x6 D7 Dc60 (register factorisation)")
     truncation(1)
     _check(lat, A, S, 1)
+
+
+def test_variational_global_scratch_factorisation(truncation):
+    """6x5, D = 12, Dc = 70: the middle sites factorise 840 x 70 matrices (470 KB), beyond
+    the register and LDS forms, so the thin QR works in global scratch: amplitudes
+    against the oracle."""
+    lat = Lattice(6, 5, 12, 70)
+    A, S = make_random(lat, 2, 45)
+    _say("variational 6x5 D12 Dc70 (global-scratch factorisation)")
+    truncation(1)
+    _check(lat, A, S, 1, with_e=False, with_g=False)
+
+
+def test_variational_dc_three_d(truncation):
+    """The Dc = 3D case of the Dc proportional to D regime (5x5, D = 8, Dc = 24):
+    amplitudes, local energies and log-derivatives against the oracle."""
+    lat = Lattice(5, 5, 8, 24)
+    A, S = make_random(lat, 3, 44)
+    _say("variational 5x5 D8 Dc24")
+    truncation(1)
+    _check(lat, A, S, 1)
