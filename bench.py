@@ -87,7 +87,7 @@ def finish_cpu_baseline(h, name):
 # same counter reads for a 256 MiB device copy (FETCH_SIZE reads half of the copied bytes:
 # factor 2.0; WRITE_SIZE all: 1.0).  Valid only for the kernel sources they were measured
 # on (hash below) and the workload, arithmetic and batch named; otherwise null.
-TRAFFIC = {"sources": "6c7d262cbc03cc88",
+TRAFFIC = {"sources": "d2c823b1675075b6",
            "bytes_per_launch": {("8x8_D4_Dc16", "f64", 4096, "gemm"): 166.4e6}}
 
 

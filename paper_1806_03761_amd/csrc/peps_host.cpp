@@ -628,7 +628,8 @@ public:
     // b = bond at cut j+1 (incoming and outgoing boundaries alike), l / r = the row's
     // horizontal legs (Dh), u / d = its incoming / outgoing physical leg (p each).
     // Overlap environments: L_j[c][a][l] = <C| rows |E> left of cut j, R_j the same right
-    // of it.  Every contraction is a float64 GEMM; every QR is k_thinq.
+    // of it.  Every contraction is a float64 GEMM; every QR a thin QR with explicit Q
+    // (launch_thinq: in registers, LDS or, for the largest, global scratch).
     hipError_t vc_step(bool down, int row) {
         const Trunc& t = down ? tU[row] : tL[row];
         const long long s_in = down ? D2 : 1, s_out = down ? 1 : D2;
@@ -643,17 +644,17 @@ public:
         // thin QR of an m x n column-major matrix at X into Q (rows q_row, columns q_col apart)
         auto thinq = [&](const Op& X, int m, int n, const Op& Q, long long q_row, long long q_col,
                          bool with_r) -> hipError_t {
-            const bool in_lds = !thinq_needs_scratch(m, n);   // registers or LDS: no scratch
+            const bool on_chip = !thinq_needs_scratch(m, n);   // registers or LDS: no scratch
             const Op Wq = op(o_vW, s_vW);
             if (!bounds_ok("vc qr in", X, (long long)m * n - 1, 0) ||
                 !bounds_ok("vc qr out", Q, (long long)(m - 1) * q_row + (long long)(n - 1) * q_col, 0) ||
                 (with_r && !bounds_ok("vc qr R", Rf, (long long)n * n - 1, 0)) ||
-                (!in_lds && (s_vW < (long long)m * n || !bounds_ok("vc qr scratch", Wq, (long long)m * n - 1, 0))))
+                (!on_chip && (s_vW < (long long)m * n || !bounds_ok("vc qr scratch", Wq, (long long)m * n - 1, 0))))
                 return hipErrorInvalidValue;
             const double fl = (4.0 * m * n * n - 4.0 / 3.0 * n * n * n) * Bcur;
             KL(timed(PEPS_KC_QR, fl, [&] {
                 return launch_thinq(X.p, X.bs, m, n, Q.p, Q.bs, q_row, q_col, with_r ? Rf.p : nullptr, Rf.bs,
-                                    in_lds ? nullptr : Wq.p, in_lds ? 0 : Wq.bs, Bcur, st_);
+                                    on_chip ? nullptr : Wq.p, on_chip ? 0 : Wq.bs, Bcur, st_);
             }));
             return hipSuccess;
         };

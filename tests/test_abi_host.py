@@ -73,3 +73,42 @@ def test_plan_rejects_bad_lattice():
             peps.plan_check(lat, 1)
     with pytest.raises(peps.PepsError):
         peps.plan_check(Lattice(4, 4, 2, 2), 0)
+
+
+def _bench():
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py")
+    spec = importlib.util.spec_from_file_location("bench_mod", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_roofline_picks_the_binding_roof():
+    """The bench's roofline takes HBM below the ridge point (peak flops / peak bandwidth)
+    and the matrix cores above it, and reports achieved / peak of that roof."""
+    b = _bench()
+    ms, n = 1000.0, 100
+    # 5 flop/byte at float64 (ridge 9.825): HBM-bound, 3 TB/s achieved
+    t = {"ms_total": ms, "launches": n, "flops": 15e12, "bytes": 3e12, "tflops": 15.0, "gbps": 3000.0}
+    r = b._roofline(t, 78.6)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["frac"] - 3000.0 / 8000.0) < 1e-12 and abs(r["arithmetic_intensity"] - 5.0) < 1e-12
+    assert abs(r["mfma_view"]["frac"] - 15.0 / 78.6) < 1e-12
+    assert abs(r["algorithmic_bytes_per_launch"] - 3e10) < 1.0
+    # 20 flop/byte: matrix-core bound
+    t2 = dict(t, bytes=0.75e12, gbps=750.0)
+    r2 = b._roofline(t2, 78.6)
+    assert r2["bound"] == "mfma" and r2["unit"] == "TFLOP/s" and abs(r2["frac"] - 15.0 / 78.6) < 1e-12
+    # no byte count (the fused steps): matrix cores
+    r3 = b._roofline(dict(t, bytes=0.0, gbps=0.0), 157.3)
+    assert r3["bound"] == "mfma" and r3["hbm_view"] is None
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode != 0 and "one GPU" in out.stderr
