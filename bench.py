@@ -225,13 +225,23 @@ def main():
     import torch
 
     if args.copy_calibration:
+        # the reference kernel of the traffic counters, and the bandwidth a plain device
+        # copy reaches (read + write bytes over event time, 20 copies after 3 untimed)
         n = 256 * 2 ** 20 // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_per_launch": 8 * n}), flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        print(json.dumps({"copy_calibration_bytes_per_launch": 8 * n,
+                          "copy_read_plus_write_GBps": 2 * 8 * n / (ms * 1e-3) / 1e9}), flush=True)
         return
 
     from paper_1806_03761_amd import peps
