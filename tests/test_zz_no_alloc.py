@@ -57,6 +57,26 @@ def test_noalloc_matches_evaluate_4x4(prec):
         _compare(ref, got, gm)
 
 
+def test_noalloc_with_variational_compression():
+    """With the context's truncation set to variational compression the allocation-free
+    entry point keeps the compression's environments and temporaries in the fixed array
+    too: per-sample results equal peps_evaluate's bit for bit on two calls in a row."""
+    peps = _peps()
+    lat = Lattice(6, 6, 3, 5)
+    A, S = make_random(lat, 64, 46)
+    Ad = torch.from_numpy(A).cuda()
+    peps.set_truncation(1)
+    try:
+        for n in (64, 21):
+            Sd = torch.from_numpy(np.ascontiguousarray(S[:n])).cuda()
+            _say("noalloc variational 6x6 D3 Dc5, batch", n)
+            ref = _run(peps, Ad, Sd, lat, "f64", 1, False)
+            got = _run(peps, Ad, Sd, lat, "f64", 1, True)
+            _compare(ref, got, 1)
+    finally:
+        peps.set_truncation(0)
+
+
 def test_noalloc_chunks_8x8_and_ignores_workspace_limit():
     """8x8, D = 4, Dc = 16 needs about 3.2 MiB for one sample and 2.2 MiB for each more,
     so 40 samples exceed the 64 MiB array and run in two chunks; then 9 samples.  With
