@@ -552,14 +552,14 @@ def proposal_bonds(lat):
     return out
 
 
-def metropolis_step(A, lat, S, u, log_abs, sign):
+def metropolis_step(A, lat, S, u, log_abs, sign, sweeps=0):
     """One Metropolis step of every chain.  Chain b proposes the exchange of the two
     spins of bond k = min(floor(u[b,0] nb), nb - 1) of proposal_bonds (a symmetric
     proposal: the same bond undoes it; a pair of equal spins is no move), contracts
     W(S') like log_amplitude, and moves to S' when u[b,1] < W(S')^2 / W(S)^2 (the
     Metropolis rule for weights W^2) and S' has flag 0.
-    log_abs, sign: ln|W(S)| and sign of the current configurations.
-    Returns (S, log_abs, sign, accepted), new arrays."""
+    log_abs, sign: ln|W(S)| and sign of the current configurations; sweeps: the
+    truncation of next_boundary.  Returns (S, log_abs, sign, accepted), new arrays."""
     bonds = proposal_bonds(lat)
     nb = len(bonds)
     S = np.array(S, dtype=np.int8, copy=True)
@@ -572,7 +572,7 @@ def metropolis_step(A, lat, S, u, log_abs, sign):
             continue
         Sp = S[b].copy()
         Sp[m], Sp[n] = S[b, n], S[b, m]
-        lap, sgp, flp = log_amplitude_one(A, lat, Sp)
+        lap, sgp, flp = log_amplitude_one(A, lat, Sp, sweeps)
         if flp != FLAG_OK:
             continue
         if u[b, 1] < math.exp(min(2.0 * (lap - la[b]), 700.0)):
@@ -634,13 +634,13 @@ def vmc_step(A, lat, S, u, p, dt):
 # --------------------------------------------------------------------------
 # Spin-spin correlations (Sec. III-A: <S_m . S_m'> and the structure factor m_s^2(k))
 # --------------------------------------------------------------------------
-def pair_correlation_one(A, lat, S, m, n, la=None, sg=None):
+def pair_correlation_one(A, lat, S, m, n, la=None, sg=None, sweeps=0):
     """Local value of S_m . S_n at configuration S: sigma_m sigma_n / 4, plus 1/2 W(S')/W(S)
     when the two spins differ (S' = S with them exchanged), W(S') from a full contraction;
     3/4 when m == n.  Returns (value, flag): the flag of S, or FLAG_NONFINITE when the
     contraction of S' is not finite (a zero W(S') just gives a zero ratio)."""
     if la is None:
-        la, sg, fl = log_amplitude_one(A, lat, S)
+        la, sg, fl = log_amplitude_one(A, lat, S, sweeps)
         if fl != FLAG_OK:
             return math.nan, fl
     if m == n:
@@ -650,7 +650,7 @@ def pair_correlation_one(A, lat, S, m, n, la=None, sg=None):
     if S[m] != S[n]:
         Sp = np.array(S, dtype=np.int8, copy=True)
         Sp[m], Sp[n] = S[n], S[m]
-        lap, sgp, flp = log_amplitude_one(A, lat, Sp)
+        lap, sgp, flp = log_amplitude_one(A, lat, Sp, sweeps)
         if flp == FLAG_ZERO_AMPLITUDE:
             return v, FLAG_OK
         if flp != FLAG_OK:
@@ -659,7 +659,7 @@ def pair_correlation_one(A, lat, S, m, n, la=None, sg=None):
     return v, FLAG_OK
 
 
-def pair_correlations(A, lat, S, pairs, weights=None):
+def pair_correlations(A, lat, S, pairs, weights=None, sweeps=0):
     """Monte Carlo mean of S_m . S_n for every (m, n) in pairs over the samples whose
     configuration and exchanged configurations all contract (flag 0); weights as in
     energy_gradient.  Returns (means [P], per-sample values [B][P], flags [B])."""
@@ -667,12 +667,12 @@ def pair_correlations(A, lat, S, pairs, weights=None):
     vals = np.full((B, P), np.nan)
     fl = np.zeros(B, dtype=np.int8)
     for b in range(B):
-        la, sg, f = log_amplitude_one(A, lat, S[b])
+        la, sg, f = log_amplitude_one(A, lat, S[b], sweeps)
         if f != FLAG_OK:
             fl[b] = f
             continue
         for k, (m, n) in enumerate(pairs):
-            vals[b, k], f = pair_correlation_one(A, lat, S[b], m, n, la, sg)
+            vals[b, k], f = pair_correlation_one(A, lat, S[b], m, n, la, sg, sweeps)
             if f != FLAG_OK:
                 fl[b] = f
                 break

@@ -280,3 +280,64 @@ def test_variational_dc_three_d(truncation):
     _say("variational 5x5 D8 Dc24")
     truncation(1)
     _check(lat, A, S, 1)
+
+
+def test_variational_metropolis_matches_oracle(truncation):
+    """The sampler contracts W(S') with the context's truncation: four Metropolis steps of
+    24 chains on 6x6, D = 2, Dc = 3 with variational compression take the oracle's moves
+    (same uniforms), with ln|W| to 1e-10; a decision may differ only inside the rounding
+    band of its margin |2 (ln|W(S')| - ln|W(S)|) - ln u|, and such a chain is dropped."""
+    p = _peps()
+    lat = Lattice(6, 6, 2, 3)
+    A, S0 = make_random(lat, 24, 47, "half")
+    U = np.random.default_rng(48).random((4, S0.shape[0], 2))
+    truncation(1)
+    Ad, Sd = _dev(A, S0)
+    la_d, sg_d, _ = p.log_amplitude(Ad, Sd, lat, "f64")
+    la_o, sg_o, fl_o = O.log_amplitude(A, lat, S0, 1)
+    assert np.all(fl_o == 0)
+    So = S0.copy()
+    live = np.ones(S0.shape[0], dtype=bool)
+    bonds = O.proposal_bonds(lat)
+    nb = len(bonds)
+    moves = 0
+    for t in range(4):
+        acc_d = p.metropolis_step(Ad, Sd, lat, torch.from_numpy(U[t]).cuda(), la_d, sg_d, "f64")
+        S_g, la_g, sg_g, acc_g = _np(Sd, la_d, sg_d, acc_d)
+        So_new, la_new, sg_new, acc_o = O.metropolis_step(A, lat, So, U[t], la_o, sg_o, sweeps=1)
+        for b in range(S0.shape[0]):
+            if not live[b]:
+                continue
+            if bool(acc_o[b]) != bool(acc_g[b]):
+                m, n = bonds[min(int(U[t, b, 0] * nb), nb - 1)]
+                Sp = So[b].copy()
+                Sp[m], Sp[n] = So[b, n], So[b, m]
+                lap = O.log_amplitude_one(A, lat, Sp, 1)[0]
+                margin = abs(2.0 * (lap - la_o[b]) - np.log(U[t, b, 1]))
+                assert margin <= 4.0 * TOL_AMP * max(1.0, abs(lap)), (t, b, margin)
+                live[b] = False
+                continue
+            assert np.array_equal(So_new[b], S_g[b]) and sg_new[b] == sg_g[b], (t, b)
+            assert abs(la_new[b] - la_g[b]) <= TOL_AMP * max(1.0, abs(la_new[b])), (t, b)
+            moves += int(acc_g[b])
+        So, la_o, sg_o = So_new, la_new, sg_new
+    _say(f"  accepted moves compared: {moves}, chains kept {int(live.sum())}")
+    assert moves > 0 and live.sum() >= S0.shape[0] - 2
+
+
+def test_variational_pair_correlations_match_oracle(truncation):
+    """Spin-spin correlations contract every exchanged configuration with the context's
+    truncation: 6x6, D = 2, Dc = 3, variational compression, the centre site with every
+    site, per-sample values and means to 1e-10."""
+    p = _peps()
+    lat = Lattice(6, 6, 2, 3)
+    A, S = make_random(lat, 8, 49, "half")
+    pairs = [(14, m) for m in range(lat.N)]
+    truncation(1)
+    means, vals, fl = p.pair_correlations(*_dev(A, S), lat, pairs, "f64", per_sample=True)
+    means, vals, fl = _np(means, vals, fl)
+    m_o, v_o, fl_o = O.pair_correlations(A, lat, S, pairs, sweeps=1)
+    assert np.array_equal(fl, fl_o) and np.all(fl_o == 0)
+    err = np.abs(vals - v_o) / np.maximum(1.0, np.abs(v_o))
+    assert err.max() <= 1e-10, err.max()
+    assert np.max(np.abs(means - m_o) / np.maximum(1.0, np.abs(m_o))) <= 1e-10
