@@ -112,3 +112,18 @@ def test_bench_refuses_several_gpus():
     out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)
     assert out.returncode != 0 and "one GPU" in out.stderr
+
+
+def test_plan_bounds_variational_many_shapes():
+    """A seeded sample of 150 lattices (Lx 2-7, Ly 2-6, D 1-5, Dc 1-30): the launch
+    sequence with variational compression stays in bounds for amplitudes alone and for
+    the whole path."""
+    import random
+    peps = _peps()
+    cases = [(lx, ly, d, dc) for lx in range(2, 8) for ly in range(2, 7) for d in (1, 2, 3, 4, 5)
+             for dc in (1, 2, 3, 5, 8, 16, 30)]
+    random.Random(7).shuffle(cases)
+    for lx, ly, d, dc in cases[:150]:
+        lat = Lattice(lx, ly, d, dc)
+        for gm, we in ((0, False), (3, True)):
+            assert peps.plan_check(lat, 3, gm, we, 1) > 0, (lx, ly, d, dc, gm)
