@@ -405,9 +405,7 @@ def main():
         # the Dc ∝ D regime (D = 16, Dc = 32) on 16x16, variational compression, 64 samples
         if _fits(60.0):
             _log("leg 16x16_D16_Dc32_variational_1sweep")
-            from paper_1806_03761_amd.workloads import Lattice, make_random
-            lat5 = Lattice(16, 16, 16, 32)
-            A5, S5 = make_random(lat5, 64, 93)
+            lat5, A5, S5, _ = make_workload("16x16_D16_Dc32")
             A5d, S5d = torch.from_numpy(A5).to(dev), torch.from_numpy(S5).to(dev)
             g5 = torch.empty((lat5.N, 2, lat5.D ** 4), dtype=torch.float64, device=dev)
             peps.set_truncation(1)
@@ -427,7 +425,7 @@ def main():
                 "samples_per_s": S5.shape[0] / d5, "ms_per_step": d5 * 1e3, "batch": int(S5.shape[0]),
                 "flagged": int((r5[4] != 0).sum().item()),
                 "kernels": {k: {"ms_total": v["ms_total"], "tflops": v["tflops"]} for k, v in k5.items()},
-                "sample": "64 seeded configurations, Frobenius-normalised Gaussian tensors, f64, heuristic GEMM tiles"}
+                "sample": "the 16x16_D16_Dc32 workload (64 configurations, Frobenius-normalised Gaussian tensors), f64, heuristic GEMM tiles"}
             del A5d, S5d, g5, r5
         else:
             legs["16x16_D16_Dc32_variational_1sweep"] = {"skipped": "time budget of the run"}

@@ -53,6 +53,9 @@ WORKLOADS = {
     "8x8_D4_Dc16": Workload("8x8_D4_Dc16", Lattice(8, 8, 4, 16), 4096, 2, 102, "frobenius", "f32"),
     "16x16_D6_Dc36": Workload("16x16_D6_Dc36", Lattice(16, 16, 6, 36), 1024, 3, 103, "frobenius", "f32"),
     "24x24_D8_Dc64": Workload("24x24_D8_Dc64", Lattice(24, 24, 8, 64), 512, 4, 104, "frobenius", "bf16"),
+    # the Dc proportional to D regime of the paper's single-core-group runs (D = 16, Dc = 32),
+    # timed with variational boundary compression
+    "16x16_D16_Dc32": Workload("16x16_D16_Dc32", Lattice(16, 16, 16, 32), 64, 5, 105, "frobenius", "f64"),
     # the three lattices of the mixed batch (2048 samples split 1024 / 614 / 410)
     "mix_8x8_D4_Dc16": Workload("mix_8x8_D4_Dc16", Lattice(8, 8, 4, 16), 1024, 51, 151, "frobenius", "f32"),
     "mix_12x12_D6_Dc36": Workload("mix_12x12_D6_Dc36", Lattice(12, 12, 6, 36), 614, 52, 152, "frobenius", "f32"),
